@@ -1,0 +1,109 @@
+"""Sort oracle: TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, obviously correct CPU implementations of everything the GPU sort
+path computes.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU
+baseline leg of ``bench.py`` may import this package.  It shares no code with
+the HIP library ``paper_2507_16710_amd`` and never imports it.
+
+Contents
+  * ``sort`` / ``sortperm`` / ``segsort`` / ``sort_mt`` -- ctypes wrappers of
+    the C merge sort in ``sort_oracle.c`` (paper Sec. II-B: ``merge_sort``,
+    ``sortperm``; Julia Base order, Sec. II).
+  * ``rmi`` -- the learned-CDF model (sampling, fitting, loss, gradients,
+    bucket codes) in float64 / IEEE float32 numpy.
+  * ``brute`` -- independent brute-force checkers (insertion sort with a
+    separately written comparator, invariant checks) that pin the above.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sort_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# dtype codes of the oracle's C API (its own numbering)
+_DT = {np.dtype(np.int32): 1, np.dtype(np.int64): 2, np.dtype(np.uint32): 3,
+       np.dtype(np.uint64): 4, np.dtype(np.float32): 5, np.dtype(np.float64): 6}
+
+
+def build(force: bool = False) -> str:
+    """Compile ``sort_oracle.c`` with gcc into ``liboracle.so``."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        lib.oracle_sort.argtypes = [i32, vp, i64]
+        lib.oracle_sortperm.argtypes = [i32, vp, vp, i64]
+        lib.oracle_segsort.argtypes = [i32, vp, vp, i64]
+        lib.oracle_sort_mt.argtypes = [i32, vp, i64, i32]
+        for f in (lib.oracle_sort, lib.oracle_sortperm, lib.oracle_segsort, lib.oracle_sort_mt):
+            f.restype = i32
+        _lib = lib
+    return _lib
+
+
+def _code(a: np.ndarray) -> int:
+    try:
+        return _DT[a.dtype]
+    except KeyError:
+        raise TypeError(f"oracle: unsupported dtype {a.dtype}") from None
+
+
+def sort(keys: np.ndarray) -> np.ndarray:
+    """Stable ascending sort under the total order; returns a new array."""
+    out = np.ascontiguousarray(keys).copy()
+    if _load().oracle_sort(_code(out), out.ctypes.data, out.size) != 0:
+        raise RuntimeError("oracle_sort failed")
+    return out
+
+
+def sort_mt(keys: np.ndarray, threads: int) -> np.ndarray:
+    """Same result as :func:`sort`, on ``threads`` POSIX threads."""
+    out = np.ascontiguousarray(keys).copy()
+    if _load().oracle_sort_mt(_code(out), out.ctypes.data, out.size, int(threads)) != 0:
+        raise RuntimeError("oracle_sort_mt failed")
+    return out
+
+
+def sortperm(keys: np.ndarray) -> np.ndarray:
+    """0-based stable index permutation (uint32) that sorts ``keys``."""
+    k = np.ascontiguousarray(keys)
+    perm = np.empty(k.size, dtype=np.uint32)
+    if _load().oracle_sortperm(_code(k), k.ctypes.data, perm.ctypes.data, k.size) != 0:
+        raise RuntimeError("oracle_sortperm failed")
+    return perm
+
+
+def segsort(keys: np.ndarray, offsets: np.ndarray) -> np.ndarray:
+    """Each segment [offsets[s], offsets[s+1]) sorted independently."""
+    out = np.ascontiguousarray(keys).copy()
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    nseg = off.size - 1
+    if nseg < 0:
+        raise ValueError("offsets must hold nseg+1 entries")
+    if nseg > 0 and off[-1] > out.size:
+        raise ValueError("offsets exceed the key array")
+    if _load().oracle_segsort(_code(out), out.ctypes.data, off.ctypes.data, nseg) != 0:
+        raise RuntimeError("oracle_segsort failed")
+    return out
+
+
+from . import brute, rmi  # noqa: E402,F401

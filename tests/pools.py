@@ -1,0 +1,56 @@
+"""Adversarial small-input pools shared by the tests (inputs only)."""
+from __future__ import annotations
+
+import numpy as np
+
+DTYPES = ["i32", "i64", "u32", "u64", "f32", "f64"]
+NP = {"i32": np.int32, "i64": np.int64, "u32": np.uint32, "u64": np.uint64,
+      "f32": np.float32, "f64": np.float64}
+
+
+def special_bits(dt: str) -> np.ndarray:
+    """Bit patterns that stress the total order of each dtype."""
+    if dt == "f32":
+        b = [0x7FC00000, 0xFFC00000, 0x7F800001, 0xFFFFFFFF, 0x7FBFFFFF,  # NaNs
+             0x7F800000, 0xFF800000, 0x00000000, 0x80000000,              # +-Inf, +-0
+             0x00000001, 0x80000001, 0x7F7FFFFF, 0xFF7FFFFF,              # denormals, max
+             0x3F800000, 0xBF800000, 0x00800000, 0x80800000]
+        return np.array(b, dtype=np.uint32).view(np.float32)
+    if dt == "f64":
+        b = [0x7FF8000000000000, 0xFFF8000000000000, 0x7FF0000000000001,
+             0xFFFFFFFFFFFFFFFF, 0x7FF0000000000000, 0xFFF0000000000000,
+             0x0000000000000000, 0x8000000000000000, 0x0000000000000001,
+             0x8000000000000001, 0x7FEFFFFFFFFFFFFF, 0xFFEFFFFFFFFFFFFF,
+             0x3FF0000000000000, 0xBFF0000000000000]
+        return np.array(b, dtype=np.uint64).view(np.float64)
+    info = np.iinfo(NP[dt])
+    vals = [info.min, info.min + 1, -1 if info.min < 0 else 1, 0, 1, 2,
+            info.max - 1, info.max, 255, 256, 65535, 65536]
+    return np.array([v for v in vals if info.min <= v <= info.max], dtype=NP[dt])
+
+
+def random_keys(dt: str, n: int, rng: np.random.Generator, kind: str = "mixed") -> np.ndarray:
+    """n keys: 'uniform' random bits, 'ties' (few distinct values) or
+    'mixed' (random bits, specials and repeated values interleaved)."""
+    w = np.dtype(NP[dt]).itemsize
+    ubits = np.uint32 if w == 4 else np.uint64
+    rand = rng.integers(0, 1 << (8 * w), size=n, dtype=np.uint64).astype(ubits).view(NP[dt])
+    if kind == "uniform":
+        out = rand
+        if dt.startswith("f"):
+            out = np.where(np.isnan(out), NP[dt](1.5), out).astype(NP[dt])
+        return out
+    sp = special_bits(dt)
+    few = rand[: max(1, min(n, 5))]
+    pool = np.concatenate([sp, few])
+    if kind == "ties":
+        return pool[rng.integers(0, pool.size, size=n)]
+    pick = rng.integers(0, 3, size=n)
+    out = rand.copy()
+    out[pick == 1] = sp[rng.integers(0, sp.size, size=int((pick == 1).sum()))]
+    out[pick == 2] = few[rng.integers(0, few.size, size=int((pick == 2).sum()))]
+    return out
+
+
+def bits(a: np.ndarray) -> np.ndarray:
+    return a.view(np.uint32 if a.itemsize == 4 else np.uint64)

@@ -1,0 +1,159 @@
+"""Pins of the sort oracle against brute force, invariants and closed forms.
+
+The oracle is the plain definition of sort / sortperm / segmented sort
+(paper Sec. II-B, with Julia Base ordering).  These tests check it against
+things other than itself: a separately written insertion sort and
+comparator, exhaustive permutations, closed forms, and invariants that are
+shown to reject planted mistakes.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+from oracle.rmi import key_image
+from pools import DTYPES, NP, bits, random_keys, special_bits
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("kind", ["mixed", "ties", "uniform"])
+def test_sortperm_matches_insertion_sort(dt, kind):
+    rng = np.random.default_rng(hash((dt, kind)) & 0xFFFF)
+    for n in [0, 1, 2, 3, 7, 64, 257]:
+        k = random_keys(dt, n, rng, kind)
+        assert np.array_equal(oracle.sortperm(k), brute.insertion_sortperm(k)), (dt, kind, n)
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+def test_sort_matches_insertion_sort_bitwise(dt):
+    rng = np.random.default_rng(7)
+    for n in [0, 1, 5, 100, 300]:
+        k = random_keys(dt, n, rng, "mixed")
+        assert np.array_equal(bits(oracle.sort(k)), bits(brute.insertion_sort(k)))
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64", "i32", "u64"])
+def test_exhaustive_permutations_small(dt):
+    """Every ordering of a 6-element multiset of specials sorts to the same
+    bits (except NaN order, which must follow input order)."""
+    sp = special_bits(dt)
+    rng = np.random.default_rng(3)
+    base = sp[rng.choice(sp.size, size=6, replace=True)]
+    expect = None
+    for p in itertools.permutations(range(6)):
+        k = base[list(p)]
+        perm = oracle.sortperm(k)
+        assert np.array_equal(perm, brute.insertion_sortperm(k))
+        out = oracle.sort(k)
+        assert np.array_equal(bits(out), bits(k[perm]))
+        if dt.startswith("f"):
+            nn = out[~np.isnan(out)]
+            if expect is None:
+                expect = bits(nn).copy()
+            assert np.array_equal(bits(nn), expect)
+            # NaNs appear last, in input order
+            nan_in = bits(k[np.isnan(k)])
+            assert np.array_equal(bits(out[out.size - nan_in.size:]), nan_in)
+
+
+def test_float_order_closed_form():
+    """-Inf < -max < -1 < -min_normal < -denorm < -0 < +0 < denorm < ... < +Inf < NaN."""
+    order = np.array([0xFF800000, 0xFF7FFFFF, 0xBF800000, 0x80800000, 0x80000001,
+                      0x80000000, 0x00000000, 0x00000001, 0x00800000, 0x3F800000,
+                      0x7F7FFFFF, 0x7F800000], dtype=np.uint32)
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        shuf = rng.permutation(order)
+        assert np.array_equal(bits(oracle.sort(shuf.view(np.float32))), order)
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+def test_closed_forms(dt):
+    rng = np.random.default_rng(5)
+    n = 5000
+    # a permutation of distinct values sorts to the ascending sequence, and
+    # sortperm of a permutation is its inverse
+    if dt.startswith("f"):
+        base = np.arange(n, dtype=NP[dt]) - n / 2
+    else:
+        base = (np.arange(n) + (np.iinfo(NP[dt]).min // 2 if dt[0] == "i" else 0)).astype(NP[dt])
+    p = rng.permutation(n)
+    k = base[p]
+    assert np.array_equal(oracle.sort(k), base)
+    inv = np.empty(n, dtype=np.int64)
+    inv[p] = np.arange(n)
+    assert np.array_equal(oracle.sortperm(k).astype(np.int64), inv)
+    # constant array: unchanged, perm = iota
+    c = np.full(n, base[17], dtype=NP[dt])
+    assert np.array_equal(oracle.sortperm(c), np.arange(n, dtype=np.uint32))
+    # reverse-sorted distinct values
+    assert np.array_equal(oracle.sortperm(base[::-1].copy()).astype(np.int64), np.arange(n)[::-1])
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+def test_invariants_and_planted_mistakes(dt):
+    rng = np.random.default_rng(9)
+    k = random_keys(dt, 400, rng, "mixed")
+    out = oracle.sort(k)
+    perm = oracle.sortperm(k)
+    assert brute.is_nondecreasing(out)
+    assert brute.same_multiset(out, k)
+    assert brute.perm_is_stable_sort(k, perm)
+    assert np.array_equal(bits(k[perm]), bits(out))
+    # planted mistakes must be caught by the checkers
+    i = int(np.argmax(out != out[0]))            # an index with a larger key
+    swapped = out.copy()
+    swapped[[0, i]] = swapped[[i, 0]]
+    if brute.isless(out[0].item(), out[i].item()):
+        assert not brute.is_nondecreasing(swapped)
+    dropped = out.copy()
+    dropped[1] = dropped[2] if not np.array_equal(bits(dropped[1:2]), bits(dropped[2:3])) else dropped[1]
+    if not np.array_equal(bits(dropped), bits(out)):
+        assert not brute.same_multiset(dropped, k)
+    # an unstable tie: swap two equal keys in the permutation
+    _, first = np.unique(bits(k[perm]), return_index=True)
+    vals, counts = np.unique(bits(k), return_counts=True)
+    dup = vals[counts > 1]
+    if dup.size:
+        pos = np.nonzero(bits(k[perm]) == dup[0])[0]
+        bad = perm.copy()
+        bad[[pos[0], pos[1]]] = bad[[pos[1], pos[0]]]
+        assert not brute.perm_is_stable_sort(k, bad)
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+def test_key_image_orders_like_comparator(dt):
+    """A stable sort keyed on the oracle's order-preserving unsigned image
+    gives the comparator sort's permutation (special patterns + random bits)."""
+    rng = np.random.default_rng(13)
+    k = np.concatenate([special_bits(dt), random_keys(dt, 3000, rng, "mixed")])
+    by_image = np.argsort(key_image(k), kind="stable").astype(np.uint32)
+    assert np.array_equal(by_image, oracle.sortperm(k))
+
+
+@pytest.mark.parametrize("threads", [1, 2, 3, 8, 13])
+def test_sort_mt_equals_sort(threads):
+    rng = np.random.default_rng(threads)
+    for dt in ["f32", "i64", "u64", "f64"]:
+        k = random_keys(dt, 20011, rng, "mixed")
+        assert np.array_equal(bits(oracle.sort_mt(k, threads)), bits(oracle.sort(k)))
+
+
+def test_segsort():
+    rng = np.random.default_rng(21)
+    k = random_keys("f32", 3000, rng, "mixed")
+    cuts = np.sort(rng.integers(0, 3000, size=40))
+    off = np.concatenate([[0], cuts, [3000], [3000]]).astype(np.int64)   # incl. empties
+    out = oracle.segsort(k, off)
+    for s in range(off.size - 1):
+        a, b = off[s], off[s + 1]
+        assert np.array_equal(bits(out[a:b]), bits(brute.insertion_sort(k[a:b])))
+    # keys outside [off[0], off[-1]) are untouched
+    off2 = np.array([100, 200, 2500], dtype=np.int64)
+    out2 = oracle.segsort(k, off2)
+    assert np.array_equal(bits(out2[:100]), bits(k[:100]))
+    assert np.array_equal(bits(out2[2500:]), bits(k[2500:]))
+    # one segment == sort
+    assert np.array_equal(bits(oracle.segsort(k, np.array([0, 3000]))), bits(oracle.sort(k)))
