@@ -1,0 +1,208 @@
+/*
+ * ak.h -- C ABI of the MI355X (gfx950) sort library.
+ *
+ * What the calls compute follows the sorting primitives of the
+ * AcceleratedKernels.jl paper (arXiv 2507.16710), Sec. II-B "Algorithms
+ * Implemented":
+ *   - sort a collection ascending (in place here); the paper's sorter is a
+ *     merge sort, so results are those of a stable sort;
+ *   - sortperm: the index permutation that would sort a collection;
+ * with the Julia Base ordering the library adopts by dispatching onto the
+ * Base function names (Sec. II): integers by value; floats with
+ * -Inf < ... < -0.0 < +0.0 < ... < +Inf < NaN, all NaNs equal (so they keep
+ * their input order).  Temporaries are predictable from the input size and
+ * can be queried (Sec. II-B, last paragraph: "all temporary arrays ... are
+ * exposed").  Device code cannot throw (Sec. II), so every call returns a
+ * status code.
+ *
+ * Conventions for every call:
+ *   - Array pointers are DEVICE pointers (hipMalloc / torch CUDA tensors) on
+ *     the current HIP device; the caller owns them.  The library never keeps
+ *     them after the call.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls are asynchronous on that stream unless stated otherwise.
+ *   - Arguments are checked before anything is launched; on an error nothing
+ *     is written and the status says why (detail in ak_last_error()).
+ *   - n == 0 (or nseg == 0) returns AK_OK and launches nothing.
+ *   - The library keeps one scratch workspace per (device, stream), grown on
+ *     demand with hipMalloc (which synchronises the device) and freed by
+ *     ak_release_workspace().  Calls issued concurrently on DIFFERENT streams
+ *     use different workspaces; calls on one stream are serialised by it.
+ *   - Key counts are limited to n < 2^32 (indices and counters are 32-bit).
+ */
+#ifndef AK_H
+#define AK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *ak_stream_t;
+
+typedef enum {
+    AK_OK = 0,
+    AK_ERR_INVALID_ARG = 1,       /* bad pointer, size, offsets or config   */
+    AK_ERR_UNSUPPORTED_DTYPE = 2, /* dtype not handled by this entry point  */
+    AK_ERR_NO_MEMORY = 3,         /* workspace could not be allocated        */
+    AK_ERR_HIP = 4,               /* a HIP runtime call or launch failed     */
+    AK_ERR_INTERNAL = 5           /* an internal consistency check failed    */
+} ak_status;
+
+typedef enum {
+    AK_I32 = 1, AK_I64 = 2, AK_U32 = 3, AK_U64 = 4, AK_F32 = 5, AK_F64 = 6
+} ak_dtype;
+
+/* ------------------------------------------------------------------ sort
+ * Sec. II-B (merge_sort): sorts keys[0..n) ascending, in place.  Output keys
+ * keep their original bit patterns (NaN payloads and signs included); NaNs
+ * end up last, in input order.  Scratch: n keys + per-tile look-back words.
+ * Errors: AK_ERR_INVALID_ARG for n < 0, n >= 2^32 or keys == NULL with
+ * n > 0; AK_ERR_UNSUPPORTED_DTYPE for an unknown dtype. */
+ak_status ak_sort(void *keys, int64_t n, ak_dtype dtype, ak_stream_t stream);
+
+/* -------------------------------------------------------------- sortperm
+ * Sec. II-B (sortperm): writes perm[0..n) (0-based uint32 indices) such that
+ * keys[perm[0]] <= keys[perm[1]] <= ... under the order above, equal keys in
+ * increasing index order (so the permutation is unique).  keys is not
+ * modified.  keys and perm must not overlap.  Scratch: 2n keys + n indices.
+ * Errors: as ak_sort, plus perm == NULL or perm overlapping keys. */
+ak_status ak_sortperm(const void *keys, uint32_t *perm, int64_t n, ak_dtype dtype,
+                      ak_stream_t stream);
+ak_status ak_sortperm_i32(const int32_t *keys, uint32_t *perm, int64_t n, ak_stream_t stream);
+ak_status ak_sortperm_i64(const int64_t *keys, uint32_t *perm, int64_t n, ak_stream_t stream);
+ak_status ak_sortperm_u32(const uint32_t *keys, uint32_t *perm, int64_t n, ak_stream_t stream);
+ak_status ak_sortperm_u64(const uint64_t *keys, uint32_t *perm, int64_t n, ak_stream_t stream);
+ak_status ak_sortperm_f32(const float *keys, uint32_t *perm, int64_t n, ak_stream_t stream);
+ak_status ak_sortperm_f64(const double *keys, uint32_t *perm, int64_t n, ak_stream_t stream);
+
+/* ------------------------------------------------------- segmented sort
+ * Batched form of Sec. II-B's sort: for s in [0, nseg) the segment
+ * keys[offsets[s] .. offsets[s+1]) is sorted ascending in place, on its own.
+ * offsets is a DEVICE array of nseg+1 nondecreasing int64 values >= 0; the
+ * call reads offsets[0] and offsets[nseg] back to the host (one small
+ * synchronous copy) to size its scratch.  Keys outside
+ * [offsets[0], offsets[nseg]) are untouched.  Empty segments are allowed.
+ * Scratch: offsets[nseg] - offsets[0] keys + per-segment work lists.
+ * The launch sequence is captured once per (dtype, nseg, total) into a HIP
+ * graph and replayed; pointers travel through a device-side argument block.
+ * Errors: nseg < 0, NULL pointers, offsets[nseg] < offsets[0] or a total of
+ * 2^32 keys or more -> AK_ERR_INVALID_ARG.  Offsets that decrease inside
+ * the array are detected on the device and reported by
+ * ak_check_device_error(). */
+ak_status ak_segmented_sort(void *keys, const int64_t *offsets, int64_t nseg, ak_dtype dtype,
+                            ak_stream_t stream);
+ak_status ak_segmented_sort_i32(int32_t *keys, const int64_t *offsets, int64_t nseg, ak_stream_t s);
+ak_status ak_segmented_sort_i64(int64_t *keys, const int64_t *offsets, int64_t nseg, ak_stream_t s);
+ak_status ak_segmented_sort_u32(uint32_t *keys, const int64_t *offsets, int64_t nseg, ak_stream_t s);
+ak_status ak_segmented_sort_u64(uint64_t *keys, const int64_t *offsets, int64_t nseg, ak_stream_t s);
+ak_status ak_segmented_sort_f32(float *keys, const int64_t *offsets, int64_t nseg, ak_stream_t s);
+ak_status ak_segmented_sort_f64(double *keys, const int64_t *offsets, int64_t nseg, ak_stream_t s);
+
+/* Synchronises `stream`, then returns AK_ERR_INVALID_ARG if a kernel on it
+ * found invalid input (decreasing segment offsets) since the last check,
+ * and clears the flag; otherwise AK_OK. */
+ak_status ak_check_device_error(ak_stream_t stream);
+
+/* ------------------------------------------------- learned-CDF partition sort
+ * Same result as ak_sort (bit for bit), reached by partitioning the keys with
+ * a learned model of their distribution (a two-level recursive model index:
+ * a fixed log-feature root and `leaves` linear leaves trained on a sample the
+ * sort draws itself), then sorting every partition on chip; runs of equal
+ * model output longer than one workgroup can hold fall back to radix
+ * passes.  Config fields (0 selects the default):
+ *   leaves       number of linear leaves (default 4096; power of two <= 65536)
+ *   buckets_log2 log2 of the number of top-level buckets reported in the
+ *                statistics (default 12 = 4096, at most 14)
+ *   sample_frac  fraction of keys sampled (default 0.01; at least 4096 keys)
+ *   seed         SplitMix64 seed of the sample positions (default 0 is used
+ *                as is)
+ *   train_iters  Newton iterations of every leaf fit (default 3)
+ *   untrained    1: skip training and use equal-width key ranges (the method
+ *                without the model, for comparisons)
+ * `stats` may be NULL; if not, the call synchronises `stream` and fills it.
+ * Integer and float dtypes are supported. */
+typedef struct {
+    int32_t leaves;
+    int32_t buckets_log2;
+    float sample_frac;
+    int32_t train_iters;
+    uint64_t seed;
+    int32_t untrained;
+    int32_t reserved[3];
+} ak_learned_cfg;
+
+typedef struct {
+    int64_t n;
+    int64_t sample_size;
+    int32_t leaves;
+    int32_t code_bits;
+    int64_t max_bucket;        /* largest of the 2^buckets_log2 buckets        */
+    double imbalance;          /* max_bucket / (n / 2^buckets_log2)           */
+    int64_t fallback_keys;     /* keys in equal-code runs too long for LDS    */
+    int64_t constant_keys;     /* of those, keys in runs of one repeated key   */
+    int64_t fallback_runs;     /* number of such runs                          */
+    int64_t chunks;            /* on-chip chunk sorts performed                */
+} ak_learned_stats;
+
+ak_status ak_sort_learned(void *keys, int64_t n, ak_dtype dtype, const ak_learned_cfg *cfg,
+                          ak_learned_stats *stats, ak_stream_t stream);
+
+/* -------------------------------------------- learned-model building blocks
+ * Exposed so that every step can be checked on its own.  Model buffers are
+ * DEVICE float arrays of ak_rmi_model_floats(leaves) floats laid out as
+ * [rc, ra, rb, leaves, 0, 0, 0, 0] followed by one 8-float record per leaf
+ * [a, b, x0, lo, hi, 0, 0, 0].  For a key with order-preserving unsigned
+ * image t: x = float(t) (round to nearest even), r = float(bits of x);
+ * leaf = clamp(floor(ra*(r - rc) + rb), 0, leaves-1);
+ * F = clamp(a*(x - x0) + b, lo, hi); code = min(floor(F * 2^code_bits),
+ * 2^code_bits - 1).  Every float operation is single precision, rounded to
+ * nearest even, multiply then add (never fused). */
+size_t ak_rmi_model_floats(int32_t leaves);
+
+/* out[j] = keys[floor(splitmix64(seed, j) * n / 2^64)] for j < m, where
+ * splitmix64(seed, j) is output j of SplitMix64 started at state `seed`. */
+ak_status ak_learned_sample(const void *keys, int64_t n, ak_dtype dtype, uint64_t seed,
+                            int64_t m, void *out, ak_stream_t stream);
+
+/* Fits a model to an ascending sample of m keys: the root spans the
+ * sample's feature range in `leaves` equal widths; every leaf is fitted to
+ * the empirical CDF j/m of its samples by `iters` Newton steps that use the
+ * forward (residual, loss) and backward (gradient, curvature) kernels, with
+ * the slope kept >= 0 and the output clamped to [st/m, en/m]. */
+ak_status ak_rmi_fit(const void *sorted_sample, int64_t m, ak_dtype dtype, int32_t leaves,
+                     int32_t iters, float *model, ak_stream_t stream);
+
+/* Forward + backward of every leaf for a given model (no update).  Each
+ * leaf is evaluated in its scaled coordinate dx' = (x_j - x0_i) * s_i, with
+ * s_i the power of two 2^-e, 2^e <= max |x - x0_i| over the leaf's samples
+ * (1 for an empty or flat leaf), and slope a'_i = a_i / s_i, residual
+ * r_j = a'_i*dx' + b_i - j/m.  out is a DEVICE array of 8*leaves floats:
+ * out[8*i .. 8*i+7] = sum r^2, dL/da', dL/db, 2*sum dx'^2, 2*sum dx',
+ * 2*count, s_i, 0 (float32 sums). */
+ak_status ak_rmi_leaf_grad(const void *sorted_sample, int64_t m, ak_dtype dtype,
+                           const float *model, float *out, ak_stream_t stream);
+
+/* codes[i] = model code of keys[i] (see above), 1 <= code_bits <= 24. */
+ak_status ak_rmi_codes(const void *keys, int64_t n, ak_dtype dtype, const float *model,
+                       int32_t code_bits, uint32_t *codes, ak_stream_t stream);
+
+/* --------------------------------------------------------------- scratch */
+typedef enum { AK_OP_SORT = 0, AK_OP_SORTPERM = 1, AK_OP_SEGMENTED = 2, AK_OP_LEARNED = 3 } ak_op;
+
+/* Bytes of device scratch the library holds for one call of `op` on n keys. */
+size_t ak_temp_bytes(ak_op op, int64_t n, ak_dtype dtype);
+
+/* Synchronises the device and frees every workspace and cached graph. */
+ak_status ak_release_workspace(void);
+
+const char *ak_status_string(ak_status s);
+/* Detail of the last error on the calling thread ("" if none). */
+const char *ak_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AK_H */

@@ -295,6 +295,41 @@ def leaf_loss_grad(model: Model, sorted_keys: np.ndarray):
     return loss, grad, hess
 
 
+def leaf_scales(model: Model, sorted_keys: np.ndarray) -> np.ndarray:
+    """Per-leaf power-of-two scale s = 2**-e, 2**e <= max|x - x0| < 2**(e+1)
+    over the leaf's first and last sample (1 for an empty or flat leaf); the
+    kernels fit the slope in the scaled coordinate dx*s so that sums of
+    dx**2 stay inside the float32 range."""
+    x, _ = features(sorted_keys)
+    st, en, _ = leaf_ranges(model, sorted_keys)
+    out = np.ones(model.L, np.float32)
+    for i in range(model.L):
+        s, e = int(st[i]), int(en[i])
+        if e == s:
+            continue
+        dm = max(abs(np.float32(x[s] - model.x0[i])), abs(np.float32(x[e - 1] - model.x0[i])))
+        if dm > 0:
+            _, ex = np.frexp(np.float64(dm))
+            out[i] = np.float32(np.ldexp(1.0, -(int(ex) - 1)))
+    return out
+
+
+def leaf_grad_scaled(model: Model, sorted_keys: np.ndarray) -> np.ndarray:
+    """(L, 7): loss, dL/da', dL/db, 2*sum dx'^2, 2*sum dx', 2*count, s, with
+    a' = a/s and dx' = dx*s -- the quantities the backward kernel reports."""
+    loss, grad, hess = leaf_loss_grad(model, sorted_keys)
+    s = leaf_scales(model, sorted_keys).astype(np.float64)
+    out = np.zeros((model.L, 7))
+    out[:, 0] = loss
+    out[:, 1] = grad[:, 0] / s
+    out[:, 2] = grad[:, 1]
+    out[:, 3] = hess[:, 0] * s * s
+    out[:, 4] = hess[:, 1] * s
+    out[:, 5] = hess[:, 2]
+    out[:, 6] = s
+    return out
+
+
 def bucket_stats(code: np.ndarray, cb: int, buckets: int = 4096):
     """Histogram of the top log2(buckets) bits of every code, and
     max bucket / ideal bucket."""

@@ -1,0 +1,250 @@
+"""MI355X (gfx950) sort library: thin Python binding of ``libak.so``.
+
+Every function marshals torch tensors into the C ABI declared in
+``include/ak.h`` (device pointers and the current HIP stream); all work runs
+in the library's HIP kernels.  There is no fallback: if ``libak.so`` is
+missing or a tensor is not on a GPU, the call raises.
+
+The operations are the paper's sorting primitives (AcceleratedKernels.jl,
+Sec. II-B): ``sort_`` (in place, stable, Julia Base order: NaN last, -0.0
+before +0.0), ``sortperm`` (stable 0-based uint32 permutation), the batched
+``segmented_sort_`` and the learned-CDF partition sort ``sort_learned_``.
+Unsigned keys are passed in signed storage of the same width with an
+explicit ``dtype`` ("u32" / "u64").
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libak.so")
+
+DTYPE_CODE = {"i32": 1, "i64": 2, "u32": 3, "u64": 4, "f32": 5, "f64": 6}
+_TORCH_DEFAULT = {torch.int32: "i32", torch.int64: "i64", torch.float32: "f32",
+                  torch.float64: "f64"}
+for _name, _dt in (("uint32", "u32"), ("uint64", "u64")):
+    if hasattr(torch, _name):
+        _TORCH_DEFAULT[getattr(torch, _name)] = _dt
+_WIDTH = {"i32": 4, "u32": 4, "f32": 4, "i64": 8, "u64": 8, "f64": 8}
+OPS = {"sort": 0, "sortperm": 1, "segmented": 2, "learned": 3}
+
+
+class AKError(RuntimeError):
+    """A library call returned a non-zero ak_status."""
+
+    def __init__(self, status: int, what: str, detail: str):
+        super().__init__(f"{what}: status {status} ({detail})")
+        self.status = status
+
+
+class LearnedCfg(ctypes.Structure):
+    _fields_ = [("leaves", ctypes.c_int32), ("buckets_log2", ctypes.c_int32),
+                ("sample_frac", ctypes.c_float), ("train_iters", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("untrained", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
+
+
+class LearnedStats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("sample_size", ctypes.c_int64),
+                ("leaves", ctypes.c_int32), ("code_bits", ctypes.c_int32),
+                ("max_bucket", ctypes.c_int64), ("imbalance", ctypes.c_double),
+                ("fallback_keys", ctypes.c_int64), ("constant_keys", ctypes.c_int64),
+                ("fallback_runs", ctypes.c_int64), ("chunks", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Loads libak.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2507_16710_amd.build` "
+                          "or __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64
+    sig = {
+        "ak_sort": [vp, i64, i32, vp],
+        "ak_sortperm": [vp, vp, i64, i32, vp],
+        "ak_segmented_sort": [vp, vp, i64, i32, vp],
+        "ak_check_device_error": [vp],
+        "ak_sort_learned": [vp, i64, i32, vp, vp, vp],
+        "ak_learned_sample": [vp, i64, i32, u64, i64, vp, vp],
+        "ak_rmi_fit": [vp, i64, i32, i32, i32, vp, vp],
+        "ak_rmi_leaf_grad": [vp, i64, i32, vp, vp, vp],
+        "ak_rmi_codes": [vp, i64, i32, vp, i32, vp, vp],
+        "ak_release_workspace": [],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = i32
+    for suf in ("i32", "i64", "u32", "u64", "f32", "f64"):
+        getattr(lib, f"ak_sortperm_{suf}").argtypes = [vp, vp, i64, vp]
+        getattr(lib, f"ak_sortperm_{suf}").restype = i32
+        getattr(lib, f"ak_segmented_sort_{suf}").argtypes = [vp, vp, i64, vp]
+        getattr(lib, f"ak_segmented_sort_{suf}").restype = i32
+    lib.ak_temp_bytes.argtypes = [i32, i64, i32]
+    lib.ak_temp_bytes.restype = ctypes.c_size_t
+    lib.ak_rmi_model_floats.argtypes = [i32]
+    lib.ak_rmi_model_floats.restype = ctypes.c_size_t
+    lib.ak_last_error.restype = ctypes.c_char_p
+    lib.ak_status_string.argtypes = [i32]
+    lib.ak_status_string.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int, what: str) -> None:
+    if status != 0:
+        lib = load_library()
+        detail = lib.ak_last_error().decode() or lib.ak_status_string(status).decode()
+        raise AKError(status, what, detail)
+
+
+def _dtype(t: torch.Tensor, dtype: str | None) -> str:
+    dt = dtype or _TORCH_DEFAULT.get(t.dtype)
+    if dt not in DTYPE_CODE:
+        raise TypeError(f"unsupported key dtype {t.dtype} (pass dtype=...)")
+    if t.element_size() != _WIDTH[dt]:
+        raise TypeError(f"dtype {dt} needs {_WIDTH[dt]}-byte elements, got {t.dtype}")
+    return dt
+
+
+def _gpu(t: torch.Tensor, name: str) -> None:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _stream(t: torch.Tensor) -> int:
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def sort_(keys: torch.Tensor, dtype: str | None = None) -> torch.Tensor:
+    """Sorts ``keys`` in place (ak_sort); returns it."""
+    _gpu(keys, "keys")
+    dt = _dtype(keys, dtype)
+    with torch.cuda.device(keys.device):
+        _check(load_library().ak_sort(keys.data_ptr(), keys.numel(), DTYPE_CODE[dt], _stream(keys)), "ak_sort")
+    return keys
+
+
+def sortperm(keys: torch.Tensor, dtype: str | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Stable 0-based permutation (uint32 bits in an int32 tensor)."""
+    _gpu(keys, "keys")
+    dt = _dtype(keys, dtype)
+    if out is None:
+        out = torch.empty(keys.numel(), dtype=torch.int32, device=keys.device)
+    _gpu(out, "out")
+    with torch.cuda.device(keys.device):
+        _check(load_library().ak_sortperm(keys.data_ptr(), out.data_ptr(), keys.numel(), DTYPE_CODE[dt],
+                                          _stream(keys)), "ak_sortperm")
+    return out
+
+
+def segmented_sort_(keys: torch.Tensor, offsets: torch.Tensor, dtype: str | None = None) -> torch.Tensor:
+    """Sorts every segment [offsets[s], offsets[s+1]) of ``keys`` in place."""
+    _gpu(keys, "keys")
+    _gpu(offsets, "offsets")
+    if offsets.dtype != torch.int64:
+        raise TypeError("offsets must be int64")
+    dt = _dtype(keys, dtype)
+    with torch.cuda.device(keys.device):
+        _check(load_library().ak_segmented_sort(keys.data_ptr(), offsets.data_ptr(), offsets.numel() - 1,
+                                                DTYPE_CODE[dt], _stream(keys)), "ak_segmented_sort")
+    return keys
+
+
+def check_device_error(device=None) -> None:
+    dev = torch.device("cuda" if device is None else device)
+    with torch.cuda.device(dev):
+        _check(load_library().ak_check_device_error(torch.cuda.current_stream(dev).cuda_stream),
+               "ak_check_device_error")
+
+
+def make_cfg(leaves=0, buckets_log2=0, sample_frac=0.0, train_iters=0, seed=0, untrained=False) -> LearnedCfg:
+    c = LearnedCfg()
+    c.leaves, c.buckets_log2, c.sample_frac = leaves, buckets_log2, sample_frac
+    c.train_iters, c.seed, c.untrained = train_iters, seed, int(bool(untrained))
+    return c
+
+
+def sort_learned_(keys: torch.Tensor, dtype: str | None = None, cfg: LearnedCfg | None = None,
+                  stats: bool = False):
+    """Learned-CDF partition sort in place.  With stats=True returns
+    (keys, stats dict) and synchronises the stream."""
+    _gpu(keys, "keys")
+    dt = _dtype(keys, dtype)
+    st = LearnedStats() if stats else None
+    with torch.cuda.device(keys.device):
+        _check(load_library().ak_sort_learned(
+            keys.data_ptr(), keys.numel(), DTYPE_CODE[dt],
+            ctypes.byref(cfg) if cfg is not None else None,
+            ctypes.byref(st) if st is not None else None, _stream(keys)), "ak_sort_learned")
+    return (keys, st.as_dict()) if stats else keys
+
+
+def learned_sample(keys: torch.Tensor, m: int, seed: int = 0, dtype: str | None = None) -> torch.Tensor:
+    _gpu(keys, "keys")
+    dt = _dtype(keys, dtype)
+    out = torch.empty(m, dtype=keys.dtype, device=keys.device)
+    with torch.cuda.device(keys.device):
+        _check(load_library().ak_learned_sample(keys.data_ptr(), keys.numel(), DTYPE_CODE[dt], seed, m,
+                                                out.data_ptr(), _stream(keys)), "ak_learned_sample")
+    return out
+
+
+def model_floats(leaves: int) -> int:
+    return int(load_library().ak_rmi_model_floats(leaves))
+
+
+def rmi_fit(sorted_sample: torch.Tensor, leaves: int = 4096, iters: int = 3, dtype: str | None = None) -> torch.Tensor:
+    _gpu(sorted_sample, "sorted_sample")
+    dt = _dtype(sorted_sample, dtype)
+    model = torch.zeros(model_floats(leaves), dtype=torch.float32, device=sorted_sample.device)
+    with torch.cuda.device(sorted_sample.device):
+        _check(load_library().ak_rmi_fit(sorted_sample.data_ptr(), sorted_sample.numel(), DTYPE_CODE[dt],
+                                         leaves, iters, model.data_ptr(), _stream(sorted_sample)), "ak_rmi_fit")
+    return model
+
+
+def rmi_leaf_grad(sorted_sample: torch.Tensor, model: torch.Tensor, dtype: str | None = None) -> torch.Tensor:
+    _gpu(sorted_sample, "sorted_sample")
+    _gpu(model, "model")
+    dt = _dtype(sorted_sample, dtype)
+    leaves = int(round(float(model[3].item())))
+    out = torch.zeros(leaves, 8, dtype=torch.float32, device=model.device)
+    with torch.cuda.device(model.device):
+        _check(load_library().ak_rmi_leaf_grad(sorted_sample.data_ptr(), sorted_sample.numel(), DTYPE_CODE[dt],
+                                               model.data_ptr(), out.data_ptr(), _stream(model)),
+               "ak_rmi_leaf_grad")
+    return out
+
+
+def rmi_codes(keys: torch.Tensor, model: torch.Tensor, code_bits: int, dtype: str | None = None) -> torch.Tensor:
+    _gpu(keys, "keys")
+    _gpu(model, "model")
+    dt = _dtype(keys, dtype)
+    out = torch.empty(keys.numel(), dtype=torch.int32, device=keys.device)
+    with torch.cuda.device(keys.device):
+        _check(load_library().ak_rmi_codes(keys.data_ptr(), keys.numel(), DTYPE_CODE[dt], model.data_ptr(),
+                                           code_bits, out.data_ptr(), _stream(keys)), "ak_rmi_codes")
+    return out
+
+
+def temp_bytes(op: str, n: int, dtype: str) -> int:
+    return int(load_library().ak_temp_bytes(OPS[op], n, DTYPE_CODE[dtype]))
+
+
+def release_workspace() -> None:
+    _check(load_library().ak_release_workspace(), "ak_release_workspace")

@@ -1,0 +1,395 @@
+// The C ABI (include/ak.h): argument checks, per-(device, stream) workspace
+// cache, error reporting, and dispatch into the drivers.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+
+#include "ak_internal.h"
+
+namespace ak {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+ak_status hip_fail(hipError_t e, const char *what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return AK_ERR_HIP;
+}
+
+int num_cus() {
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cached[dev]) {
+        int c = 0;
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0) c = 256;
+        cached[dev] = c;
+    }
+    return cached[dev];
+}
+
+// ------------------------------------------------------------- workspace
+static std::mutex g_ws_mu;
+static std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
+
+constexpr int RUN_SLOTS = 4;
+
+__global__ void k_zero_u64(uint64_t *p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+static ak_status zero_fill(hipStream_t s, void *p, size_t bytes) {
+    const size_t n = bytes / 8;
+    if (!n) return AK_OK;
+    const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero_u64, dim3(grid), dim3(256), 0, s, (uint64_t *)p, n);
+    AK_LAUNCH_CHECK("k_zero_u64");
+    return AK_OK;
+}
+
+Workspace *get_workspace(hipStream_t stream) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        set_error("hipGetDevice failed");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto key = std::make_pair(dev, stream);
+    auto it = g_ws.find(key);
+    if (it != g_ws.end()) return it->second;
+    Workspace *ws = new Workspace();
+    ws->device = dev;
+    ws->stream = stream;
+    if (hipMalloc((void **)&ws->state, sizeof(RunState) * RUN_SLOTS) != hipSuccess) {
+        set_error("hipMalloc(run state) failed");
+        delete ws;
+        return nullptr;
+    }
+    if (zero_fill(stream, ws->state, sizeof(RunState) * RUN_SLOTS) != AK_OK ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+        (void)hipFree(ws->state);
+        delete ws;
+        return nullptr;
+    }
+    g_ws[key] = ws;
+    return ws;
+}
+
+// Grows *p to at least `need` bytes (rounded up by 1/8 to limit regrowth).
+// The old buffer may still be read by queued work, so the stream is drained
+// before it is freed.
+ak_status ws_reserve(Workspace *ws, void **p, size_t *have, size_t need) {
+    if (need <= *have) return AK_OK;
+    size_t sz = need + need / 8 + 4096;
+    if (*p) {
+        AK_HIP(hipStreamSynchronize(ws->stream));
+        AK_HIP(hipFree(*p));
+        *p = nullptr;
+        *have = 0;
+    }
+    if (hipMalloc(p, sz) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        set_error("workspace allocation of " + std::to_string(sz) + " bytes failed");
+        return AK_ERR_NO_MEMORY;
+    }
+    *have = sz;
+    return AK_OK;
+}
+
+ak_status ws_reserve_lookback(Workspace *ws, size_t need) {
+    if (need <= ws->lookback_bytes) return AK_OK;
+    void *p = ws->lookback;
+    size_t have = ws->lookback_bytes;
+    ak_status r = ws_reserve(ws, &p, &have, need);
+    if (r != AK_OK) return r;
+    ws->lookback = (uint64_t *)p;
+    ws->lookback_bytes = have;
+    ws->epoch = 0;
+    return zero_fill(ws->stream, ws->lookback, ws->lookback_bytes);
+}
+
+// Each run takes 16 consecutive epochs (one per pass).  Epochs are 30-bit;
+// before they would wrap, the look-back words are cleared and numbering
+// restarts, so a word left by an earlier run never matches.
+ak_status ws_next_epoch(Workspace *ws, uint32_t *epoch) {
+    if (ws->epoch + 32 >= (1u << 30)) {
+        ak_status r = zero_fill(ws->stream, ws->lookback, ws->lookback_bytes);
+        if (r != AK_OK) return r;
+        ws->epoch = 0;
+    }
+    ws->epoch += 16;
+    *epoch = ws->epoch;
+    return AK_OK;
+}
+
+uint32_t segmented_take_error(Workspace *ws);
+void segmented_release(Workspace *ws);
+
+static void free_ws(Workspace *ws) {
+    segmented_release(ws);
+    void *bufs[] = {ws->keys0, ws->keys1, ws->vals0, ws->lookback, ws->state, ws->misc, ws->misc2};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    for (void *b : ws->aux)
+        if (b) (void)hipFree(b);
+    delete ws;
+}
+
+}  // namespace ak
+
+using namespace ak;
+
+// ------------------------------------------------------------- checks
+static bool overlaps(const void *a, size_t an, const void *b, size_t bn) {
+    const char *x = (const char *)a, *y = (const char *)b;
+    return x < y + bn && y < x + an;
+}
+
+static ak_status check_keys(const void *keys, int64_t n, int dtype) {
+    if (!dtype_ok(dtype)) {
+        set_error("unknown dtype " + std::to_string(dtype));
+        return AK_ERR_UNSUPPORTED_DTYPE;
+    }
+    if (n < 0) {
+        set_error("n < 0");
+        return AK_ERR_INVALID_ARG;
+    }
+    if (n >= (int64_t(1) << 32)) {
+        set_error("n >= 2^32 keys is not supported");
+        return AK_ERR_INVALID_ARG;
+    }
+    if (n > 0 && !keys) {
+        set_error("keys is NULL");
+        return AK_ERR_INVALID_ARG;
+    }
+    return AK_OK;
+}
+
+static Workspace *ws_or_error(ak_stream_t stream, ak_status *st) {
+    Workspace *ws = get_workspace((hipStream_t)stream);
+    *st = ws ? AK_OK : AK_ERR_HIP;
+    return ws;
+}
+
+extern "C" {
+
+const char *ak_status_string(ak_status s) {
+    switch (s) {
+    case AK_OK: return "ok";
+    case AK_ERR_INVALID_ARG: return "invalid argument";
+    case AK_ERR_UNSUPPORTED_DTYPE: return "unsupported dtype";
+    case AK_ERR_NO_MEMORY: return "out of device memory";
+    case AK_ERR_HIP: return "HIP runtime error";
+    case AK_ERR_INTERNAL: return "internal error";
+    }
+    return "unknown status";
+}
+
+const char *ak_last_error(void) { return g_last_error.c_str(); }
+
+ak_status ak_sort(void *keys, int64_t n, ak_dtype dtype, ak_stream_t stream) {
+    g_last_error.clear();
+    ak_status r = check_keys(keys, n, dtype);
+    if (r != AK_OK || n == 0) return r;
+    Workspace *ws = ws_or_error(stream, &r);
+    if (!ws) return r;
+    return radix_sort(ws, dtype, keys, nullptr, n, 0);
+}
+
+ak_status ak_sortperm(const void *keys, uint32_t *perm, int64_t n, ak_dtype dtype, ak_stream_t stream) {
+    g_last_error.clear();
+    ak_status r = check_keys(keys, n, dtype);
+    if (r != AK_OK) return r;
+    if (n > 0 && !perm) {
+        set_error("perm is NULL");
+        return AK_ERR_INVALID_ARG;
+    }
+    if (n == 0) return AK_OK;
+    if (overlaps(keys, (size_t)n * dtype_bytes(dtype), perm, (size_t)n * 4)) {
+        set_error("perm overlaps keys");
+        return AK_ERR_INVALID_ARG;
+    }
+    Workspace *ws = ws_or_error(stream, &r);
+    if (!ws) return r;
+    return radix_sort(ws, dtype, const_cast<void *>(keys), perm, n, 0);
+}
+
+#define AK_PERM_T(SUF, T, DT)                                                              \
+    ak_status ak_sortperm_##SUF(const T *keys, uint32_t *perm, int64_t n, ak_stream_t s) { \
+        return ak_sortperm(keys, perm, n, DT, s);                                          \
+    }
+AK_PERM_T(i32, int32_t, AK_I32)
+AK_PERM_T(i64, int64_t, AK_I64)
+AK_PERM_T(u32, uint32_t, AK_U32)
+AK_PERM_T(u64, uint64_t, AK_U64)
+AK_PERM_T(f32, float, AK_F32)
+AK_PERM_T(f64, double, AK_F64)
+
+ak_status ak_segmented_sort(void *keys, const int64_t *offsets, int64_t nseg, ak_dtype dtype, ak_stream_t stream) {
+    g_last_error.clear();
+    if (!dtype_ok(dtype)) {
+        set_error("unknown dtype");
+        return AK_ERR_UNSUPPORTED_DTYPE;
+    }
+    if (nseg < 0) {
+        set_error("nseg < 0");
+        return AK_ERR_INVALID_ARG;
+    }
+    if (nseg == 0) return AK_OK;
+    if (!offsets || !keys) {
+        set_error("keys or offsets is NULL");
+        return AK_ERR_INVALID_ARG;
+    }
+    ak_status r;
+    Workspace *ws = ws_or_error(stream, &r);
+    if (!ws) return r;
+    return segmented_sort(ws, dtype, keys, offsets, nseg);
+}
+
+#define AK_SEG_T(SUF, T, DT)                                                                  \
+    ak_status ak_segmented_sort_##SUF(T *keys, const int64_t *off, int64_t nseg, ak_stream_t s) { \
+        return ak_segmented_sort(keys, off, nseg, DT, s);                                     \
+    }
+AK_SEG_T(i32, int32_t, AK_I32)
+AK_SEG_T(i64, int64_t, AK_I64)
+AK_SEG_T(u32, uint32_t, AK_U32)
+AK_SEG_T(u64, uint64_t, AK_U64)
+AK_SEG_T(f32, float, AK_F32)
+AK_SEG_T(f64, double, AK_F64)
+
+ak_status ak_check_device_error(ak_stream_t stream) {
+    g_last_error.clear();
+    ak_status r;
+    Workspace *ws = ws_or_error(stream, &r);
+    if (!ws) return r;
+    AK_HIP(hipStreamSynchronize(ws->stream));
+    uint32_t flag = 0;
+    for (int slot = 0; slot < RUN_SLOTS; ++slot) {
+        uint32_t f = 0;
+        AK_HIP(hipMemcpy(&f, &ws->state[slot].error, sizeof(f), hipMemcpyDeviceToHost));
+        flag |= f;
+    }
+    flag |= segmented_take_error(ws);
+    if (flag) {
+        const uint32_t zero = 0;
+        for (int slot = 0; slot < RUN_SLOTS; ++slot)
+            AK_HIP(hipMemcpy(&ws->state[slot].error, &zero, sizeof(zero), hipMemcpyHostToDevice));
+        set_error("a kernel found invalid input (decreasing segment offsets)");
+        return AK_ERR_INVALID_ARG;
+    }
+    return AK_OK;
+}
+
+static ak_learned_cfg resolve_cfg(const ak_learned_cfg *cfg) {
+    ak_learned_cfg c{};
+    if (cfg) c = *cfg;
+    if (c.leaves <= 0) c.leaves = 4096;
+    if (c.buckets_log2 <= 0) c.buckets_log2 = 12;
+    if (!(c.sample_frac > 0.f)) c.sample_frac = 0.01f;
+    if (c.train_iters <= 0) c.train_iters = 3;
+    return c;
+}
+
+ak_status ak_sort_learned(void *keys, int64_t n, ak_dtype dtype, const ak_learned_cfg *cfg,
+                          ak_learned_stats *stats, ak_stream_t stream) {
+    g_last_error.clear();
+    ak_status r = check_keys(keys, n, dtype);
+    if (r != AK_OK) return r;
+    ak_learned_cfg c = resolve_cfg(cfg);
+    if (c.leaves > 65536 || (c.leaves & (c.leaves - 1)) || c.buckets_log2 > 14 || c.sample_frac > 1.f) {
+        set_error("bad learned config (leaves: power of two <= 65536; buckets_log2 <= 14; sample_frac <= 1)");
+        return AK_ERR_INVALID_ARG;
+    }
+    if (n == 0) {
+        if (stats) *stats = ak_learned_stats{};
+        return AK_OK;
+    }
+    Workspace *ws = ws_or_error(stream, &r);
+    if (!ws) return r;
+    return learned_sort(ws, dtype, keys, n, &c, stats);
+}
+
+size_t ak_rmi_model_floats(int32_t leaves) { return leaves > 0 ? 8 + 8 * (size_t)leaves : 0; }
+
+ak_status ak_learned_sample(const void *keys, int64_t n, ak_dtype dtype, uint64_t seed, int64_t m, void *out,
+                            ak_stream_t stream) {
+    g_last_error.clear();
+    ak_status r = check_keys(keys, n, dtype);
+    if (r != AK_OK) return r;
+    if (m < 0 || (m > 0 && (!out || n == 0)) || m >= (int64_t(1) << 32)) {
+        set_error("bad sample size or output");
+        return AK_ERR_INVALID_ARG;
+    }
+    if (m == 0) return AK_OK;
+    return learned_sample((hipStream_t)stream, dtype, keys, n, seed, m, out);
+}
+
+ak_status ak_rmi_fit(const void *sorted_sample, int64_t m, ak_dtype dtype, int32_t leaves, int32_t iters,
+                     float *model, ak_stream_t stream) {
+    g_last_error.clear();
+    ak_status r = check_keys(sorted_sample, m, dtype);
+    if (r != AK_OK) return r;
+    if (m == 0 || !model || leaves <= 0 || leaves > 65536 || (leaves & (leaves - 1)) || iters < 0) {
+        set_error("bad model arguments (m > 0, leaves a power of two <= 65536, iters >= 0)");
+        return AK_ERR_INVALID_ARG;
+    }
+    Workspace *ws = ws_or_error(stream, &r);
+    if (!ws) return r;
+    return rmi_fit(ws, dtype, sorted_sample, m, leaves, iters, model);
+}
+
+ak_status ak_rmi_leaf_grad(const void *sorted_sample, int64_t m, ak_dtype dtype, const float *model, float *out,
+                           ak_stream_t stream) {
+    g_last_error.clear();
+    ak_status r = check_keys(sorted_sample, m, dtype);
+    if (r != AK_OK) return r;
+    if (m == 0 || !model || !out) {
+        set_error("bad arguments");
+        return AK_ERR_INVALID_ARG;
+    }
+    Workspace *ws = ws_or_error(stream, &r);
+    if (!ws) return r;
+    return rmi_leaf_grad(ws, dtype, sorted_sample, m, model, out);
+}
+
+ak_status ak_rmi_codes(const void *keys, int64_t n, ak_dtype dtype, const float *model, int32_t code_bits,
+                       uint32_t *codes, ak_stream_t stream) {
+    g_last_error.clear();
+    ak_status r = check_keys(keys, n, dtype);
+    if (r != AK_OK) return r;
+    if (code_bits < 1 || code_bits > 24 || (n > 0 && (!model || !codes))) {
+        set_error("bad arguments (1 <= code_bits <= 24)");
+        return AK_ERR_INVALID_ARG;
+    }
+    if (n == 0) return AK_OK;
+    return rmi_codes((hipStream_t)stream, dtype, keys, n, model, code_bits, codes);
+}
+
+size_t ak_temp_bytes(ak_op op, int64_t n, ak_dtype dtype) {
+    if (!dtype_ok(dtype) || n <= 0) return 0;
+    switch (op) {
+    case AK_OP_SORT: return radix_temp_bytes(dtype, n, false);
+    case AK_OP_SORTPERM: return radix_temp_bytes(dtype, n, true);
+    case AK_OP_SEGMENTED: return segmented_temp_bytes(dtype, n, 0);
+    case AK_OP_LEARNED: {
+        ak_learned_cfg c = resolve_cfg(nullptr);
+        return learned_temp_bytes(dtype, n, &c);
+    }
+    }
+    return 0;
+}
+
+ak_status ak_release_workspace(void) {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    AK_HIP(hipDeviceSynchronize());
+    for (auto &kv : g_ws) free_ws(kv.second);
+    g_ws.clear();
+    return AK_OK;
+}
+
+}  // extern "C"

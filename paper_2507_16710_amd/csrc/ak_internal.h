@@ -1,0 +1,185 @@
+// Internal definitions shared by the library's HIP sources (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/ak.h"
+
+namespace ak {
+
+// ----------------------------------------------------------------- keys
+// Order-preserving unsigned image of a key's bits: unsigned order of the
+// image equals the library's total order (Julia Base ordering: integers by
+// value; floats -Inf < ... < -0.0 < +0.0 < ... < +Inf < NaN with all NaNs
+// tied).  It is recomputed on every load and never stored: kernels move the
+// original bits, so outputs are bit-identical to the inputs.
+template <int DT> struct KT;
+template <> struct KT<AK_U32> {
+    using U = uint32_t;
+    static __host__ __device__ __forceinline__ U image(U b) { return b; }
+};
+template <> struct KT<AK_I32> {
+    using U = uint32_t;
+    static __host__ __device__ __forceinline__ U image(U b) { return b ^ 0x80000000u; }
+};
+template <> struct KT<AK_F32> {
+    using U = uint32_t;
+    static __host__ __device__ __forceinline__ U image(U b) {
+        if ((b & 0x7FFFFFFFu) > 0x7F800000u) return 0xFFFFFFFFu;  // any NaN
+        return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+    }
+};
+template <> struct KT<AK_U64> {
+    using U = uint64_t;
+    static __host__ __device__ __forceinline__ U image(U b) { return b; }
+};
+template <> struct KT<AK_I64> {
+    using U = uint64_t;
+    static __host__ __device__ __forceinline__ U image(U b) { return b ^ 0x8000000000000000ull; }
+};
+template <> struct KT<AK_F64> {
+    using U = uint64_t;
+    static __host__ __device__ __forceinline__ U image(U b) {
+        if ((b & 0x7FFFFFFFFFFFFFFFull) > 0x7FF0000000000000ull) return ~0ull;
+        return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+    }
+};
+
+constexpr int key_bits(int dt) { return (dt == AK_I64 || dt == AK_U64 || dt == AK_F64) ? 64 : 32; }
+inline int dtype_bytes(int dt) { return key_bits(dt) / 8; }
+inline bool dtype_ok(int dt) { return dt >= AK_I32 && dt <= AK_F64; }
+
+// ------------------------------------------------------------- wave64
+__device__ __forceinline__ uint32_t lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+// number of set bits of m in lanes below the calling lane
+__device__ __forceinline__ uint32_t count_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+__device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+
+// inclusive prefix sum across the 64 lanes of a wave
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t o = __shfl_up(v, d, 64);
+        if (lane >= (uint32_t)d) v += o;
+    }
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// ----------------------------------------------------- look-back words
+// One 64-bit word per (tile, digit): count in bits 0..31, status in bits
+// 32..33 (1 = this tile's own count, 2 = inclusive prefix through this
+// tile), and the pass epoch in bits 34..63 so stale words from earlier
+// passes never need clearing.
+constexpr uint64_t LB_AGG = 1, LB_INC = 2;
+__device__ __forceinline__ uint64_t lb_pack(uint32_t epoch, uint64_t flag, uint32_t cnt) {
+    return (uint64_t)cnt | (flag << 32) | ((uint64_t)epoch << 34);
+}
+__device__ __forceinline__ void lb_store(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t lb_load(const uint64_t *p) {
+    return __hip_atomic_load(const_cast<uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ----------------------------------------------------- radix run state
+constexpr int RADIX_BITS = 8;
+constexpr int RADIX = 1 << RADIX_BITS;
+constexpr int MAX_PLACES = 8;
+
+struct PassDesc {
+    int32_t active;  // 0: every key has the same digit here; the pass is skipped
+    int32_t j;       // index of this pass among the active ones
+    int32_t q;       // number of active passes
+    int32_t shift;   // bit offset of the digit
+};
+
+// Device-resident state of one radix run.
+struct RunState {
+    uint32_t hist[MAX_PLACES][RADIX];  // digit counts per place
+    uint32_t base[MAX_PLACES][RADIX];  // exclusive digit offsets per place
+    uint32_t tile_ctr[MAX_PLACES];     // dynamic tile ids per pass
+    PassDesc desc[MAX_PLACES];
+    int32_t q;                         // number of active passes
+    uint32_t error;                    // device-detected input error flag
+};
+
+// ------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+ak_status hip_fail(hipError_t e, const char *what);
+#define AK_HIP(call)                                  \
+    do {                                              \
+        hipError_t e_ = (call);                       \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+#define AK_LAUNCH_CHECK(what)                                 \
+    do {                                                      \
+        hipError_t e_ = hipGetLastError();                    \
+        if (e_ != hipSuccess) return hip_fail(e_, what);      \
+    } while (0)
+
+// ------------------------------------------------------------ workspace
+// Per (device, stream) scratch.  Regions are grown independently; the
+// look-back region is zero-filled when (re)allocated and then relies on
+// epochs, so it is never cleared between calls.
+struct Workspace {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    void *keys0 = nullptr; size_t keys0_bytes = 0;
+    void *keys1 = nullptr; size_t keys1_bytes = 0;
+    void *vals0 = nullptr; size_t vals0_bytes = 0;
+    uint64_t *lookback = nullptr; size_t lookback_bytes = 0;
+    RunState *state = nullptr;      // several run states (sample sort, main run)
+    void *misc = nullptr; size_t misc_bytes = 0;   // learned / segmented scratch
+    void *misc2 = nullptr; size_t misc2_bytes = 0;
+    void *aux[6] = {nullptr}; size_t aux_bytes[6] = {0};     // learned-sort scratch
+    uint32_t epoch = 0;             // last epoch base handed out
+};
+
+Workspace *get_workspace(hipStream_t stream);
+ak_status ws_reserve(Workspace *ws, void **p, size_t *have, size_t need);
+ak_status ws_reserve_lookback(Workspace *ws, size_t need);
+// epoch base for a run of up to 16 passes (clears the look-back region on wrap)
+ak_status ws_next_epoch(Workspace *ws, uint32_t *epoch);
+
+int num_cus();
+
+// --------------------------------------------------------- radix driver
+// Sorts keys (sort mode, in place) or writes perm (sortperm mode) on
+// `stream`, using run state slot `slot` of the workspace.
+ak_status radix_sort(Workspace *ws, int dtype, void *keys, uint32_t *perm, int64_t n, int slot);
+size_t radix_temp_bytes(int dtype, int64_t n, bool perm);
+
+// Single-workgroup on-chip sort capacity (keys) for a dtype.
+int64_t small_sort_capacity(int dtype);
+
+// -------------------------------------------------------- segmented sort
+ak_status segmented_sort(Workspace *ws, int dtype, void *keys, const int64_t *offsets, int64_t nseg);
+size_t segmented_temp_bytes(int dtype, int64_t n, int64_t nseg);
+
+// ------------------------------------------------------------- learned
+ak_status learned_sort(Workspace *ws, int dtype, void *keys, int64_t n, const ak_learned_cfg *cfg,
+                       ak_learned_stats *stats);
+size_t learned_temp_bytes(int dtype, int64_t n, const ak_learned_cfg *cfg);
+ak_status learned_sample(hipStream_t s, int dtype, const void *keys, int64_t n, uint64_t seed, int64_t m,
+                         void *out);
+ak_status rmi_fit(Workspace *ws, int dtype, const void *sorted, int64_t m, int leaves, int iters,
+                  float *model);
+ak_status rmi_leaf_grad(Workspace *ws, int dtype, const void *sorted, int64_t m, const float *model,
+                        float *out);
+ak_status rmi_codes(hipStream_t s, int dtype, const void *keys, int64_t n, const float *model, int cb,
+                    uint32_t *codes);
+
+}  // namespace ak

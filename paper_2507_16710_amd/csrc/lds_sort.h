@@ -1,0 +1,83 @@
+// On-chip sort of one tile by a group of waves (used for small inputs, for
+// short segments and for the learned sort's chunks).
+#pragma once
+
+#include "radix_common.h"
+#include "radix_kernels.h"
+
+namespace ak {
+
+// ------------------------------------------------ single-workgroup sort
+// Sorts up to W*64*IPT keys on chip with a group of W waves (tid = thread
+// index within the group): load once, skip the bits that do not vary
+// (OR/AND reduction of the images), one stable ranking per 8-bit digit
+// between the lowest and highest varying bit, store once.  `in` may equal
+// `out`: every key is read before any is written.  With VAL the output is
+// the permutation (vout[i] = input index of the i-th smallest key).
+template <int DT, bool VAL, int W, int IPT>
+__device__ __forceinline__ void lds_sort_tile(const typename KT<DT>::U *in, typename KT<DT>::U *out,
+                                              uint32_t *vout, uint32_t len,
+                                              SmallSmem<typename KT<DT>::U, VAL, W, IPT> &sm, int tid) {
+    using U = typename KT<DT>::U;
+    constexpr int B = W * 64;
+    const int lane = tid & 63, w = tid >> 6;
+    U k[IPT];
+    uint32_t v[IPT], dg[IPT], rk[IPT];
+    uint64_t vor = 0, vand = ~0ull;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const uint32_t e = striped_elem<IPT>(w, j, lane);
+        k[j] = U(0);
+        if (e < len) {
+            k[j] = in[e];
+            const uint64_t t = (uint64_t)KT<DT>::image(k[j]);
+            vor |= t;
+            vand &= t;
+        }
+        if (VAL) v[j] = e;
+    }
+    uint64_t ror, rand_;
+    block_or_and<W>(vor, vand, sm.red, ror, rand_, tid);
+    const uint64_t diff = ror ^ rand_;
+    if (diff != 0) {
+        const int lo = __builtin_ctzll(diff), hi = 63 - __builtin_clzll(diff);
+        for (int shift = lo; shift <= hi; shift += RADIX_BITS) {
+#pragma unroll
+            for (int j = 0; j < IPT; ++j) {
+                const uint32_t e = striped_elem<IPT>(w, j, lane);
+                dg[j] = e < len ? (uint32_t)(KT<DT>::image(k[j]) >> shift) & (RADIX - 1) : 0u;
+            }
+            rank_match<RADIX_BITS, W, IPT>(dg, len, rk, sm.cnt, sm.tot, tid);
+            block_exscan<B, RADIX>(sm.tot, sm.start, sm.wsum, tid);
+            rank_finish<RADIX_BITS, W, IPT>(dg, rk, sm.cnt, sm.start, tid);
+#pragma unroll
+            for (int j = 0; j < IPT; ++j) {
+                const uint32_t e = striped_elem<IPT>(w, j, lane);
+                if (e < len) {
+                    sm.keys[rk[j]] = k[j];
+                    if (VAL) sm.vals[rk[j]] = v[j];
+                }
+            }
+            grp_sync<W>();
+#pragma unroll
+            for (int j = 0; j < IPT; ++j) {
+                const uint32_t e = striped_elem<IPT>(w, j, lane);
+                if (e < len) {
+                    k[j] = sm.keys[e];
+                    if (VAL) v[j] = sm.vals[e];
+                }
+            }
+            grp_sync<W>();
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const uint32_t e = striped_elem<IPT>(w, j, lane);
+        if (e < len) {
+            if (!VAL) out[e] = k[j];
+            else vout[e] = v[j];
+        }
+    }
+}
+
+}  // namespace ak

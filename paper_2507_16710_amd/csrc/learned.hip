@@ -1,0 +1,708 @@
+// Learned-CDF partition sort: same output as the radix sort, reached by
+// ordering the keys by a learned estimate of their CDF first.
+//
+//   1. sample m keys at SplitMix64-hashed positions, sort the sample;
+//   2. fit a two-level RMI to the sorted sample: a fixed root spreading the
+//      sample's log-like feature range over L leaves, and per leaf a linear
+//      CDF trained by Newton steps built from a forward kernel (residuals,
+//      loss) and a backward kernel (gradient, curvature);
+//   3. stable LSD passes over the model's cb-bit code of every key (the
+//      one-sweep kernel with code digits): keys ordered by code;
+//   4. cut the code-ordered array at code changes into chunks that fit one
+//      workgroup and sort each chunk on chip (keys of different codes never
+//      need to cross a cut, because the code grows with the key);
+//   5. runs of a single code longer than a chunk fall back to radix passes
+//      (after a check that skips runs of one repeated key).
+// The paper's sorter is a merge sort (Sec. II-B); the learned partition is
+// this library's own design for the same result.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "lds_sort.h"
+#include "long_sort.h"
+#include "radix_kernels.h"
+#include "rmi_device.h"
+
+namespace ak {
+
+constexpr uint64_t SM64_GAMMA = 0x9E3779B97F4A7C15ull;
+
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t j) {
+    uint64_t z = seed + (j + 1) * SM64_GAMMA;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+template <typename U>
+__global__ __launch_bounds__(256) void k_sample(const U *keys, uint64_t n, uint64_t seed, uint32_t m, U *out) {
+    const uint32_t j = blockIdx.x * 256u + threadIdx.x;
+    if (j >= m) return;
+    const uint64_t pos = __umul64hi(splitmix64_at(seed, j), n);
+    out[j] = keys[pos];
+}
+
+// ------------------------------------------------------------- fitting
+// Scratch layout of a fit (floats / ints in one buffer):
+struct FitScratch {
+    uint32_t *st;    // L+1 leaf sample starts
+    float *resid;    // m residuals
+    float *stats;    // L x 8 per-leaf sums
+};
+
+template <int DT>
+__global__ void k_rmi_root(const typename KT<DT>::U *sorted, uint32_t m, int L, float *model) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const float x0 = to_f32(KT<DT>::image(sorted[0]));
+    const float x1 = to_f32(KT<DT>::image(sorted[m - 1]));
+    const float r0 = (float)__float_as_uint(x0), r1 = (float)__float_as_uint(x1);
+    const float width = __fsub_rn(r1, r0);
+    RmiHead h;
+    h.rc = r0;
+    h.ra = width > 0.f ? __fdiv_rn((float)L, width) : 0.f;
+    h.rb = 0.f;
+    h.L = (float)L;
+    for (int i = 0; i < 4; ++i) h.pad[i] = 0.f;
+    *reinterpret_cast<RmiHead *>(model) = h;
+}
+
+// Model of the method without training: every key in leaf 0, F linear from
+// the smallest to the largest sampled key (equal-width key ranges).
+template <int DT>
+__global__ void k_rmi_untrained(const typename KT<DT>::U *sorted, uint32_t m, int L, float *model) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const float x0 = to_f32(KT<DT>::image(sorted[0]));
+    const float x1 = to_f32(KT<DT>::image(sorted[m - 1]));
+    if (i == 0) {
+        RmiHead h{};
+        h.L = (float)L;
+        *reinterpret_cast<RmiHead *>(model) = h;
+    }
+    if (i < L) {
+        RmiLeaf lf{};
+        lf.x0 = x0;
+        const float width = __fsub_rn(x1, x0);
+        lf.a = (i == 0 && width > 0.f) ? __fdiv_rn(1.0f, width) : 0.f;
+        lf.b = 0.f;
+        lf.lo = 0.f;
+        lf.hi = 1.f;
+        reinterpret_cast<RmiLeaf *>(model + 8)[i] = lf;
+    }
+}
+
+// st[i] = first sample routed to leaf >= i (routing is monotone, so every
+// leaf owns a contiguous range of the sorted sample).
+template <int DT>
+__global__ void k_rmi_bounds(const typename KT<DT>::U *sorted, uint32_t m, const float *model, uint32_t *st) {
+    const int L = (int)reinterpret_cast<const RmiHead *>(model)->L;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > L) return;
+    const RmiHead h = *reinterpret_cast<const RmiHead *>(model);
+    uint32_t lo = 0, hi = m;
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        float x;
+        if (rmi_leaf(h, KT<DT>::image(sorted[mid]), x) < i) lo = mid + 1;
+        else hi = mid;
+    }
+    st[i] = lo;
+}
+
+// Leaf setup: output range [st/m, en/m], centre x0 = middle sample, slope
+// scale s = 2^-e with 2^e <= max |x - x0| over the leaf (a power of two, so
+// scaled and unscaled products round identically), a = b = 0.
+template <int DT>
+__global__ void k_rmi_leaf_init(const typename KT<DT>::U *sorted, uint32_t m, const uint32_t *st, float *model) {
+    const int L = (int)reinterpret_cast<const RmiHead *>(model)->L;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L) return;
+    RmiLeaf *lf = reinterpret_cast<RmiLeaf *>(model + 8) + i;
+    const uint32_t s = st[i], e = st[i + 1];
+    RmiLeaf v{};
+    v.lo = __fdiv_rn((float)s, (float)m);
+    v.hi = __fdiv_rn((float)e, (float)m);
+    v.pad0 = 1.f;
+    if (e == s) {
+        v.b = v.lo;
+    } else {
+        v.x0 = to_f32(KT<DT>::image(sorted[s + (e - s - 1) / 2]));
+        const float d0 = fabsf(__fsub_rn(to_f32(KT<DT>::image(sorted[s])), v.x0));
+        const float d1 = fabsf(__fsub_rn(to_f32(KT<DT>::image(sorted[e - 1])), v.x0));
+        const float dm = fmaxf(d0, d1);
+        v.pad0 = dm > 0.f ? ldexpf(1.0f, -ilogbf(dm)) : 1.f;
+    }
+    *lf = v;
+}
+
+// Scale of every leaf for given parameters (as in k_rmi_leaf_init).
+template <int DT>
+__global__ void k_leaf_scale(const typename KT<DT>::U *sorted, const uint32_t *st, float *model) {
+    const int L = (int)reinterpret_cast<const RmiHead *>(model)->L;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L) return;
+    RmiLeaf *lf = reinterpret_cast<RmiLeaf *>(model + 8) + i;
+    const uint32_t s = st[i], e = st[i + 1];
+    float sc = 1.f;
+    if (e > s) {
+        const float d0 = fabsf(__fsub_rn(to_f32(KT<DT>::image(sorted[s])), lf->x0));
+        const float d1 = fabsf(__fsub_rn(to_f32(KT<DT>::image(sorted[e - 1])), lf->x0));
+        const float dm = fmaxf(d0, d1);
+        sc = dm > 0.f ? ldexpf(1.0f, -ilogbf(dm)) : 1.f;
+    }
+    lf->pad0 = sc;
+}
+
+template <int B>
+__device__ __forceinline__ float block_sum_f(float v, float *s_red) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) s_red[w] = v;
+    __syncthreads();
+    float t = 0.f;
+#pragma unroll
+    for (int i = 0; i < B / 64; ++i) t += s_red[i];
+    __syncthreads();
+    return t;
+}
+
+// Forward: residual of every sample of leaf blockIdx.x, r = a*dx + b - j/m
+// (in the leaf's scaled coordinates a' = a/s, dx' = dx*s), and the loss.
+template <int DT>
+__global__ __launch_bounds__(256) void k_rmi_fwd(const typename KT<DT>::U *sorted, uint32_t m, const uint32_t *st,
+                                                 const float *model, float *resid, float *stats) {
+    __shared__ float s_red[4];
+    const int i = blockIdx.x;
+    const RmiLeaf lf = reinterpret_cast<const RmiLeaf *>(model + 8)[i];
+    const uint32_t s = st[i], e = st[i + 1];
+    const float sc = lf.pad0;
+    const float a_s = __fdiv_rn(lf.a, sc);  // exact: sc is a power of two
+    const float fm = (float)m;
+    float loss = 0.f;
+    for (uint32_t j = s + threadIdx.x; j < e; j += 256) {
+        const float dx = __fmul_rn(__fsub_rn(to_f32(KT<DT>::image(sorted[j])), lf.x0), sc);
+        const float y = __fdiv_rn((float)j, fm);
+        const float r = __fsub_rn(__fadd_rn(__fmul_rn(a_s, dx), lf.b), y);
+        resid[j] = r;
+        loss = __fadd_rn(loss, __fmul_rn(r, r));
+    }
+    loss = block_sum_f<256>(loss, s_red);
+    if (threadIdx.x == 0) stats[8 * i + 0] = loss;
+}
+
+// Backward: gradient of the loss w.r.t. (a', b) and the curvature terms
+// (Gauss-Newton = exact Hessian for this least-squares loss).
+template <int DT>
+__global__ __launch_bounds__(256) void k_rmi_bwd(const typename KT<DT>::U *sorted, uint32_t m, const uint32_t *st,
+                                                 const float *model, const float *resid, float *stats) {
+    __shared__ float s_red[4];
+    const int i = blockIdx.x;
+    const RmiLeaf lf = reinterpret_cast<const RmiLeaf *>(model + 8)[i];
+    const uint32_t s = st[i], e = st[i + 1];
+    const float sc = lf.pad0;
+    float ga = 0.f, gb = 0.f, hxx = 0.f, hx = 0.f;
+    for (uint32_t j = s + threadIdx.x; j < e; j += 256) {
+        const float dx = __fmul_rn(__fsub_rn(to_f32(KT<DT>::image(sorted[j])), lf.x0), sc);
+        const float r = resid[j];
+        ga = __fadd_rn(ga, __fmul_rn(r, dx));
+        gb = __fadd_rn(gb, r);
+        hxx = __fadd_rn(hxx, __fmul_rn(dx, dx));
+        hx = __fadd_rn(hx, dx);
+    }
+    ga = block_sum_f<256>(ga, s_red);
+    gb = block_sum_f<256>(gb, s_red);
+    hxx = block_sum_f<256>(hxx, s_red);
+    hx = block_sum_f<256>(hx, s_red);
+    if (threadIdx.x == 0) {
+        float *o = stats + 8 * i;
+        o[1] = 2.f * ga;
+        o[2] = 2.f * gb;
+        o[3] = 2.f * hxx;
+        o[4] = 2.f * hx;
+        o[5] = 2.f * (float)(e - s);
+        o[6] = sc;
+        o[7] = 0.f;
+    }
+}
+
+// Newton step per leaf on the quadratic loss, projected onto a' >= 0 (the
+// monotone set): if the step would make the slope negative, the slope is
+// set to 0 and b takes its optimum for that slope.
+__global__ void k_rmi_update(float *model, const uint32_t *st, const float *stats) {
+    const int L = (int)reinterpret_cast<const RmiHead *>(model)->L;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L || st[i + 1] == st[i]) return;
+    RmiLeaf *lf = reinterpret_cast<RmiLeaf *>(model + 8) + i;
+    const float *g = stats + 8 * i;
+    const float sc = lf->pad0;
+    float a = __fdiv_rn(lf->a, sc), b = lf->b;
+    const float ga = g[1], gb = g[2], h00 = g[3], h01 = g[4], h11 = g[5];
+    const float det = h00 * h11 - h01 * h01;
+    float na, nb;
+    if (det > 1e-6f * h00 * h11 && h00 > 0.f) {
+        na = a - (h11 * ga - h01 * gb) / det;
+        nb = b - (h00 * gb - h01 * ga) / det;
+    } else {
+        na = a;
+        nb = b - gb / h11;
+    }
+    if (!(na >= 0.f)) {
+        nb = b - (gb - h01 * a) / h11;
+        na = 0.f;
+    }
+    lf->a = __fmul_rn(na, sc);
+    lf->b = nb;
+}
+
+// ------------------------------------------------------------ inference
+template <int DT>
+__global__ __launch_bounds__(256) void k_rmi_codes(const typename KT<DT>::U *keys, uint32_t n, const float *model,
+                                                   int cb, uint32_t *codes) {
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i >= n) return;
+    const RmiHead h = *reinterpret_cast<const RmiHead *>(model);
+    codes[i] = rmi_code(h, reinterpret_cast<const RmiLeaf *>(model + 8), KT<DT>::image(keys[i]), cb,
+                        (float)(1u << cb));
+}
+
+// ------------------------------------------------------ chunk sorting
+struct LearnedState {
+    uint32_t fb_count;      // fallback runs found
+    uint32_t fb_next;       // fallback work counter
+    uint32_t chunks;        // on-chip chunk sorts
+    uint32_t pad;
+    unsigned long long fb_keys;
+    unsigned long long const_keys;
+};
+
+struct FbRun {
+    uint32_t start, len;
+};
+
+template <int DT>
+__device__ __forceinline__ uint32_t code_at(const typename KT<DT>::U *keys, uint32_t i, const RmiHead &h,
+                                            const RmiLeaf *lv, int cb, float scale) {
+    return rmi_code(h, lv, KT<DT>::image(keys[i]), cb, scale);
+}
+
+// Smallest i >= q with code(i) != c (or n); codes are nondecreasing in the
+// position.  Gallops, then bisects (single thread).
+template <int DT>
+__device__ uint32_t next_code_change(const typename KT<DT>::U *keys, uint32_t n, uint32_t q, uint32_t c,
+                                     const RmiHead &h, const RmiLeaf *lv, int cb, float scale) {
+    if (q >= n || code_at<DT>(keys, q, h, lv, cb, scale) != c) return q;
+    uint32_t good = q;  // code(good) == c
+    uint64_t step = 1;
+    uint32_t bad = n;   // first known position with a different code (or n)
+    while (true) {
+        const uint64_t probe = (uint64_t)good + step;
+        if (probe >= n) break;
+        if (code_at<DT>(keys, (uint32_t)probe, h, lv, cb, scale) != c) {
+            bad = (uint32_t)probe;
+            break;
+        }
+        good = (uint32_t)probe;
+        step <<= 1;
+    }
+    while (bad - good > 1) {
+        const uint32_t mid = good + (bad - good) / 2;
+        if (code_at<DT>(keys, mid, h, lv, cb, scale) != c) bad = mid;
+        else good = mid;
+    }
+    return bad;
+}
+
+// A piece boundary: p itself if p is 0, n, or the first key of a code run;
+// otherwise the start of the next code run.
+template <int DT>
+__device__ uint32_t piece_boundary(const typename KT<DT>::U *keys, uint32_t n, uint32_t p, const RmiHead &h,
+                                   const RmiLeaf *lv, int cb, float scale) {
+    if (p == 0 || p >= n) return p >= n ? n : 0;
+    const uint32_t c = code_at<DT>(keys, p - 1, h, lv, cb, scale);
+    return next_code_change<DT>(keys, n, p, c, h, lv, cb, scale);
+}
+
+template <typename U, int W, int IPT>
+struct ChunkSmem {
+    SmallSmem<U, false, W, IPT> sort;
+    uint32_t code[W * 64 * IPT + 1];
+    uint32_t cut;
+    uint32_t bound[2];
+};
+
+// One workgroup per piece of the code-ordered array: cuts it at code
+// changes into chunks of at most W*64*IPT keys and sorts each on chip.
+template <int DT, int W, int IPT>
+__global__ __launch_bounds__(W * 64) void k_chunk_sort(typename KT<DT>::U *keys, uint32_t n, const float *model,
+                                                       int cb, uint32_t piece, FbRun *fb, LearnedState *ls) {
+    using U = typename KT<DT>::U;
+    constexpr int B = W * 64, CAP = B * IPT;
+    __shared__ ChunkSmem<U, W, IPT> sm;
+    const int tid = threadIdx.x;
+    const RmiHead h = *reinterpret_cast<const RmiHead *>(model);
+    const RmiLeaf *lv = reinterpret_cast<const RmiLeaf *>(model + 8);
+    const float scale = (float)(1u << cb);
+    const uint64_t p0 = (uint64_t)blockIdx.x * piece;
+    const uint64_t p1 = std::min<uint64_t>(p0 + piece, n);
+    if (tid == 0) {
+        sm.bound[0] = piece_boundary<DT>(keys, n, (uint32_t)p0, h, lv, cb, scale);
+        sm.bound[1] = piece_boundary<DT>(keys, n, (uint32_t)p1, h, lv, cb, scale);
+    }
+    __syncthreads();
+    uint32_t pos = sm.bound[0];
+    const uint32_t end = sm.bound[1];
+    uint32_t nchunks = 0;
+    while (pos < end) {
+        const uint32_t len = std::min<uint32_t>(CAP, end - pos);
+        uint32_t cut = end;
+        if (pos + len < end) {
+            // codes of keys pos .. pos+len (one past the chunk)
+            for (uint32_t e = tid; e <= len; e += B) sm.code[e] = code_at<DT>(keys, pos + e, h, lv, cb, scale);
+            if (tid == 0) sm.cut = 0;
+            __syncthreads();
+            uint32_t best = 0;
+            for (uint32_t e = 1 + tid; e <= len; e += B)
+                if (sm.code[e] != sm.code[e - 1]) best = e;
+            if (best) atomicMax(&sm.cut, best);
+            __syncthreads();
+            const uint32_t q = sm.cut;
+            if (q == 0) {
+                // one code spans past the chunk: hand the whole run to the fallback
+                if (tid == 0) {
+                    const uint32_t run_end = next_code_change<DT>(keys, end, pos + len, sm.code[0], h, lv, cb, scale);
+                    const uint32_t slot = atomicAdd(&ls->fb_count, 1u);
+                    fb[slot] = FbRun{pos, run_end - pos};
+                    sm.cut = run_end;
+                }
+                __syncthreads();
+                pos = sm.cut;
+                __syncthreads();
+                continue;
+            }
+            cut = pos + q;
+            __syncthreads();
+        }
+        lds_sort_tile<DT, false, W, IPT>(keys + pos, keys + pos, nullptr, cut - pos, sm.sort, tid);
+        ++nchunks;
+        pos = cut;
+        __syncthreads();
+    }
+    if (tid == 0 && nchunks) atomicAdd(&ls->chunks, nchunks);
+}
+
+// Fallback, step 1: flag runs holding more than one distinct key (every
+// workgroup scans a slice of every run).
+template <int DT>
+__global__ __launch_bounds__(256) void k_fb_check(const typename KT<DT>::U *keys, const FbRun *fb,
+                                                  const LearnedState *ls, uint32_t *nonconst) {
+    using U = typename KT<DT>::U;
+    const uint32_t nr = ls->fb_count;
+    for (uint32_t r = 0; r < nr; ++r) {
+        const FbRun run = fb[r];
+        const U first = keys[run.start];
+        bool diff = false;
+        for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < run.len; i += (uint64_t)gridDim.x * 256)
+            diff |= keys[run.start + i] != first;
+        if (__syncthreads_or(diff) && threadIdx.x == 0) atomicOr(&nonconst[r], 1u);
+    }
+}
+
+// Fallback, step 2: every non-constant run is radix-sorted by one workgroup.
+template <int DT>
+__global__ __launch_bounds__(256) void k_fb_sort(typename KT<DT>::U *keys, typename KT<DT>::U *tmp, const FbRun *fb,
+                                                 LearnedState *ls, const uint32_t *nonconst) {
+    using U = typename KT<DT>::U;
+    __shared__ LongSmem<U, 4, 16> sm;
+    __shared__ uint32_t s_r;
+    const uint32_t nr = ls->fb_count;
+    while (true) {
+        if (threadIdx.x == 0) s_r = atomicAdd(&ls->fb_next, 1u);
+        __syncthreads();
+        const uint32_t r = s_r;
+        __syncthreads();
+        if (r >= nr) break;
+        const FbRun run = fb[r];
+        if (threadIdx.x == 0) {
+            atomicAdd(&ls->fb_keys, (unsigned long long)run.len);
+            if (!nonconst[r]) atomicAdd(&ls->const_keys, (unsigned long long)run.len);
+        }
+        if (nonconst[r]) sort_long<DT, 4, 16>(keys + run.start, tmp + run.start, run.len, sm);
+    }
+}
+
+__global__ void k_learned_reset(LearnedState *ls, uint32_t *nonconst, uint32_t cap) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *ls = LearnedState{};
+    for (uint32_t k = i; k < cap; k += gridDim.x * blockDim.x) nonconst[k] = 0;
+}
+
+// Top-level bucket histogram (statistics only).
+template <int DT>
+__global__ __launch_bounds__(256) void k_bucket_hist(const typename KT<DT>::U *keys, uint32_t n, const float *model,
+                                                     int cb, int shift, int nb, uint32_t *hist) {
+    extern __shared__ uint32_t s_h[];
+    for (int i = threadIdx.x; i < nb; i += 256) s_h[i] = 0;
+    __syncthreads();
+    const RmiHead h = *reinterpret_cast<const RmiHead *>(model);
+    const RmiLeaf *lv = reinterpret_cast<const RmiLeaf *>(model + 8);
+    const float scale = (float)(1u << cb);
+    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u)
+        atomicAdd(&s_h[rmi_code(h, lv, KT<DT>::image(keys[i]), cb, scale) >> shift], 1u);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb; i += 256)
+        if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
+}
+
+// ------------------------------------------------------------ drivers
+static int64_t sample_count(int64_t n, float frac) {
+    int64_t m = (int64_t)((double)n * (double)frac);
+    m = std::max<int64_t>(m, 4096);
+    return std::min<int64_t>(m, n);
+}
+
+static int code_bits(int64_t n) {
+    int lg = 1;
+    while (lg < 40 && (int64_t(1) << lg) < n) ++lg;
+    return std::min(24, std::max(12, lg - 7));
+}
+
+template <int DT>
+static ak_status fit_t(Workspace *ws, const void *sorted, uint32_t m, int L, int iters, float *model,
+                       bool untrained) {
+    using U = typename KT<DT>::U;
+    hipStream_t s = ws->stream;
+    ak_status r;
+    const size_t need = (size_t)(L + 1) * 4 + 256 + (size_t)m * 4 + 256 + (size_t)L * 32;
+    if ((r = ws_reserve(ws, &ws->aux[1], &ws->aux_bytes[1], need)) != AK_OK) return r;
+    char *base = (char *)ws->aux[1];
+    uint32_t *st = (uint32_t *)base;
+    float *resid = (float *)(base + (((size_t)(L + 1) * 4 + 255) & ~size_t(255)));
+    float *stats = (float *)((char *)resid + (((size_t)m * 4 + 255) & ~size_t(255)));
+    const U *srt = (const U *)sorted;
+    const unsigned lg = (unsigned)((L + 256) / 256);
+    if (untrained) {
+        hipLaunchKernelGGL((k_rmi_untrained<DT>), dim3(lg), dim3(256), 0, s, srt, m, L, model);
+        AK_LAUNCH_CHECK("k_rmi_untrained");
+        return AK_OK;
+    }
+    hipLaunchKernelGGL((k_rmi_root<DT>), dim3(1), dim3(64), 0, s, srt, m, L, model);
+    AK_LAUNCH_CHECK("k_rmi_root");
+    hipLaunchKernelGGL((k_rmi_bounds<DT>), dim3(lg), dim3(256), 0, s, srt, m, (const float *)model, st);
+    AK_LAUNCH_CHECK("k_rmi_bounds");
+    hipLaunchKernelGGL((k_rmi_leaf_init<DT>), dim3(lg), dim3(256), 0, s, srt, m, (const uint32_t *)st, model);
+    AK_LAUNCH_CHECK("k_rmi_leaf_init");
+    for (int it = 0; it < iters; ++it) {
+        hipLaunchKernelGGL((k_rmi_fwd<DT>), dim3(L), dim3(256), 0, s, srt, m, (const uint32_t *)st,
+                           (const float *)model, resid, stats);
+        AK_LAUNCH_CHECK("k_rmi_fwd");
+        hipLaunchKernelGGL((k_rmi_bwd<DT>), dim3(L), dim3(256), 0, s, srt, m, (const uint32_t *)st,
+                           (const float *)model, (const float *)resid, stats);
+        AK_LAUNCH_CHECK("k_rmi_bwd");
+        hipLaunchKernelGGL(k_rmi_update, dim3(lg), dim3(256), 0, s, model, (const uint32_t *)st,
+                           (const float *)stats);
+        AK_LAUNCH_CHECK("k_rmi_update");
+    }
+    return AK_OK;
+}
+
+template <int DT>
+static ak_status leaf_grad_t(Workspace *ws, const void *sorted, uint32_t m, const float *model_in, float *out) {
+    using U = typename KT<DT>::U;
+    hipStream_t s = ws->stream;
+    float head[8];
+    AK_HIP(hipMemcpyAsync(head, model_in, sizeof(head), hipMemcpyDeviceToHost, s));
+    AK_HIP(hipStreamSynchronize(s));
+    const int L = (int)head[3];
+    if (L <= 0 || L > 65536) {
+        set_error("model has a bad leaf count");
+        return AK_ERR_INVALID_ARG;
+    }
+    ak_status r;
+    const size_t mbytes = (8 + 8 * (size_t)L) * 4;
+    const size_t need = (size_t)(L + 1) * 4 + 256 + (size_t)m * 4 + 256 + mbytes;
+    if ((r = ws_reserve(ws, &ws->aux[1], &ws->aux_bytes[1], need)) != AK_OK) return r;
+    char *base = (char *)ws->aux[1];
+    uint32_t *st = (uint32_t *)base;
+    float *resid = (float *)(base + (((size_t)(L + 1) * 4 + 255) & ~size_t(255)));
+    float *model = (float *)((char *)resid + (((size_t)m * 4 + 255) & ~size_t(255)));
+    // the scale of each leaf is derived from the samples (as in a fit); the
+    // given parameters (a, b, x0) are used as they are
+    AK_HIP(hipMemcpyAsync(model, model_in, mbytes, hipMemcpyDeviceToDevice, s));
+    const U *srt = (const U *)sorted;
+    const unsigned lg = (unsigned)((L + 256) / 256);
+    hipLaunchKernelGGL((k_rmi_bounds<DT>), dim3(lg), dim3(256), 0, s, srt, m, (const float *)model, st);
+    AK_LAUNCH_CHECK("k_rmi_bounds");
+    hipLaunchKernelGGL((k_leaf_scale<DT>), dim3(lg), dim3(256), 0, s, srt, (const uint32_t *)st, model);
+    AK_LAUNCH_CHECK("k_leaf_scale");
+    hipLaunchKernelGGL((k_rmi_fwd<DT>), dim3(L), dim3(256), 0, s, srt, m, (const uint32_t *)st,
+                       (const float *)model, resid, out);
+    AK_LAUNCH_CHECK("k_rmi_fwd");
+    hipLaunchKernelGGL((k_rmi_bwd<DT>), dim3(L), dim3(256), 0, s, srt, m, (const uint32_t *)st,
+                       (const float *)model, (const float *)resid, out);
+    AK_LAUNCH_CHECK("k_rmi_bwd");
+    return AK_OK;
+}
+
+template <int DT>
+static ak_status learned_t(Workspace *ws, void *keys, int64_t n64, const ak_learned_cfg *cfg,
+                           ak_learned_stats *stats) {
+    using U = typename KT<DT>::U;
+    hipStream_t s = ws->stream;
+    const uint32_t n = (uint32_t)n64;
+    if (n64 <= small_sort_capacity(DT)) {  // one workgroup sorts it on chip
+        ak_status r = radix_sort(ws, DT, keys, nullptr, n64, 1);
+        if (r == AK_OK && stats) {
+            *stats = ak_learned_stats{};
+            stats->n = n64;
+            AK_HIP(hipStreamSynchronize(s));
+        }
+        return r;
+    }
+    const int L = cfg->leaves;
+    const uint32_t m = (uint32_t)sample_count(n64, cfg->sample_frac);
+    const int cb = code_bits(n64);
+    constexpr int CW = 4, CIPT = 16, CAP = CW * 64 * CIPT;
+    const uint32_t fb_cap = n / CAP + 2;
+    ak_status r;
+    // aux[0]: sample keys | model | learned state | fallback runs | flags
+    const size_t off_model = ((size_t)m * sizeof(U) + 255) & ~size_t(255);
+    const size_t off_state = off_model + (((8 + 8 * (size_t)L) * 4 + 255) & ~size_t(255));
+    const size_t off_fb = off_state + 256;
+    const size_t off_nc = off_fb + (((size_t)fb_cap * sizeof(FbRun) + 255) & ~size_t(255));
+    const size_t need = off_nc + (size_t)fb_cap * 4 + 256;
+    if ((r = ws_reserve(ws, &ws->aux[0], &ws->aux_bytes[0], need)) != AK_OK) return r;
+    char *base = (char *)ws->aux[0];
+    U *sample = (U *)base;
+    float *model = (float *)(base + off_model);
+    LearnedState *ls = (LearnedState *)(base + off_state);
+    FbRun *fb = (FbRun *)(base + off_fb);
+    uint32_t *nonconst = (uint32_t *)(base + off_nc);
+
+    hipLaunchKernelGGL(k_learned_reset, dim3(std::min<uint32_t>((fb_cap + 255) / 256, 1024)), dim3(256), 0, s, ls,
+                       nonconst, fb_cap);
+    AK_LAUNCH_CHECK("k_learned_reset");
+    // 1. sample + sort the sample
+    hipLaunchKernelGGL((k_sample<U>), dim3((m + 255) / 256), dim3(256), 0, s, (const U *)keys, (uint64_t)n,
+                       cfg->seed, m, sample);
+    AK_LAUNCH_CHECK("k_sample");
+    if ((r = radix_sort(ws, DT, sample, nullptr, m, 1)) != AK_OK) return r;
+    // 2. fit
+    if ((r = fit_t<DT>(ws, sample, m, L, cfg->train_iters, model, cfg->untrained != 0)) != AK_OK) return r;
+    // 3. order by code
+    if ((r = code_partition(ws, DT, keys, n, model, cb, 2)) != AK_OK) return r;
+    // 4. chunks on chip
+    const uint32_t pieces_target = (uint32_t)num_cus() * 16;
+    uint32_t piece = std::max<uint32_t>((uint32_t)CAP * 4, (n + pieces_target - 1) / pieces_target);
+    const uint32_t npieces = (n + piece - 1) / piece;
+    hipLaunchKernelGGL((k_chunk_sort<DT, CW, CIPT>), dim3(npieces), dim3(CW * 64), 0, s, (U *)keys, n,
+                       (const float *)model, cb, piece, fb, ls);
+    AK_LAUNCH_CHECK("k_chunk_sort");
+    // 5. fallback runs
+    if ((r = ws_reserve(ws, &ws->keys0, &ws->keys0_bytes, (size_t)n * sizeof(U))) != AK_OK) return r;
+    hipLaunchKernelGGL((k_fb_check<DT>), dim3(num_cus() * 4), dim3(256), 0, s, (const U *)keys, (const FbRun *)fb,
+                       (const LearnedState *)ls, nonconst);
+    AK_LAUNCH_CHECK("k_fb_check");
+    hipLaunchKernelGGL((k_fb_sort<DT>), dim3(num_cus() * 2), dim3(256), 0, s, (U *)keys, (U *)ws->keys0,
+                       (const FbRun *)fb, ls, (const uint32_t *)nonconst);
+    AK_LAUNCH_CHECK("k_fb_sort");
+
+    if (stats) {
+        const int bl = std::min(std::min(cfg->buckets_log2, cb), 14);
+        const int nb = 1 << bl;
+        if ((r = ws_reserve(ws, &ws->aux[2], &ws->aux_bytes[2], (size_t)nb * 4)) != AK_OK) return r;
+        uint32_t *hist = (uint32_t *)ws->aux[2];
+        AK_HIP(hipMemsetAsync(hist, 0, (size_t)nb * 4, s));
+        hipLaunchKernelGGL((k_bucket_hist<DT>), dim3(num_cus() * 4), dim3(256), (size_t)nb * 4, s, (const U *)keys,
+                           n, (const float *)model, cb, cb - bl, nb, hist);
+        AK_LAUNCH_CHECK("k_bucket_hist");
+        LearnedState hls;
+        std::vector<uint32_t> hh(nb);
+        AK_HIP(hipMemcpyAsync(&hls, ls, sizeof(hls), hipMemcpyDeviceToHost, s));
+        AK_HIP(hipMemcpyAsync(hh.data(), hist, (size_t)nb * 4, hipMemcpyDeviceToHost, s));
+        AK_HIP(hipStreamSynchronize(s));
+        ak_learned_stats st{};
+        st.n = n64;
+        st.sample_size = m;
+        st.leaves = L;
+        st.code_bits = cb;
+        st.max_bucket = *std::max_element(hh.begin(), hh.end());
+        st.imbalance = (double)st.max_bucket / ((double)n64 / nb);
+        st.fallback_keys = (int64_t)hls.fb_keys;
+        st.constant_keys = (int64_t)hls.const_keys;
+        st.fallback_runs = hls.fb_count;
+        st.chunks = hls.chunks;
+        *stats = st;
+    }
+    return AK_OK;
+}
+
+#define AK_DT_SWITCH(dt, FN, ...)                          \
+    switch (dt) {                                          \
+    case AK_I32: return FN<AK_I32>(__VA_ARGS__);           \
+    case AK_I64: return FN<AK_I64>(__VA_ARGS__);           \
+    case AK_U32: return FN<AK_U32>(__VA_ARGS__);           \
+    case AK_U64: return FN<AK_U64>(__VA_ARGS__);           \
+    case AK_F32: return FN<AK_F32>(__VA_ARGS__);           \
+    case AK_F64: return FN<AK_F64>(__VA_ARGS__);           \
+    }                                                      \
+    return AK_ERR_UNSUPPORTED_DTYPE;
+
+ak_status learned_sort(Workspace *ws, int dt, void *keys, int64_t n, const ak_learned_cfg *cfg,
+                       ak_learned_stats *stats) {
+    AK_DT_SWITCH(dt, learned_t, ws, keys, n, cfg, stats)
+}
+
+size_t learned_temp_bytes(int dt, int64_t n, const ak_learned_cfg *cfg) {
+    const int64_t m = sample_count(n, cfg->sample_frac);
+    const size_t kb = (size_t)dtype_bytes(dt);
+    return radix_temp_bytes(dt, n, false) + (size_t)m * kb * 2 + (size_t)m * 4 + (size_t)cfg->leaves * 64 +
+           (size_t)(n / 4096 + 2) * 12;
+}
+
+template <int DT>
+static ak_status sample_t(hipStream_t s, const void *keys, int64_t n, uint64_t seed, int64_t m, void *out) {
+    using U = typename KT<DT>::U;
+    hipLaunchKernelGGL((k_sample<U>), dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, (const U *)keys,
+                       (uint64_t)n, seed, (uint32_t)m, (U *)out);
+    AK_LAUNCH_CHECK("k_sample");
+    return AK_OK;
+}
+
+ak_status learned_sample(hipStream_t s, int dt, const void *keys, int64_t n, uint64_t seed, int64_t m, void *out) {
+    AK_DT_SWITCH(dt, sample_t, s, keys, n, seed, m, out)
+}
+
+template <int DT>
+static ak_status fit_entry_t(Workspace *ws, const void *sorted, int64_t m, int L, int iters, float *model) {
+    return fit_t<DT>(ws, sorted, (uint32_t)m, L, iters, model, false);
+}
+
+ak_status rmi_fit(Workspace *ws, int dt, const void *sorted, int64_t m, int leaves, int iters, float *model) {
+    AK_DT_SWITCH(dt, fit_entry_t, ws, sorted, m, leaves, iters, model)
+}
+
+template <int DT>
+static ak_status grad_entry_t(Workspace *ws, const void *sorted, int64_t m, const float *model, float *out) {
+    return leaf_grad_t<DT>(ws, sorted, (uint32_t)m, model, out);
+}
+
+ak_status rmi_leaf_grad(Workspace *ws, int dt, const void *sorted, int64_t m, const float *model, float *out) {
+    AK_DT_SWITCH(dt, grad_entry_t, ws, sorted, m, model, out)
+}
+
+template <int DT>
+static ak_status codes_t(hipStream_t s, const void *keys, int64_t n, const float *model, int cb, uint32_t *codes) {
+    using U = typename KT<DT>::U;
+    hipLaunchKernelGGL((k_rmi_codes<DT>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (const U *)keys,
+                       (uint32_t)n, model, cb, codes);
+    AK_LAUNCH_CHECK("k_rmi_codes");
+    return AK_OK;
+}
+
+ak_status rmi_codes(hipStream_t s, int dt, const void *keys, int64_t n, const float *model, int cb,
+                    uint32_t *codes) {
+    AK_DT_SWITCH(dt, codes_t, s, keys, n, model, cb, codes)
+}
+
+}  // namespace ak

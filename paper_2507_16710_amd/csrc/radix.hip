@@ -1,0 +1,504 @@
+// LSD radix sort for gfx950: up-front multi-place histogram, digit-offset
+// scan with device-side pass skipping, and one-sweep digit passes (stable
+// in-tile ranking by wave ballots, decoupled look-back across tiles,
+// LDS-staged coalesced scatter).  Also the single-workgroup on-chip sort for
+// small inputs.
+//
+// What is computed is the paper's sort / sortperm (Sec. II-B): a stable
+// ascending sort under the Julia Base order.  The paper builds its sorter
+// as a merge sort in a portable kernel language; this file instead uses
+// 8-bit LSD radix passes because ballots and per-wave LDS counters are
+// available on gfx950 (the paper names wave-level intrinsics as what radix
+// sort needs, Sec. I-B), and the prefix scan uses the look-back scheme the
+// paper cites for its accumulate (Sec. II-B, "opportunistic look-back").
+#include <cstdlib>
+
+#include "radix_common.h"
+#include "radix_kernels.h"
+#include "lds_sort.h"
+#include "rmi_device.h"
+
+namespace ak {
+
+// ---------------------------------------------------------------- init
+__global__ void k_run_init(RunState *st) {
+    const int tid = threadIdx.x;
+    for (int i = tid; i < MAX_PLACES * RADIX; i += blockDim.x) (&st->hist[0][0])[i] = 0;
+    if (tid < MAX_PLACES) st->tile_ctr[tid] = 0;
+}
+
+// ---------------------------------------------------------- histogram
+// One read of the keys; counts the digit of every place.  LDS counters per
+// workgroup, then one global atomic per nonzero bin.  A wave whose lanes all
+// hold the same digit adds its lane count once instead of 64 conflicting
+// LDS atomics (long runs of equal digits are the common case for the
+// high places of small keys).
+template <int DT, bool CODE>
+__global__ __launch_bounds__(256) void k_hist(const typename KT<DT>::U *__restrict__ keys, uint32_t n,
+                                              int nplaces, RunState *st, const float *model, int cb) {
+    using U = typename KT<DT>::U;
+    constexpr int B = 256, ITEMS = 8;
+    __shared__ uint32_t s_h[MAX_PLACES * RADIX];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < MAX_PLACES * RADIX; i += B) s_h[i] = 0;
+    RmiHead h;
+    const RmiLeaf *leaves = nullptr;
+    float scale = 0.f;
+    if (CODE) {
+        h = *reinterpret_cast<const RmiHead *>(model);
+        leaves = reinterpret_cast<const RmiLeaf *>(model + 8);
+        scale = (float)(1u << cb);
+    }
+    __syncthreads();
+    const uint32_t stride = gridDim.x * B * ITEMS;
+    for (uint32_t base = blockIdx.x * B * ITEMS; base < n; base += stride) {
+        U v[ITEMS];
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+            const uint32_t i = base + it * B + tid;
+            v[it] = i < n ? __builtin_nontemporal_load(keys + i) : U(0);
+        }
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+            const uint32_t i = base + it * B + tid;
+            if (i >= n) break;
+            U t = KT<DT>::image(v[it]);
+            if (CODE) t = (U)rmi_code(h, leaves, t, cb, scale);
+            const uint64_t act = ballot64(true);
+            for (int p = 0; p < nplaces; ++p) {
+                const uint32_t d = (uint32_t)(t >> (p * RADIX_BITS)) & (RADIX - 1);
+                const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+                if (ballot64(d == d0) == act) {
+                    if (count_below(act) == 0) atomicAdd(&s_h[p * RADIX + d0], (uint32_t)__popcll(act));
+                } else {
+                    atomicAdd(&s_h[p * RADIX + d], 1u);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < nplaces * RADIX; i += B)
+        if (s_h[i]) atomicAdd(&st->hist[i / RADIX][i % RADIX], s_h[i]);
+}
+
+// --------------------------------------------------------- digit scan
+// Exclusive digit offsets per place; a place where one digit holds every
+// key is inactive (its pass would be a copy).  Active passes are numbered
+// so that each pass kernel can pick its source and destination buffers
+// without a host round trip.
+__global__ __launch_bounds__(256) void k_scan(RunState *st, uint32_t n, int nplaces) {
+    __shared__ uint32_t s_wsum[4];
+    __shared__ uint32_t s_buf[RADIX];
+    __shared__ int s_active[MAX_PLACES];
+    const int tid = threadIdx.x;
+    for (int p = 0; p < nplaces; ++p) {
+        const uint32_t c = st->hist[p][tid];
+        const int trivial = __syncthreads_or(c == n);
+        s_buf[tid] = c;
+        __syncthreads();
+        block_exscan<256, RADIX>(s_buf, s_buf, s_wsum, tid);
+        st->base[p][tid] = s_buf[tid];
+        if (tid == 0) s_active[p] = !trivial;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        int q = 0;
+        for (int p = 0; p < nplaces; ++p) q += s_active[p];
+        int j = 0;
+        for (int p = 0; p < MAX_PLACES; ++p) {
+            PassDesc d;
+            d.active = p < nplaces ? s_active[p] : 0;
+            d.j = d.active ? j++ : -1;
+            d.q = q;
+            d.shift = p * RADIX_BITS;
+            st->desc[p] = d;
+        }
+        st->q = q;
+    }
+}
+
+// ----------------------------------------------------- one-sweep pass
+// One workgroup per tile of W*64*IPT keys, tiles taken in launch order from
+// an atomic counter (so every tile's predecessors are already running).
+// LDS: the per-wave 16-bit digit counters of the ranking phase share their
+// bytes with the key staging buffer of the scatter phase.
+template <typename U, bool VAL, bool CODE, int W, int IPT>
+struct OsSmem {
+    static constexpr int TILE = W * 64 * IPT;
+    static constexpr size_t KEYS = (size_t)TILE * sizeof(U) + (VAL ? (size_t)TILE * 4 : 0) + (CODE ? TILE : 0);
+    static constexpr size_t CNT = (size_t)W * RADIX * 2;
+    static constexpr size_t RAW = KEYS > CNT ? KEYS : CNT;
+};
+
+template <int DT, bool VAL, int W, int IPT, bool CODE>
+__global__ __launch_bounds__(W * 64) void k_onesweep(OnesweepArgs a) {
+    using U = typename KT<DT>::U;
+    using SM = OsSmem<U, VAL, CODE, W, IPT>;
+    constexpr int B = W * 64, TILE = B * IPT;
+    constexpr int K = B / RADIX;  // threads per digit in the look-back
+    static_assert(B >= RADIX && B % RADIX == 0, "block must cover the radix");
+    const PassDesc pd = a.st->desc[a.place];
+    if (!pd.active) return;
+
+    __shared__ __align__(16) uint8_t s_raw[SM::RAW];
+    __shared__ uint32_t s_tot[RADIX], s_start[RADIX], s_glob[RADIX];
+    __shared__ uint32_t s_wsum[W];
+    __shared__ uint32_t s_tile;
+    uint16_t *s_cnt = reinterpret_cast<uint16_t *>(s_raw);
+    U *s_keys = reinterpret_cast<U *>(s_raw);
+    uint32_t *s_vals = reinterpret_cast<uint32_t *>(s_raw + (size_t)TILE * sizeof(U));
+    uint8_t *s_dig = s_raw + (size_t)TILE * sizeof(U) + (VAL ? (size_t)TILE * 4 : 0);
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) s_tile = atomicAdd(&a.st->tile_ctr[a.place], 1u);
+
+    // buffers of this pass: sort mode ping-pongs between the keys and
+    // keys0; sortperm mode reads the const keys first, then keys0/keys1,
+    // and its values end in perm after the last active pass.
+    const int j = pd.j, q = pd.q;
+    const U *src;
+    U *dst;
+    const uint32_t *vsrc = nullptr;
+    uint32_t *vdst = nullptr;
+    if (!VAL) {
+        src = (const U *)((j & 1) ? a.t0 : a.keys);
+        dst = (U *)((j & 1) ? a.keys : a.t0);
+    } else {
+        src = (const U *)(j == 0 ? a.keys : (((j - 1) & 1) ? a.t1 : a.t0));
+        dst = (U *)((j & 1) ? a.t1 : a.t0);
+        auto vb = [&](int i) { return (((q - 1 - i) & 1) == 0) ? a.perm : a.v0; };
+        vsrc = j == 0 ? nullptr : vb(j - 1);
+        vdst = vb(j);
+    }
+    const bool last = (j == q - 1);
+    const int shift = pd.shift;
+
+    RmiHead h;
+    const RmiLeaf *leaves = nullptr;
+    float scale = 0.f;
+    if (CODE) {
+        h = *reinterpret_cast<const RmiHead *>(a.model);
+        leaves = reinterpret_cast<const RmiLeaf *>(a.model + 8);
+        scale = (float)(1u << a.cb);
+    }
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint32_t tbase = tile * (uint32_t)TILE;
+    const uint32_t tvalid = min((uint32_t)TILE, a.n - tbase);
+
+    U k[IPT];
+    uint32_t v[IPT], dg[IPT], rk[IPT];
+    const U *sp = src + tbase + w * 64 * IPT + lane;
+    if (tvalid == (uint32_t)TILE) {
+#pragma unroll
+        for (int jj = 0; jj < IPT; ++jj) k[jj] = __builtin_nontemporal_load(sp + jj * 64);
+    } else {
+#pragma unroll
+        for (int jj = 0; jj < IPT; ++jj) {
+            const uint32_t e = striped_elem<IPT>(w, jj, lane);
+            k[jj] = e < tvalid ? __builtin_nontemporal_load(sp + jj * 64) : U(0);
+        }
+    }
+    if (VAL) {
+#pragma unroll
+        for (int jj = 0; jj < IPT; ++jj) {
+            const uint32_t e = striped_elem<IPT>(w, jj, lane);
+            v[jj] = e >= tvalid ? 0u : (vsrc ? __builtin_nontemporal_load(vsrc + tbase + e) : tbase + e);
+        }
+    }
+#pragma unroll
+    for (int jj = 0; jj < IPT; ++jj) {
+        const uint32_t e = striped_elem<IPT>(w, jj, lane);
+        U t = KT<DT>::image(k[jj]);
+        if (CODE) t = (U)rmi_code(h, leaves, t, a.cb, scale);
+        dg[jj] = e < tvalid ? (uint32_t)(t >> shift) & (RADIX - 1) : 0u;
+    }
+
+    rank_match<RADIX_BITS, W, IPT, uint16_t>(dg, tvalid, rk, s_cnt, s_tot, tid);
+
+    // publish this tile's digit counts first, so successors can look back
+    uint64_t *lb = a.lookback + (size_t)tile * RADIX;
+    const uint32_t epoch = a.epoch;
+    for (int d = tid; d < RADIX; d += B)
+        lb_store(lb + d, lb_pack(epoch, tile == 0 ? LB_INC : LB_AGG, s_tot[d]));
+
+    block_exscan<B, RADIX>(s_tot, s_start, s_wsum, tid);
+    rank_finish<RADIX_BITS, W, IPT, uint16_t>(dg, rk, s_cnt, s_start, tid);
+
+    // decoupled look-back, K predecessors per round trip: thread (d, kk)
+    // reads tile p - kk; the group sums the counts down to the nearest
+    // inclusive prefix, or all K if none is inclusive, and repeats.
+    {
+        const int d = tid / K, kk = tid % K;
+        uint32_t excl = 0;
+        if (tile > 0) {
+            int64_t p = (int64_t)tile - 1;
+            while (true) {
+                const int64_t pt = p - kk;
+                uint64_t wv = pt >= 0 ? lb_load(a.lookback + (size_t)pt * RADIX + d) : lb_pack(epoch, LB_INC, 0u);
+                uint32_t fl = (uint32_t)(wv >> 32) & 3u;
+                if ((uint32_t)(wv >> 34) != epoch) fl = 0;
+                // nearest inclusive predecessor within the window
+                uint32_t inc_at = fl == LB_INC ? (uint32_t)kk : (uint32_t)K;
+                uint32_t notready_at = fl == 0 ? (uint32_t)kk : (uint32_t)K;
+#pragma unroll
+                for (int o = 1; o < K; o <<= 1) {
+                    inc_at = min(inc_at, (uint32_t)__shfl_xor((int)inc_at, o, 64));
+                    notready_at = min(notready_at, (uint32_t)__shfl_xor((int)notready_at, o, 64));
+                }
+                const uint32_t need = inc_at < (uint32_t)K ? inc_at : (uint32_t)K - 1;
+                if (notready_at <= need) {
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                uint32_t c = (uint32_t)kk <= need ? (uint32_t)wv : 0u;
+#pragma unroll
+                for (int o = 1; o < K; o <<= 1) c += (uint32_t)__shfl_xor((int)c, o, 64);
+                excl += c;
+                if (inc_at < (uint32_t)K) break;
+                p -= K;
+            }
+            if (kk == 0) lb_store(lb + d, lb_pack(epoch, LB_INC, excl + s_tot[d]));
+        }
+        if (kk == 0) s_glob[d] = a.st->base[a.place][d] + excl - s_start[d];
+    }
+    __syncthreads();  // counters are dead from here on: their bytes hold keys
+
+#pragma unroll
+    for (int jj = 0; jj < IPT; ++jj) {
+        const uint32_t e = striped_elem<IPT>(w, jj, lane);
+        if (e < tvalid) {
+            s_keys[rk[jj]] = k[jj];
+            if (CODE) s_dig[rk[jj]] = (uint8_t)dg[jj];
+            if (VAL) s_vals[rk[jj]] = v[jj];
+        }
+    }
+    __syncthreads();
+
+    // coalesced scatter: consecutive threads write consecutive slots of a
+    // digit's run
+#pragma unroll
+    for (int jj = 0; jj < IPT; ++jj) {
+        const uint32_t i = (uint32_t)(jj * B + tid);
+        if (i < tvalid) {
+            const U key = s_keys[i];
+            const uint32_t d = CODE ? (uint32_t)s_dig[i] : (uint32_t)(KT<DT>::image(key) >> shift) & (RADIX - 1);
+            const uint32_t pos = s_glob[d] + i;
+            if (!VAL || !last) __builtin_nontemporal_store(key, dst + pos);
+            if (VAL) __builtin_nontemporal_store(s_vals[i], vdst + pos);
+        }
+    }
+}
+
+// ---------------------------------------------------------- finalize
+// Sort mode: after an odd number of active passes the result sits in
+// keys0 and is copied back.  Sortperm mode: with no active pass (all keys
+// equal) the permutation is the identity.
+template <typename U, bool VAL>
+__global__ __launch_bounds__(256) void k_finalize(const RunState *st, U *keys, const U *t0, uint32_t *perm,
+                                                  uint32_t n) {
+    const int q = st->q;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    if (!VAL) {
+        if ((q & 1) == 0) return;
+        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+            __builtin_nontemporal_store(__builtin_nontemporal_load(t0 + i), keys + i);
+    } else {
+        if (q != 0) return;
+        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) perm[i] = i;
+    }
+}
+
+template <int DT, bool VAL, int W, int IPT>
+__global__ __launch_bounds__(W * 64) void k_small_sort(const typename KT<DT>::U *in, typename KT<DT>::U *out,
+                                                       uint32_t *perm, uint32_t n) {
+    using U = typename KT<DT>::U;
+    __shared__ SmallSmem<U, VAL, W, IPT> sm;
+    lds_sort_tile<DT, VAL, W, IPT>(in, out, perm, n, sm, threadIdx.x);
+}
+
+// ------------------------------------------------------------ driver
+// default shape per (64-bit keys, values), from the tuning sweep
+static const int OS_DEFAULT[2][2] = {{0, 0}, {0, 0}};
+
+int os_variant(int dt, bool val) {
+    static int forced = -2;
+    if (forced == -2) {
+        const char *e = getenv("AK_OS_VARIANT");
+        forced = (e && *e) ? atoi(e) : -1;
+        if (forced >= OS_NVAR) forced = -1;
+    }
+    return forced >= 0 ? forced : OS_DEFAULT[key_bits(dt) == 64][val];
+}
+
+constexpr int SMALL_W = 4, SMALL_IPT = 16;
+
+int64_t small_sort_capacity(int) { return SMALL_W * 64 * SMALL_IPT; }
+
+static inline int tile_keys(int dt, bool val) { return os_tile(dt, val); }
+
+size_t radix_temp_bytes(int dt, int64_t n, bool perm) {
+    if (n <= small_sort_capacity(dt)) return 0;
+    const size_t kb = (size_t)dtype_bytes(dt);
+    const size_t tiles = (size_t)((n + tile_keys(dt, perm) - 1) / tile_keys(dt, perm));
+    size_t b = (size_t)n * kb + tiles * RADIX * 8;
+    if (perm) b += (size_t)n * kb + (size_t)n * 4;
+    return b;
+}
+
+template <int DT, bool VAL, bool CODE, int V>
+static void launch_pass_v(hipStream_t s, uint32_t tiles, const OnesweepArgs &a) {
+    constexpr OsShape sh = OS_SHAPES[key_bits(DT) == 64][VAL][V];
+    hipLaunchKernelGGL((k_onesweep<DT, VAL, sh.w, sh.ipt, CODE>), dim3(tiles), dim3(sh.w * 64), 0, s, a);
+}
+
+template <int DT, bool VAL, bool CODE>
+static ak_status launch_passes(Workspace *ws, RunState *st, const void *keys_in, void *t0, void *t1, uint32_t *v0,
+                               uint32_t *perm, uint32_t n, int nplaces, uint32_t epoch, const float *model, int cb) {
+    const int var = os_variant(DT, VAL);
+    const int TILE = os_tile(DT, VAL);
+    const uint32_t tiles = (n + TILE - 1) / TILE;
+    OnesweepArgs a{};
+    a.keys = const_cast<void *>(keys_in);
+    a.t0 = t0;
+    a.t1 = t1;
+    a.v0 = v0;
+    a.perm = perm;
+    a.lookback = ws->lookback;
+    a.st = st;
+    a.n = n;
+    a.model = model;
+    a.cb = cb;
+    for (int p = 0; p < nplaces; ++p) {
+        a.place = p;
+        a.epoch = epoch + (uint32_t)p;
+        switch (var) {
+        case 0: launch_pass_v<DT, VAL, CODE, 0>(ws->stream, tiles, a); break;
+        case 1: launch_pass_v<DT, VAL, CODE, 1>(ws->stream, tiles, a); break;
+        case 2: launch_pass_v<DT, VAL, CODE, 2>(ws->stream, tiles, a); break;
+        default: launch_pass_v<DT, VAL, CODE, 3>(ws->stream, tiles, a); break;
+        }
+        AK_LAUNCH_CHECK("k_onesweep");
+    }
+    return AK_OK;
+}
+
+template <int DT>
+static ak_status radix_sort_t(Workspace *ws, void *keys, uint32_t *perm, int64_t n64, int slot) {
+    using U = typename KT<DT>::U;
+    hipStream_t s = ws->stream;
+    const uint32_t n = (uint32_t)n64;
+    const bool pm = perm != nullptr;
+    if (n64 <= small_sort_capacity(DT)) {
+        if (pm)
+            hipLaunchKernelGGL((k_small_sort<DT, true, SMALL_W, SMALL_IPT>), dim3(1), dim3(SMALL_W * 64), 0, s,
+                               (const U *)keys, (U *)nullptr, perm, n);
+        else
+            hipLaunchKernelGGL((k_small_sort<DT, false, SMALL_W, SMALL_IPT>), dim3(1), dim3(SMALL_W * 64), 0, s,
+                               (const U *)keys, (U *)keys, (uint32_t *)nullptr, n);
+        AK_LAUNCH_CHECK("k_small_sort");
+        return AK_OK;
+    }
+    const size_t kb = sizeof(U);
+    ak_status r;
+    if ((r = ws_reserve(ws, &ws->keys0, &ws->keys0_bytes, (size_t)n * kb)) != AK_OK) return r;
+    if (pm) {
+        if ((r = ws_reserve(ws, &ws->keys1, &ws->keys1_bytes, (size_t)n * kb)) != AK_OK) return r;
+        if ((r = ws_reserve(ws, &ws->vals0, &ws->vals0_bytes, (size_t)n * 4)) != AK_OK) return r;
+    }
+    const int TILE = tile_keys(DT, pm);
+    const size_t tiles = (n + TILE - 1) / TILE;
+    if ((r = ws_reserve_lookback(ws, tiles * RADIX * 8)) != AK_OK) return r;
+    uint32_t epoch;
+    if ((r = ws_next_epoch(ws, &epoch)) != AK_OK) return r;
+    RunState *st = ws->state + slot;
+    const int nplaces = (int)(sizeof(U) * 8 / RADIX_BITS);
+
+    hipLaunchKernelGGL(k_run_init, dim3(1), dim3(256), 0, s, st);
+    AK_LAUNCH_CHECK("k_run_init");
+    const uint32_t hgrid = (uint32_t)std::min<int64_t>((n64 + 2047) / 2048, (int64_t)num_cus() * 8);
+    hipLaunchKernelGGL((k_hist<DT, false>), dim3(hgrid), dim3(256), 0, s, (const U *)keys, n, nplaces, st,
+                       (const float *)nullptr, 0);
+    AK_LAUNCH_CHECK("k_hist");
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(256), 0, s, st, n, nplaces);
+    AK_LAUNCH_CHECK("k_scan");
+    if (pm)
+        r = launch_passes<DT, true, false>(ws, st, keys, ws->keys0, ws->keys1, (uint32_t *)ws->vals0, perm, n,
+                                           nplaces, epoch, nullptr, 0);
+    else
+        r = launch_passes<DT, false, false>(ws, st, keys, ws->keys0, nullptr, nullptr, nullptr, n, nplaces, epoch,
+                                            nullptr, 0);
+    if (r != AK_OK) return r;
+    const uint32_t fgrid = (uint32_t)std::min<int64_t>((n64 + 1023) / 1024, (int64_t)num_cus() * 8);
+    if (pm)
+        hipLaunchKernelGGL((k_finalize<U, true>), dim3(fgrid), dim3(256), 0, s, st, (U *)nullptr,
+                           (const U *)nullptr, perm, n);
+    else
+        hipLaunchKernelGGL((k_finalize<U, false>), dim3(fgrid), dim3(256), 0, s, st, (U *)keys,
+                           (const U *)ws->keys0, (uint32_t *)nullptr, n);
+    AK_LAUNCH_CHECK("k_finalize");
+    return AK_OK;
+}
+
+ak_status radix_sort(Workspace *ws, int dt, void *keys, uint32_t *perm, int64_t n, int slot) {
+    switch (dt) {
+    case AK_I32: return radix_sort_t<AK_I32>(ws, keys, perm, n, slot);
+    case AK_I64: return radix_sort_t<AK_I64>(ws, keys, perm, n, slot);
+    case AK_U32: return radix_sort_t<AK_U32>(ws, keys, perm, n, slot);
+    case AK_U64: return radix_sort_t<AK_U64>(ws, keys, perm, n, slot);
+    case AK_F32: return radix_sort_t<AK_F32>(ws, keys, perm, n, slot);
+    case AK_F64: return radix_sort_t<AK_F64>(ws, keys, perm, n, slot);
+    }
+    set_error("radix_sort: unknown dtype");
+    return AK_ERR_UNSUPPORTED_DTYPE;
+}
+
+// ------------------------------------------- code-digit passes (learned)
+// Stable LSD passes over the model code of every key instead of its bits:
+// after ceil(cb/8) passes the keys are ordered by code, equal codes in
+// input order.
+template <int DT>
+static ak_status code_partition_t(Workspace *ws, void *keys, uint32_t n, const float *model, int cb, int slot,
+                                  uint32_t *q_host_unused) {
+    (void)q_host_unused;
+    using U = typename KT<DT>::U;
+    hipStream_t s = ws->stream;
+    ak_status r;
+    if ((r = ws_reserve(ws, &ws->keys0, &ws->keys0_bytes, (size_t)n * sizeof(U))) != AK_OK) return r;
+    const int TILE = tile_keys(DT, false);
+    const size_t tiles = (n + TILE - 1) / TILE;
+    if ((r = ws_reserve_lookback(ws, tiles * RADIX * 8)) != AK_OK) return r;
+    uint32_t epoch;
+    if ((r = ws_next_epoch(ws, &epoch)) != AK_OK) return r;
+    RunState *st = ws->state + slot;
+    const int nplaces = (cb + RADIX_BITS - 1) / RADIX_BITS;
+    hipLaunchKernelGGL(k_run_init, dim3(1), dim3(256), 0, s, st);
+    AK_LAUNCH_CHECK("k_run_init");
+    const uint32_t hgrid = (uint32_t)std::min<int64_t>(((int64_t)n + 2047) / 2048, (int64_t)num_cus() * 8);
+    hipLaunchKernelGGL((k_hist<DT, true>), dim3(hgrid), dim3(256), 0, s, (const U *)keys, n, nplaces, st, model, cb);
+    AK_LAUNCH_CHECK("k_hist(code)");
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(256), 0, s, st, n, nplaces);
+    AK_LAUNCH_CHECK("k_scan");
+    if ((r = launch_passes<DT, false, true>(ws, st, keys, ws->keys0, nullptr, nullptr, nullptr, n, nplaces, epoch,
+                                            model, cb)) != AK_OK)
+        return r;
+    const uint32_t fgrid = (uint32_t)std::min<int64_t>(((int64_t)n + 1023) / 1024, (int64_t)num_cus() * 8);
+    hipLaunchKernelGGL((k_finalize<U, false>), dim3(fgrid), dim3(256), 0, s, st, (U *)keys, (const U *)ws->keys0,
+                       (uint32_t *)nullptr, n);
+    AK_LAUNCH_CHECK("k_finalize");
+    return AK_OK;
+}
+
+ak_status code_partition(Workspace *ws, int dt, void *keys, uint32_t n, const float *model, int cb, int slot) {
+    switch (dt) {
+    case AK_I32: return code_partition_t<AK_I32>(ws, keys, n, model, cb, slot, nullptr);
+    case AK_I64: return code_partition_t<AK_I64>(ws, keys, n, model, cb, slot, nullptr);
+    case AK_U32: return code_partition_t<AK_U32>(ws, keys, n, model, cb, slot, nullptr);
+    case AK_U64: return code_partition_t<AK_U64>(ws, keys, n, model, cb, slot, nullptr);
+    case AK_F32: return code_partition_t<AK_F32>(ws, keys, n, model, cb, slot, nullptr);
+    case AK_F64: return code_partition_t<AK_F64>(ws, keys, n, model, cb, slot, nullptr);
+    }
+    return AK_ERR_UNSUPPORTED_DTYPE;
+}
+
+}  // namespace ak

@@ -1,0 +1,143 @@
+// Block-level building blocks of the radix kernels: exclusive scans and the
+// stable in-tile digit ranking (wave ballot match + per-wave LDS counters).
+#pragma once
+
+#include "ak_internal.h"
+
+namespace ak {
+
+// Barrier of a cooperating group of W waves.  A group of one wave (several
+// independent single-wave groups share a block) only needs its own LDS
+// accesses ordered: a wavefront fence and a wave barrier.
+template <int W>
+__device__ __forceinline__ void grp_sync() {
+    if constexpr (W == 1) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+// Exclusive scan of R counters held in LDS (`in`, may alias `out`) by the B
+// threads of a group (tid = thread index within the group).  s_wsum needs
+// B/64 words.  Ends with a group barrier.
+template <int B, int R>
+__device__ __forceinline__ void block_exscan(const uint32_t *in, uint32_t *out, uint32_t *s_wsum, int tid) {
+    constexpr int K = (R + B - 1) / B;
+    constexpr int W = B / 64;
+    const int lane = tid & 63, w = tid >> 6;
+    uint32_t v[K];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int idx = tid * K + k;
+        v[k] = idx < R ? in[idx] : 0u;
+        sum += v[k];
+    }
+    const uint32_t incl = wave_incl_scan(sum);
+    if (lane == 63) s_wsum[w] = incl;
+    grp_sync<W>();
+    uint32_t run = incl - sum;
+    for (int ww = 0; ww < w; ++ww) run += s_wsum[ww];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int idx = tid * K + k;
+        if (idx < R) out[idx] = run;
+        run += v[k];
+    }
+    grp_sync<W>();
+}
+
+// Tile layout used by every ranking kernel: "wave-striped".  Item j of lane
+// l in wave w is tile element w*64*IPT + j*64 + l, so each item is one
+// coalesced 64-lane access and processing items j = 0..IPT-1 in order walks
+// the wave's elements in input order (which makes the ranking stable).
+template <int IPT>
+__device__ __forceinline__ uint32_t striped_elem(int w, int j, int lane) {
+    return (uint32_t)(w * 64 * IPT + j * 64 + lane);
+}
+
+// Phase 1 of the stable ranking.  For every valid item, finds the lanes of
+// its wave holding the same digit (RB ballots), and gives the item its rank
+// among equal digits of earlier items of the wave.  Per-wave digit counters
+// live in s_cnt[w*R + d].  Afterwards (and a barrier), s_cnt holds, per
+// digit, the exclusive prefix over waves and s_tot the tile's digit totals.
+template <int RB, int W, int IPT, typename C = uint32_t>
+__device__ __forceinline__ void rank_match(const uint32_t (&dg)[IPT], uint32_t nvalid, uint32_t (&rk)[IPT],
+                                           C *s_cnt, uint32_t *s_tot, int tid) {
+    constexpr int R = 1 << RB;
+    constexpr int B = W * 64;
+    const int lane = tid & 63, w = tid >> 6;
+    for (int i = tid; i < W * R; i += B) s_cnt[i] = 0;
+    grp_sync<W>();
+    C *cnt = s_cnt + w * R;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const bool valid = striped_elem<IPT>(w, j, lane) < nvalid;
+        uint64_t peers = ballot64(valid);
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+            const bool bit = (dg[j] >> b) & 1u;
+            const uint64_t m = ballot64(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t below = count_below(peers);
+        const uint32_t c = cnt[dg[j]];
+        rk[j] = c + below;
+        if (valid && below == 0) cnt[dg[j]] = (C)(c + (uint32_t)__popcll(peers));
+    }
+    grp_sync<W>();
+    for (int d = tid; d < R; d += B) {
+        uint32_t run = 0;
+#pragma unroll
+        for (int ww = 0; ww < W; ++ww) {
+            const uint32_t c = s_cnt[ww * R + d];
+            s_cnt[ww * R + d] = (C)run;
+            run += c;
+        }
+        s_tot[d] = run;
+    }
+    grp_sync<W>();
+}
+
+// Phase 2: with s_start = exclusive scan of s_tot over digits, turns the
+// wave-local ranks into tile positions.
+template <int RB, int W, int IPT, typename C = uint32_t>
+__device__ __forceinline__ void rank_finish(const uint32_t (&dg)[IPT], uint32_t (&rk)[IPT], const C *s_cnt,
+                                            const uint32_t *s_start, int tid) {
+    constexpr int R = 1 << RB;
+    const int w = tid >> 6;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) rk[j] += s_start[dg[j]] + (uint32_t)s_cnt[w * R + dg[j]];
+}
+
+// OR and AND of a 64-bit value over the valid lanes of the block.
+template <int W>
+__device__ __forceinline__ void block_or_and(uint64_t vor, uint64_t vand, uint64_t *s_red, uint64_t &ror,
+                                             uint64_t &rand_, int tid) {
+    const int lane = tid & 63, w = tid >> 6;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint32_t olo = __shfl_xor((uint32_t)vor, d, 64), ohi = __shfl_xor((uint32_t)(vor >> 32), d, 64);
+        const uint32_t alo = __shfl_xor((uint32_t)vand, d, 64), ahi = __shfl_xor((uint32_t)(vand >> 32), d, 64);
+        vor |= ((uint64_t)ohi << 32) | olo;
+        vand &= ((uint64_t)ahi << 32) | alo;
+    }
+    if (lane == 0) {
+        s_red[w] = vor;
+        s_red[W + w] = vand;
+    }
+    grp_sync<W>();
+    ror = 0;
+    rand_ = ~0ull;
+#pragma unroll
+    for (int ww = 0; ww < W; ++ww) {
+        ror |= s_red[ww];
+        rand_ &= s_red[W + ww];
+    }
+    grp_sync<W>();
+}
+
+}  // namespace ak

@@ -1,0 +1,53 @@
+// Kernel argument blocks and launch shapes of the radix kernels.
+#pragma once
+
+#include "ak_internal.h"
+
+namespace ak {
+
+struct OnesweepArgs {
+    void *keys;           // sort: keys (in/out); sortperm: the const keys
+    void *t0, *t1;        // key scratch buffers
+    uint32_t *v0, *perm;  // value scratch, permutation output
+    uint64_t *lookback;   // tiles x RADIX look-back words
+    RunState *st;
+    const float *model;   // learned model (code digits only)
+    uint32_t n;
+    int place;
+    uint32_t epoch;
+    int cb;               // code bits (code digits only)
+};
+
+// One-sweep tile shapes (W waves x IPT keys per lane).  A few shapes are
+// compiled per (key width, with values); os_variant() picks one at run time
+// (default from the tuning sweep; $AK_OS_VARIANT overrides it).
+struct OsShape {
+    int w, ipt;
+};
+constexpr int OS_NVAR = 4;
+constexpr OsShape OS_SHAPES[2][2][OS_NVAR] = {
+    // 32-bit keys: keys only, with values
+    {{{8, 12}, {16, 8}, {16, 12}, {8, 16}}, {{8, 12}, {16, 8}, {16, 6}, {8, 8}}},
+    // 64-bit keys: keys only, with values
+    {{{8, 8}, {16, 4}, {16, 6}, {8, 12}}, {{8, 6}, {16, 4}, {8, 8}, {16, 6}}},
+};
+int os_variant(int dt, bool val);
+inline int os_tile(int dt, bool val) {
+    const OsShape s = OS_SHAPES[key_bits(dt) == 64][val][os_variant(dt, val)];
+    return s.w * 64 * s.ipt;
+}
+
+template <typename U, bool VAL, int W, int IPT>
+struct SmallSmem {
+    U keys[W * 64 * IPT];
+    uint32_t vals[VAL ? W * 64 * IPT : 1];
+    uint32_t cnt[W * RADIX];
+    uint32_t tot[RADIX];
+    uint32_t start[RADIX];
+    uint32_t wsum[W];
+    uint64_t red[2 * W];
+};
+
+ak_status code_partition(Workspace *ws, int dt, void *keys, uint32_t n, const float *model, int cb, int slot);
+
+}  // namespace ak

@@ -1,0 +1,103 @@
+"""GPU parity of ak_segmented_sort against the oracle's per-segment sort."""
+import zlib
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2507_16710_amd as ak
+import synth
+from gpucheck import fingerprint, signed_order_key, to_gpu, to_host
+from pools import DTYPES, bits, random_keys
+
+pytestmark = pytest.mark.gpu
+
+
+def _seg(k: np.ndarray, off: np.ndarray, dt: str) -> np.ndarray:
+    t = to_gpu(k, dt)
+    o = torch.from_numpy(off.astype(np.int64)).cuda()
+    ak.segmented_sort_(t, o, dtype=dt)
+    torch.cuda.synchronize()
+    return to_host(t, dt)
+
+
+def _offsets(lengths) -> np.ndarray:
+    return np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+def test_class_boundaries(dt):
+    """Lengths at and around the short / medium / long class limits (with
+    every tuning: 128/256 short, 2048/4096/8192 medium), empties and ones."""
+    rng = np.random.default_rng(zlib.crc32(dt.encode()))
+    lens = [0, 1, 2, 3, 63, 64, 65, 127, 128, 129, 255, 256, 257, 0, 2047, 2048, 2049,
+            4095, 4096, 4097, 8191, 8192, 8193, 12289, 70_001, 1, 0]
+    lens = lens + list(rng.integers(0, 600, size=200))
+    k = random_keys(dt, int(np.sum(lens)), rng, "mixed")
+    off = _offsets(lens)
+    assert np.array_equal(bits(_seg(k, off, dt)), bits(oracle.segsort(k, off)))
+
+
+@pytest.mark.parametrize("dt", ["u32", "f64", "i64"])
+def test_single_segment_equals_sort(dt):
+    rng = np.random.default_rng(3)
+    for n in [5, 4096, 100_000]:
+        k = random_keys(dt, n, rng, "mixed")
+        assert np.array_equal(bits(_seg(k, np.array([0, n]), dt)), bits(oracle.sort(k)))
+
+
+def test_outside_range_untouched_and_repeated_calls():
+    rng = np.random.default_rng(5)
+    k = random_keys("u32", 50_000, rng, "uniform")
+    off = np.array([1000, 1000, 5000, 20_000, 30_000], dtype=np.int64)
+    got = _seg(k, off, "u32")
+    assert np.array_equal(got[:1000], k[:1000]) and np.array_equal(got[30_000:], k[30_000:])
+    assert np.array_equal(got, oracle.segsort(k, off))
+    # replays of the captured graph with new pointers and new data
+    for seed in range(3):
+        k2 = random_keys("u32", 50_000, np.random.default_rng(100 + seed), "mixed")
+        assert np.array_equal(_seg(k2, off, "u32"), oracle.segsort(k2, off))
+
+
+def test_bad_offsets_reported():
+    k = torch.zeros(100, dtype=torch.int32, device="cuda")
+    off = torch.tensor([0, 50, 40, 100], dtype=torch.int64, device="cuda")
+    ak.segmented_sort_(k, off, dtype="u32")
+    with pytest.raises(ak.AKError):
+        ak.check_device_error()
+    ak.check_device_error()        # the flag was cleared
+    lib = ak.load_library()
+    assert lib.ak_segmented_sort(k.data_ptr(), off.data_ptr(), -1, 3, None) == 1
+    bad_end = torch.tensor([10, 5], dtype=torch.int64, device="cuda")
+    assert lib.ak_segmented_sort(k.data_ptr(), bad_end.data_ptr(), 1, 3, None) == 1
+
+
+def test_workload4_scaled():
+    """Lognormal segment sizes (clip [16, 2**20], mean 5000), uniform uint32
+    keys: 4,000 segments."""
+    keys, off = synth.workload4(nseg=4000, seed=2)
+    k = keys.numpy().view(np.uint32)
+    assert np.array_equal(_seg(k, off.numpy(), "u32"), oracle.segsort(k, off.numpy()))
+
+
+def test_workload4_full_size():
+    """100,000 segments, ~5e8 keys: every segment sorted (GPU check), the
+    multiset kept, and a sample of segments equal to the oracle's."""
+    keys, off = synth.workload4(device="cuda")
+    orig = keys.clone()
+    fp = fingerprint(keys)
+    ak.segmented_sort_(keys, off, dtype="u32")
+    torch.cuda.synchronize()
+    assert fingerprint(keys) == fp
+    k = signed_order_key(keys, "u32")
+    seg_id = torch.repeat_interleave(torch.arange(off.numel() - 1, device="cuda"), off[1:] - off[:-1])
+    same = seg_id[1:] == seg_id[:-1]
+    assert bool((k[1:][same] >= k[:-1][same]).all())
+    offh = off.cpu().numpy()
+    lens = np.diff(offh)
+    pick = list(np.argsort(lens)[-3:]) + list(np.random.default_rng(0).integers(0, lens.size, 50))
+    for s in pick:
+        a, b = int(offh[s]), int(offh[s + 1])
+        src = to_host(orig[a:b], "u32")
+        assert np.array_equal(to_host(keys[a:b], "u32"), oracle.sort(src)), s

@@ -1,0 +1,158 @@
+"""GPU parity of ak_sort / ak_sortperm against the oracle (bit-exact).
+
+Sizes cover the single-workgroup path (<= 4096 keys), several one-sweep tiles
+with ragged tails, and the workload shapes; full-size workloads are checked
+through sampled ranks and properties that hold at any size.
+"""
+import zlib
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2507_16710_amd as ak
+import synth
+from gpucheck import (check_perm_sorts_stably, fingerprint, is_sorted, rank_checks, to_gpu, to_host)
+from pools import DTYPES, bits, random_keys
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [1, 2, 3, 64, 1000, 4095, 4096, 4097, 3071, 3073, 12289, 65536 + 7, 300_001]
+
+
+def _run_sort(k: np.ndarray, dt: str) -> np.ndarray:
+    t = to_gpu(k, dt)
+    ak.sort_(t, dtype=dt)
+    torch.cuda.synchronize()
+    return to_host(t, dt)
+
+
+def _run_perm(k: np.ndarray, dt: str) -> np.ndarray:
+    t = to_gpu(k, dt)
+    before = to_host(t, dt).copy()
+    p = ak.sortperm(t, dtype=dt)
+    torch.cuda.synchronize()
+    assert np.array_equal(bits(to_host(t, dt)), bits(before)), "sortperm modified its keys"
+    return p.cpu().numpy().view(np.uint32)
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("kind", ["mixed", "uniform", "ties"])
+def test_sort_bit_exact(dt, kind):
+    rng = np.random.default_rng(zlib.crc32(f"{dt}{kind}s".encode()))
+    for n in SIZES:
+        k = random_keys(dt, n, rng, kind)
+        print(f"sort dt={dt} kind={kind} n={n}", flush=True)
+        got = _run_sort(k, dt)
+        assert np.array_equal(bits(got), bits(oracle.sort(k))), (dt, kind, n)
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("kind", ["mixed", "ties"])
+def test_sortperm_exact(dt, kind):
+    rng = np.random.default_rng(zlib.crc32(f"{dt}{kind}p".encode()))
+    for n in SIZES:
+        k = random_keys(dt, n, rng, kind)
+        print(f"sortperm dt={dt} kind={kind} n={n}", flush=True)
+        assert np.array_equal(_run_perm(k, dt), oracle.sortperm(k)), (dt, kind, n)
+
+
+@pytest.mark.parametrize("dt", ["i64", "f32", "u32"])
+def test_degenerate_inputs(dt):
+    rng = np.random.default_rng(1)
+    for n in [5000, 70_000]:
+        base = random_keys(dt, 3, rng, "uniform")
+        const = np.full(n, base[0])
+        assert np.array_equal(bits(_run_sort(const, dt)), bits(const))
+        assert np.array_equal(_run_perm(const, dt), np.arange(n, dtype=np.uint32))
+        srt = oracle.sort(random_keys(dt, n, rng, "mixed"))
+        assert np.array_equal(bits(_run_sort(srt, dt)), bits(srt))
+        rev = srt[::-1].copy()
+        assert np.array_equal(_run_perm(rev, dt), oracle.sortperm(rev))
+        # only the lowest byte varies: one active pass, odd count -> copy back
+        lowbyte = (np.arange(n) % 7).astype(np.int64).astype(bits(const).dtype).view(const.dtype)
+        assert np.array_equal(bits(_run_sort(lowbyte, dt)), bits(oracle.sort(lowbyte)))
+    # n == 0: nothing launched, no error
+    t = torch.empty(0, dtype=torch.int64, device="cuda")
+    ak.sort_(t, dtype="i64")
+    assert ak.sortperm(t, dtype="i64").numel() == 0
+
+
+def test_argument_errors():
+    t = torch.zeros(10, dtype=torch.int64, device="cuda")
+    lib = ak.load_library()
+    assert lib.ak_sort(t.data_ptr(), -1, 2, None) == 1
+    assert lib.ak_sort(None, 10, 2, None) == 1
+    assert lib.ak_sort(t.data_ptr(), 10, 99, None) == 2
+    assert lib.ak_sort(t.data_ptr(), 1 << 32, 2, None) == 1
+    assert lib.ak_sortperm(t.data_ptr(), t.data_ptr(), 10, 2, None) == 1     # overlap
+    assert lib.ak_sortperm(t.data_ptr(), None, 10, 2, None) == 1
+    assert lib.ak_sort(t.data_ptr(), 0, 2, None) == 0
+    with pytest.raises(ak.AKError):
+        ak._check(lib.ak_sort(t.data_ptr(), -5, 2, None), "ak_sort")
+    with pytest.raises(TypeError):
+        ak.sort_(t, dtype="f32")         # 8-byte elements declared as f32
+
+
+def test_workload1_full():
+    """1,000,000 uniform int64 keys: sort and sortperm, full size."""
+    k = synth.as_numpy(synth.workload1(), "i64")
+    assert np.array_equal(_run_sort(k, "i64"), oracle.sort(k))
+    assert np.array_equal(_run_perm(k, "i64"), oracle.sortperm(k))
+
+
+def test_workload2_scaled():
+    """float32 N(0,1e3) with NaN / signed zero / Inf injections, 2**22 keys."""
+    k = synth.as_numpy(synth.workload2(n=1 << 22), "f32")
+    assert np.array_equal(bits(_run_sort(k, "f32")), bits(oracle.sort(k)))
+    assert np.array_equal(_run_perm(k, "f32"), oracle.sortperm(k))
+
+
+@pytest.mark.parametrize("variant", ["uniform", "zipf", "lognormal"])
+def test_workload3_scaled(variant):
+    k = synth.as_numpy(synth.workload3(variant, n=1 << 22), "i64")
+    assert np.array_equal(_run_sort(k, "i64"), oracle.sort(k))
+    assert np.array_equal(_run_perm(k, "i64"), oracle.sortperm(k))
+
+
+def test_workload2_full_size_properties():
+    """2**28 float32 keys with specials, in the benchmark's launch shape."""
+    t = synth.workload2(device="cuda")
+    fp = fingerprint(t)
+    keys = t.clone()
+    perm = ak.sortperm(keys, dtype="f32")
+    ak.sort_(t, dtype="f32")
+    torch.cuda.synchronize()
+    assert is_sorted(t, "f32") and fingerprint(t) == fp
+    assert torch.equal(torch.isnan(t[-(t.numel() // 1000):]).all(), torch.tensor(True, device="cuda"))
+    check_perm_sorts_stably(keys, perm, "f32")
+    assert torch.equal(keys[perm.to(torch.int64) & 0xFFFFFFFF].view(torch.int32), t.view(torch.int32))
+    rank_checks(keys, t, "f32", samples=16)
+
+
+@pytest.mark.parametrize("variant", ["uniform", "zipf", "lognormal"])
+def test_workload3_full_size_properties(variant):
+    """One GPU's share: 2**30 int64 keys (8 GiB)."""
+    t = synth.workload3(variant, device="cuda")
+    keys = t.clone()
+    fp = fingerprint(t)
+    ak.sort_(t, dtype="i64")
+    torch.cuda.synchronize()
+    assert is_sorted(t, "i64") and fingerprint(t) == fp
+    rank_checks(keys, t, "i64", samples=8)
+    # the sorted sample equals the oracle's sort of the same sample
+    idx = torch.arange(0, keys.numel(), 4099, device="cuda")
+    sub = to_host(keys[idx], "i64")
+    del keys
+    t2 = to_gpu(sub, "i64")
+    ak.sort_(t2, dtype="i64")
+    assert np.array_equal(to_host(t2, "i64"), oracle.sort(sub))
+
+
+def test_repeat_determinism():
+    rng = np.random.default_rng(4)
+    k = random_keys("f32", 200_000, rng, "mixed")
+    first = _run_perm(k, "f32")
+    for _ in range(5):
+        assert np.array_equal(_run_perm(k, "f32"), first)
