@@ -101,6 +101,18 @@ ak_status ak_segmented_sort_u64(uint64_t *keys, const int64_t *offsets, int64_t 
 ak_status ak_segmented_sort_f32(float *keys, const int64_t *offsets, int64_t nseg, ak_stream_t s);
 ak_status ak_segmented_sort_f64(double *keys, const int64_t *offsets, int64_t nseg, ak_stream_t s);
 
+/* Tuning of the segmented sort for 32- or 64-bit keys (what the autotuner
+ * writes to tune_gfx950.json next to libak.so, or $AK_TUNE_TABLE):
+ *   ipt_a      keys per lane of the one-wave class (2 or 4: 128 / 256 keys)
+ *   ipt_b      keys per lane of the one-workgroup class and of the long
+ *              class's tiles (8 or 16; 32 too for 32-bit keys)
+ *   grid_mult  persistent workgroups per compute unit (1..16)
+ *   b_max      longest segment sorted on chip (0: the class capacity)
+ *   xl_min     shortest segment sorted by many workgroups (>= 4096)
+ * Takes effect for later calls (a new graph is captured).  AK_ERR_INVALID_ARG
+ * for values outside those sets. */
+ak_status ak_seg_set_tuning(int key_bits, int ipt_a, int ipt_b, int grid_mult, int b_max, int xl_min);
+
 /* Synchronises `stream`, then returns AK_ERR_INVALID_ARG if a kernel on it
  * found invalid input (decreasing segment offsets) since the last check,
  * and clears the flag; otherwise AK_OK. */
@@ -197,6 +209,15 @@ size_t ak_temp_bytes(ak_op op, int64_t n, ak_dtype dtype);
 
 /* Synchronises the device and frees every workspace and cached graph. */
 ak_status ak_release_workspace(void);
+
+/* ------------------------------------------------------------ profiling
+ * While enabled, every library kernel launch is bracketed by HIP events
+ * recorded on the stream it is launched on (a few microseconds per launch).
+ * ak_profile_read waits for the recorded launches, writes one line
+ * "kernel_name count total_ms" per kernel into buf (len bytes, always
+ * NUL-terminated), clears the records and returns the bytes it needed. */
+ak_status ak_profile_enable(int on);
+size_t ak_profile_read(char *buf, size_t len);
 
 const char *ak_status_string(ak_status s);
 /* Detail of the last error on the calling thread ("" if none). */

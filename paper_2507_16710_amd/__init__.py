@@ -96,6 +96,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ak_temp_bytes.restype = ctypes.c_size_t
     lib.ak_rmi_model_floats.argtypes = [i32]
     lib.ak_rmi_model_floats.restype = ctypes.c_size_t
+    lib.ak_profile_enable.argtypes = [i32]
+    lib.ak_profile_enable.restype = i32
+    lib.ak_profile_read.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+    lib.ak_profile_read.restype = ctypes.c_size_t
+    lib.ak_seg_set_tuning.argtypes = [i32, i32, i32, i32, i32, i32]
+    lib.ak_seg_set_tuning.restype = i32
     lib.ak_last_error.restype = ctypes.c_char_p
     lib.ak_status_string.argtypes = [i32]
     lib.ak_status_string.restype = ctypes.c_char_p
@@ -240,6 +246,31 @@ def rmi_codes(keys: torch.Tensor, model: torch.Tensor, code_bits: int, dtype: st
         _check(load_library().ak_rmi_codes(keys.data_ptr(), keys.numel(), DTYPE_CODE[dt], model.data_ptr(),
                                            code_bits, out.data_ptr(), _stream(keys)), "ak_rmi_codes")
     return out
+
+
+def profile_enable(on: bool = True) -> None:
+    """Start / stop per-kernel event timing inside the library."""
+    _check(load_library().ak_profile_enable(int(on)), "ak_profile_enable")
+
+
+def profile_read() -> dict:
+    """{kernel name: (launches, total ms)} since the last read."""
+    lib = load_library()
+    need = lib.ak_profile_read(None, 0)
+    buf = ctypes.create_string_buffer(int(need) + 64)
+    lib.ak_profile_read(buf, len(buf))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, cnt, ms = line.split()
+        out[name] = (int(cnt), float(ms))
+    return out
+
+
+def seg_set_tuning(key_bits: int, ipt_a: int, ipt_b: int, grid_mult: int = 4, b_max: int = 0,
+                   xl_min: int = 32768) -> None:
+    """Override the segmented-sort tuning for 32- or 64-bit keys."""
+    _check(load_library().ak_seg_set_tuning(key_bits, ipt_a, ipt_b, grid_mult, b_max, xl_min),
+           "ak_seg_set_tuning")
 
 
 def temp_bytes(op: str, n: int, dtype: str) -> int:

@@ -64,12 +64,14 @@ Workspace *get_workspace(hipStream_t stream) {
     Workspace *ws = new Workspace();
     ws->device = dev;
     ws->stream = stream;
-    if (hipMalloc((void **)&ws->state, sizeof(RunState) * RUN_SLOTS) != hipSuccess) {
+    const size_t state_bytes = sizeof(RunState) * RUN_SLOTS + 256;
+    if (hipMalloc((void **)&ws->state, state_bytes) != hipSuccess) {
         set_error("hipMalloc(run state) failed");
         delete ws;
         return nullptr;
     }
-    if (zero_fill(stream, ws->state, sizeof(RunState) * RUN_SLOTS) != AK_OK ||
+    ws->epoch_dev = reinterpret_cast<uint32_t *>(ws->state + RUN_SLOTS);
+    if (zero_fill(stream, ws->state, state_bytes) != AK_OK ||
         hipStreamSynchronize(stream) != hipSuccess) {
         (void)hipFree(ws->state);
         delete ws;
@@ -98,6 +100,7 @@ ak_status ws_reserve(Workspace *ws, void **p, size_t *have, size_t need) {
         return AK_ERR_NO_MEMORY;
     }
     *have = sz;
+    ++ws->gen;
     return AK_OK;
 }
 
@@ -109,29 +112,38 @@ ak_status ws_reserve_lookback(Workspace *ws, size_t need) {
     if (r != AK_OK) return r;
     ws->lookback = (uint64_t *)p;
     ws->lookback_bytes = have;
-    ws->epoch = 0;
     return zero_fill(ws->stream, ws->lookback, ws->lookback_bytes);
 }
 
-// Each run takes 16 consecutive epochs (one per pass).  Epochs are 30-bit;
-// before they would wrap, the look-back words are cleared and numbering
-// restarts, so a word left by an earlier run never matches.
+// Each run takes 16 consecutive epochs (one per pass), handed out on the
+// device by k_run_init from a counter this function mirrors.  Epochs are
+// 30-bit; before they would wrap, the look-back words are cleared and both
+// counters restart at 16, so a word left by an earlier run never matches.
 ak_status ws_next_epoch(Workspace *ws, uint32_t *epoch) {
-    if (ws->epoch + 32 >= (1u << 30)) {
+    uint32_t e = ws->epoch + 16;
+    if (e + 16 >= (1u << 30)) {
         ak_status r = zero_fill(ws->stream, ws->lookback, ws->lookback_bytes);
         if (r != AK_OK) return r;
-        ws->epoch = 0;
+        e = 16;
     }
-    ws->epoch += 16;
-    *epoch = ws->epoch;
+    ws->epoch = e;
+    *epoch = e;
     return AK_OK;
+}
+
+bool stream_capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+    return st == hipStreamCaptureStatusActive;
 }
 
 uint32_t segmented_take_error(Workspace *ws);
 void segmented_release(Workspace *ws);
+void radix_release(Workspace *ws);
 
 static void free_ws(Workspace *ws) {
     segmented_release(ws);
+    radix_release(ws);
     void *bufs[] = {ws->keys0, ws->keys1, ws->vals0, ws->lookback, ws->state, ws->misc, ws->misc2};
     for (void *b : bufs)
         if (b) (void)hipFree(b);

@@ -114,6 +114,8 @@ struct RunState {
     PassDesc desc[MAX_PLACES];
     int32_t q;                         // number of active passes
     uint32_t error;                    // device-detected input error flag
+    uint32_t epoch_base;               // look-back epoch of this run's first pass
+    uint32_t hist_done;                // histogram workgroups finished
 };
 
 // ------------------------------------------------------------- errors
@@ -130,6 +132,19 @@ ak_status hip_fail(hipError_t e, const char *what);
         if (e_ != hipSuccess) return hip_fail(e_, what);      \
     } while (0)
 
+// ------------------------------------------------------------ profiling
+// RAII bracket of one launch; records events only while profiling is on.
+class ProfScope {
+  public:
+    ProfScope(const char *name, hipStream_t s);
+    ~ProfScope();
+
+  private:
+    const char *name_;
+    hipStream_t s_;
+    void *a_ = nullptr, *b_ = nullptr;
+};
+
 // ------------------------------------------------------------ workspace
 // Per (device, stream) scratch.  Regions are grown independently; the
 // look-back region is zero-filled when (re)allocated and then relies on
@@ -142,6 +157,8 @@ struct Workspace {
     void *vals0 = nullptr; size_t vals0_bytes = 0;
     uint64_t *lookback = nullptr; size_t lookback_bytes = 0;
     RunState *state = nullptr;      // several run states (sample sort, main run)
+    uint32_t *epoch_dev = nullptr;  // device copy of `epoch` (advanced by k_run_init)
+    uint32_t gen = 0;               // bumped whenever a buffer is reallocated
     void *misc = nullptr; size_t misc_bytes = 0;   // learned / segmented scratch
     void *misc2 = nullptr; size_t misc2_bytes = 0;
     void *aux[6] = {nullptr}; size_t aux_bytes[6] = {0};     // learned-sort scratch
@@ -151,8 +168,11 @@ struct Workspace {
 Workspace *get_workspace(hipStream_t stream);
 ak_status ws_reserve(Workspace *ws, void **p, size_t *have, size_t need);
 ak_status ws_reserve_lookback(Workspace *ws, size_t need);
-// epoch base for a run of up to 16 passes (clears the look-back region on wrap)
+// Mirrors the device's epoch advance of one run (16 epochs per run; both
+// restart at 16 before 2^30) and clears the look-back words when it wraps.
 ak_status ws_next_epoch(Workspace *ws, uint32_t *epoch);
+// true while `s` is being captured into a graph
+bool stream_capturing(hipStream_t s);
 
 int num_cus();
 

@@ -595,6 +595,7 @@ static ak_status learned_t(Workspace *ws, void *keys, int64_t n64, const ak_lear
     const uint32_t pieces_target = (uint32_t)num_cus() * 16;
     uint32_t piece = std::max<uint32_t>((uint32_t)CAP * 4, (n + pieces_target - 1) / pieces_target);
     const uint32_t npieces = (n + piece - 1) / piece;
+    ProfScope ps_chunk("chunk_sort", s);
     hipLaunchKernelGGL((k_chunk_sort<DT, CW, CIPT>), dim3(npieces), dim3(CW * 64), 0, s, (U *)keys, n,
                        (const float *)model, cb, piece, fb, ls);
     AK_LAUNCH_CHECK("k_chunk_sort");

@@ -12,6 +12,8 @@
 // sort needs, Sec. I-B), and the prefix scan uses the look-back scheme the
 // paper cites for its accumulate (Sec. II-B, "opportunistic look-back").
 #include <cstdlib>
+#include <map>
+#include <mutex>
 
 #include "radix_common.h"
 #include "radix_kernels.h"
@@ -21,10 +23,54 @@
 namespace ak {
 
 // ---------------------------------------------------------------- init
-__global__ void k_run_init(RunState *st) {
+// Zeroes the run's counters and takes the next 16 look-back epochs from the
+// workspace counter (restarting at 16 before 2^30; the host mirrors this and
+// clears the look-back words at that point).
+__global__ void k_run_init(RunState *st, uint32_t *epoch_dev) {
     const int tid = threadIdx.x;
     for (int i = tid; i < MAX_PLACES * RADIX; i += blockDim.x) (&st->hist[0][0])[i] = 0;
     if (tid < MAX_PLACES) st->tile_ctr[tid] = 0;
+    if (tid == 0) {
+        st->hist_done = 0;
+        uint32_t e = *epoch_dev + 16;
+        if (e + 16 >= (1u << 30)) e = 16;
+        *epoch_dev = e;
+        st->epoch_base = e;
+    }
+}
+
+// Exclusive digit offsets per place; a place where one digit holds every
+// key is inactive (its pass would be a copy).  Active passes are numbered
+// so that each pass kernel can pick its source and destination buffers
+// without a host round trip.  Run by one workgroup of 256 threads, reading
+// counts that other workgroups accumulated with device-scope atomics.
+__device__ void scan_places(RunState *st, uint32_t n, int nplaces, uint32_t *s_buf, uint32_t *s_wsum,
+                            int *s_active) {
+    const int tid = threadIdx.x;
+    for (int p = 0; p < nplaces; ++p) {
+        const uint32_t c = __hip_atomic_load(&st->hist[p][tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int trivial = __syncthreads_or(c == n);
+        s_buf[tid] = c;
+        __syncthreads();
+        block_exscan<256, RADIX>(s_buf, s_buf, s_wsum, tid);
+        st->base[p][tid] = s_buf[tid];
+        if (tid == 0) s_active[p] = !trivial;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        int q = 0;
+        for (int p = 0; p < nplaces; ++p) q += s_active[p];
+        int j = 0;
+        for (int p = 0; p < MAX_PLACES; ++p) {
+            PassDesc d;
+            d.active = p < nplaces ? s_active[p] : 0;
+            d.j = d.active ? j++ : -1;
+            d.q = q;
+            d.shift = p * RADIX_BITS;
+            st->desc[p] = d;
+        }
+        st->q = q;
+    }
 }
 
 // ---------------------------------------------------------- histogram
@@ -79,42 +125,17 @@ __global__ __launch_bounds__(256) void k_hist(const typename KT<DT>::U *__restri
     __syncthreads();
     for (int i = tid; i < nplaces * RADIX; i += B)
         if (s_h[i]) atomicAdd(&st->hist[i / RADIX][i % RADIX], s_h[i]);
-}
-
-// --------------------------------------------------------- digit scan
-// Exclusive digit offsets per place; a place where one digit holds every
-// key is inactive (its pass would be a copy).  Active passes are numbered
-// so that each pass kernel can pick its source and destination buffers
-// without a host round trip.
-__global__ __launch_bounds__(256) void k_scan(RunState *st, uint32_t n, int nplaces) {
+    // the last workgroup to finish turns the counts into digit offsets
+    __shared__ int s_last;
     __shared__ uint32_t s_wsum[4];
-    __shared__ uint32_t s_buf[RADIX];
     __shared__ int s_active[MAX_PLACES];
-    const int tid = threadIdx.x;
-    for (int p = 0; p < nplaces; ++p) {
-        const uint32_t c = st->hist[p][tid];
-        const int trivial = __syncthreads_or(c == n);
-        s_buf[tid] = c;
-        __syncthreads();
-        block_exscan<256, RADIX>(s_buf, s_buf, s_wsum, tid);
-        st->base[p][tid] = s_buf[tid];
-        if (tid == 0) s_active[p] = !trivial;
-        __syncthreads();
-    }
-    if (tid == 0) {
-        int q = 0;
-        for (int p = 0; p < nplaces; ++p) q += s_active[p];
-        int j = 0;
-        for (int p = 0; p < MAX_PLACES; ++p) {
-            PassDesc d;
-            d.active = p < nplaces ? s_active[p] : 0;
-            d.j = d.active ? j++ : -1;
-            d.q = q;
-            d.shift = p * RADIX_BITS;
-            st->desc[p] = d;
-        }
-        st->q = q;
-    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) s_last = atomicAdd(&st->hist_done, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    scan_places(st, n, nplaces, s_h, s_wsum, s_active);
 }
 
 // ----------------------------------------------------- one-sweep pass
@@ -218,7 +239,7 @@ __global__ __launch_bounds__(W * 64) void k_onesweep(OnesweepArgs a) {
 
     // publish this tile's digit counts first, so successors can look back
     uint64_t *lb = a.lookback + (size_t)tile * RADIX;
-    const uint32_t epoch = a.epoch;
+    const uint32_t epoch = a.st->epoch_base + (uint32_t)a.place;
     for (int d = tid; d < RADIX; d += B)
         lb_store(lb + d, lb_pack(epoch, tile == 0 ? LB_INC : LB_AGG, s_tot[d]));
 
@@ -353,8 +374,8 @@ static void launch_pass_v(hipStream_t s, uint32_t tiles, const OnesweepArgs &a) 
 }
 
 template <int DT, bool VAL, bool CODE>
-static ak_status launch_passes(Workspace *ws, RunState *st, const void *keys_in, void *t0, void *t1, uint32_t *v0,
-                               uint32_t *perm, uint32_t n, int nplaces, uint32_t epoch, const float *model, int cb) {
+static ak_status launch_passes(hipStream_t stream, Workspace *ws, RunState *st, const void *keys_in, void *t0, void *t1,
+                               uint32_t *v0, uint32_t *perm, uint32_t n, int nplaces, const float *model, int cb) {
     const int var = os_variant(DT, VAL);
     const int TILE = os_tile(DT, VAL);
     const uint32_t tiles = (n + TILE - 1) / TILE;
@@ -371,16 +392,92 @@ static ak_status launch_passes(Workspace *ws, RunState *st, const void *keys_in,
     a.cb = cb;
     for (int p = 0; p < nplaces; ++p) {
         a.place = p;
-        a.epoch = epoch + (uint32_t)p;
+        ProfScope ps(CODE ? "onesweep_code_pass" : (VAL ? "onesweep_pair_pass" : "onesweep_pass"), stream);
         switch (var) {
-        case 0: launch_pass_v<DT, VAL, CODE, 0>(ws->stream, tiles, a); break;
-        case 1: launch_pass_v<DT, VAL, CODE, 1>(ws->stream, tiles, a); break;
-        case 2: launch_pass_v<DT, VAL, CODE, 2>(ws->stream, tiles, a); break;
-        default: launch_pass_v<DT, VAL, CODE, 3>(ws->stream, tiles, a); break;
+        case 0: launch_pass_v<DT, VAL, CODE, 0>(stream, tiles, a); break;
+        case 1: launch_pass_v<DT, VAL, CODE, 1>(stream, tiles, a); break;
+        case 2: launch_pass_v<DT, VAL, CODE, 2>(stream, tiles, a); break;
+        default: launch_pass_v<DT, VAL, CODE, 3>(stream, tiles, a); break;
         }
         AK_LAUNCH_CHECK("k_onesweep");
     }
     return AK_OK;
+}
+
+// The whole multi-workgroup run: init (epochs, counters), histogram with
+// the digit scan fused into its last workgroup, one pass per place (inactive
+// ones exit at once), and the device-decided copy-back / identity.
+template <int DT, bool CODE>
+static ak_status launch_run(hipStream_t s, Workspace *ws, RunState *st, void *keys, uint32_t *perm, uint32_t n,
+                            int nplaces, const float *model, int cb) {
+    using U = typename KT<DT>::U;
+    const bool pm = perm != nullptr;
+    hipLaunchKernelGGL(k_run_init, dim3(1), dim3(256), 0, s, st, ws->epoch_dev);
+    AK_LAUNCH_CHECK("k_run_init");
+    const uint32_t hgrid = (uint32_t)std::min<int64_t>(((int64_t)n + 2047) / 2048, (int64_t)num_cus() * 8);
+    {
+        ProfScope ps(CODE ? "code_hist" : "digit_hist", s);
+        hipLaunchKernelGGL((k_hist<DT, CODE>), dim3(hgrid), dim3(256), 0, s, (const U *)keys, n, nplaces, st, model,
+                           cb);
+    }
+    AK_LAUNCH_CHECK("k_hist");
+    ak_status r;
+    if (pm)
+        r = launch_passes<DT, true, CODE>(s, ws, st, keys, ws->keys0, ws->keys1, (uint32_t *)ws->vals0, perm, n,
+                                          nplaces, model, cb);
+    else
+        r = launch_passes<DT, false, CODE>(s, ws, st, keys, ws->keys0, nullptr, nullptr, nullptr, n, nplaces, model,
+                                           cb);
+    if (r != AK_OK) return r;
+    const uint32_t fgrid = (uint32_t)std::min<int64_t>(((int64_t)n + 1023) / 1024, (int64_t)num_cus() * 8);
+    if (pm)
+        hipLaunchKernelGGL((k_finalize<U, true>), dim3(fgrid), dim3(256), 0, s, st, (U *)nullptr, (const U *)nullptr,
+                           perm, n);
+    else
+        hipLaunchKernelGGL((k_finalize<U, false>), dim3(fgrid), dim3(256), 0, s, st, (U *)keys,
+                           (const U *)ws->keys0, (uint32_t *)nullptr, n);
+    AK_LAUNCH_CHECK("k_finalize");
+    return AK_OK;
+}
+
+// ------------------------------------------------------- graph replay
+// Runs of up to GRAPH_MAX keys are latency-bound (about p+3 launches of a
+// few microseconds of work each), so their launch sequence is captured once
+// per (dtype, mode, n, pointers, workspace generation) and replayed.
+// Epochs come from the device counter, so replays never meet stale words.
+constexpr int64_t GRAPH_MAX = int64_t(1) << 22;
+
+struct GraphKey {
+    int dt;
+    int slot;
+    uint32_t n;
+    const void *keys;
+    const void *perm;
+    uint32_t gen;
+    bool operator<(const GraphKey &o) const {
+        if (dt != o.dt) return dt < o.dt;
+        if (slot != o.slot) return slot < o.slot;
+        if (n != o.n) return n < o.n;
+        if (keys != o.keys) return keys < o.keys;
+        if (perm != o.perm) return perm < o.perm;
+        return gen < o.gen;
+    }
+};
+struct GraphCache {
+    hipStream_t capture = nullptr;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+};
+static std::mutex g_graph_mu;
+static std::map<Workspace *, GraphCache> g_graphs;
+constexpr size_t GRAPH_CACHE_MAX = 64;
+
+void radix_release(Workspace *ws) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(ws);
+    if (it == g_graphs.end()) return;
+    for (auto &kv : it->second.graphs) (void)hipGraphExecDestroy(kv.second);
+    if (it->second.capture) (void)hipStreamDestroy(it->second.capture);
+    g_graphs.erase(it);
 }
 
 template <int DT>
@@ -413,30 +510,35 @@ static ak_status radix_sort_t(Workspace *ws, void *keys, uint32_t *perm, int64_t
     if ((r = ws_next_epoch(ws, &epoch)) != AK_OK) return r;
     RunState *st = ws->state + slot;
     const int nplaces = (int)(sizeof(U) * 8 / RADIX_BITS);
+    if (n64 > GRAPH_MAX || stream_capturing(s)) return launch_run<DT, false>(s, ws, st, keys, perm, n, nplaces, nullptr, 0);
 
-    hipLaunchKernelGGL(k_run_init, dim3(1), dim3(256), 0, s, st);
-    AK_LAUNCH_CHECK("k_run_init");
-    const uint32_t hgrid = (uint32_t)std::min<int64_t>((n64 + 2047) / 2048, (int64_t)num_cus() * 8);
-    hipLaunchKernelGGL((k_hist<DT, false>), dim3(hgrid), dim3(256), 0, s, (const U *)keys, n, nplaces, st,
-                       (const float *)nullptr, 0);
-    AK_LAUNCH_CHECK("k_hist");
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(256), 0, s, st, n, nplaces);
-    AK_LAUNCH_CHECK("k_scan");
-    if (pm)
-        r = launch_passes<DT, true, false>(ws, st, keys, ws->keys0, ws->keys1, (uint32_t *)ws->vals0, perm, n,
-                                           nplaces, epoch, nullptr, 0);
-    else
-        r = launch_passes<DT, false, false>(ws, st, keys, ws->keys0, nullptr, nullptr, nullptr, n, nplaces, epoch,
-                                            nullptr, 0);
-    if (r != AK_OK) return r;
-    const uint32_t fgrid = (uint32_t)std::min<int64_t>((n64 + 1023) / 1024, (int64_t)num_cus() * 8);
-    if (pm)
-        hipLaunchKernelGGL((k_finalize<U, true>), dim3(fgrid), dim3(256), 0, s, st, (U *)nullptr,
-                           (const U *)nullptr, perm, n);
-    else
-        hipLaunchKernelGGL((k_finalize<U, false>), dim3(fgrid), dim3(256), 0, s, st, (U *)keys,
-                           (const U *)ws->keys0, (uint32_t *)nullptr, n);
-    AK_LAUNCH_CHECK("k_finalize");
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    GraphCache &c = g_graphs[ws];
+    if (!c.capture) AK_HIP(hipStreamCreateWithFlags(&c.capture, hipStreamNonBlocking));
+    const GraphKey key{DT, slot, n, keys, perm, ws->gen};
+    auto it = c.graphs.find(key);
+    if (it == c.graphs.end()) {
+        if (c.graphs.size() >= GRAPH_CACHE_MAX) {
+            for (auto &kv : c.graphs) (void)hipGraphExecDestroy(kv.second);
+            c.graphs.clear();
+        }
+        hipGraph_t g = nullptr;
+        AK_HIP(hipStreamBeginCapture(c.capture, hipStreamCaptureModeRelaxed));
+        ak_status lr = launch_run<DT, false>(c.capture, ws, st, keys, perm, n, nplaces, nullptr, 0);
+        hipError_t ce = hipStreamEndCapture(c.capture, &g);
+        if (lr != AK_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return lr;
+        }
+        if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+        hipGraphExec_t ex = nullptr;
+        hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) return hip_fail(ie, "hipGraphInstantiate");
+        it = c.graphs.emplace(key, ex).first;
+    }
+    ProfScope ps("radix_graph", s);
+    AK_HIP(hipGraphLaunch(it->second, s));
     return AK_OK;
 }
 
@@ -458,11 +560,8 @@ ak_status radix_sort(Workspace *ws, int dt, void *keys, uint32_t *perm, int64_t 
 // after ceil(cb/8) passes the keys are ordered by code, equal codes in
 // input order.
 template <int DT>
-static ak_status code_partition_t(Workspace *ws, void *keys, uint32_t n, const float *model, int cb, int slot,
-                                  uint32_t *q_host_unused) {
-    (void)q_host_unused;
+static ak_status code_partition_t(Workspace *ws, void *keys, uint32_t n, const float *model, int cb, int slot) {
     using U = typename KT<DT>::U;
-    hipStream_t s = ws->stream;
     ak_status r;
     if ((r = ws_reserve(ws, &ws->keys0, &ws->keys0_bytes, (size_t)n * sizeof(U))) != AK_OK) return r;
     const int TILE = tile_keys(DT, false);
@@ -470,33 +569,18 @@ static ak_status code_partition_t(Workspace *ws, void *keys, uint32_t n, const f
     if ((r = ws_reserve_lookback(ws, tiles * RADIX * 8)) != AK_OK) return r;
     uint32_t epoch;
     if ((r = ws_next_epoch(ws, &epoch)) != AK_OK) return r;
-    RunState *st = ws->state + slot;
     const int nplaces = (cb + RADIX_BITS - 1) / RADIX_BITS;
-    hipLaunchKernelGGL(k_run_init, dim3(1), dim3(256), 0, s, st);
-    AK_LAUNCH_CHECK("k_run_init");
-    const uint32_t hgrid = (uint32_t)std::min<int64_t>(((int64_t)n + 2047) / 2048, (int64_t)num_cus() * 8);
-    hipLaunchKernelGGL((k_hist<DT, true>), dim3(hgrid), dim3(256), 0, s, (const U *)keys, n, nplaces, st, model, cb);
-    AK_LAUNCH_CHECK("k_hist(code)");
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(256), 0, s, st, n, nplaces);
-    AK_LAUNCH_CHECK("k_scan");
-    if ((r = launch_passes<DT, false, true>(ws, st, keys, ws->keys0, nullptr, nullptr, nullptr, n, nplaces, epoch,
-                                            model, cb)) != AK_OK)
-        return r;
-    const uint32_t fgrid = (uint32_t)std::min<int64_t>(((int64_t)n + 1023) / 1024, (int64_t)num_cus() * 8);
-    hipLaunchKernelGGL((k_finalize<U, false>), dim3(fgrid), dim3(256), 0, s, st, (U *)keys, (const U *)ws->keys0,
-                       (uint32_t *)nullptr, n);
-    AK_LAUNCH_CHECK("k_finalize");
-    return AK_OK;
+    return launch_run<DT, true>(ws->stream, ws, ws->state + slot, keys, nullptr, n, nplaces, model, cb);
 }
 
 ak_status code_partition(Workspace *ws, int dt, void *keys, uint32_t n, const float *model, int cb, int slot) {
     switch (dt) {
-    case AK_I32: return code_partition_t<AK_I32>(ws, keys, n, model, cb, slot, nullptr);
-    case AK_I64: return code_partition_t<AK_I64>(ws, keys, n, model, cb, slot, nullptr);
-    case AK_U32: return code_partition_t<AK_U32>(ws, keys, n, model, cb, slot, nullptr);
-    case AK_U64: return code_partition_t<AK_U64>(ws, keys, n, model, cb, slot, nullptr);
-    case AK_F32: return code_partition_t<AK_F32>(ws, keys, n, model, cb, slot, nullptr);
-    case AK_F64: return code_partition_t<AK_F64>(ws, keys, n, model, cb, slot, nullptr);
+    case AK_I32: return code_partition_t<AK_I32>(ws, keys, n, model, cb, slot);
+    case AK_I64: return code_partition_t<AK_I64>(ws, keys, n, model, cb, slot);
+    case AK_U32: return code_partition_t<AK_U32>(ws, keys, n, model, cb, slot);
+    case AK_U64: return code_partition_t<AK_U64>(ws, keys, n, model, cb, slot);
+    case AK_F32: return code_partition_t<AK_F32>(ws, keys, n, model, cb, slot);
+    case AK_F64: return code_partition_t<AK_F64>(ws, keys, n, model, cb, slot);
     }
     return AK_ERR_UNSUPPORTED_DTYPE;
 }

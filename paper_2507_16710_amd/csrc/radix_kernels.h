@@ -14,7 +14,6 @@ struct OnesweepArgs {
     const float *model;   // learned model (code digits only)
     uint32_t n;
     int place;
-    uint32_t epoch;
     int cb;               // code bits (code digits only)
 };
 

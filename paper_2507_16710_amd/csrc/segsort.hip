@@ -2,7 +2,11 @@
 // all segments in one persistent launch.
 //
 // Segments are binned by length into work buckets processed largest first:
-//   long   (> b_max keys)         one workgroup, multi-pass LSD radix through
+//   huge   (>= xl_min keys)       many workgroups: per-segment digit
+//                                 histograms, then one-sweep passes whose
+//                                 look-back stays inside the segment (tiles of
+//                                 all huge segments share persistent grids)
+//   long   (b_max < len < xl_min) one workgroup, multi-pass LSD radix through
 //                                 a scratch copy (one bucket per power of two,
 //                                 longest first, so the tail is short ones)
 //   medium (a_max < len <= b_max) one workgroup, on-chip sort
@@ -29,10 +33,21 @@
 namespace ak {
 
 constexpr int SEG_W = 4;              // waves of a persistent workgroup
-constexpr int NB_LONG = 24;           // long buckets: 31 - floor(log2(len))
-constexpr int B_MED = NB_LONG;        // medium bucket
-constexpr int B_SHORT = NB_LONG + 1;  // short bucket
-constexpr int NB = NB_LONG + 2;
+constexpr int B_XL = 0;               // huge segments
+constexpr int NB_LONG = 24;           // long buckets 1..24: 32 - floor(log2(len))
+constexpr int B_MED = NB_LONG + 1;    // medium bucket
+constexpr int B_SHORT = NB_LONG + 2;  // short bucket
+constexpr int NB = NB_LONG + 3;
+constexpr int XL_W = 8, XL_IPT = 8;   // huge-class tile: 4096 keys
+constexpr int XL_TILE = XL_W * 64 * XL_IPT;
+constexpr int XL_HT = 16;             // tiles per histogram work item
+
+// per huge segment: active digit places and the index of each active pass
+struct XlDesc {
+    uint8_t j[8];
+    uint32_t mask;
+    uint32_t q;
+};
 
 struct SegArgs {
     void *keys;
@@ -42,7 +57,13 @@ struct SegArgs {
     int64_t nseg;
     int64_t base;       // off[0]
     int64_t end;        // off[nseg]
-    uint32_t a_max, b_max;
+    uint32_t a_max, b_max, xl_min;
+    uint32_t xl_cap;    // room for huge segments in the arrays below
+    uint32_t *xl_pre;   // xl_cap+1 tile prefix of the huge segments
+    uint32_t *xl_hist;  // xl_cap x places x RADIX digit counts
+    XlDesc *xl_desc;    // xl_cap descriptors
+    uint64_t *xl_lb;    // look-back words, tiles x RADIX
+    uint64_t xl_lb_words;
 };
 
 struct SegState {
@@ -52,34 +73,51 @@ struct SegState {
     uint32_t next_item;
     uint32_t nitems;
     uint32_t error;
+    uint32_t xl_count;      // huge segments (<= xl_cap)
+    uint32_t xl_tiles;      // their tiles
+    uint32_t xl_ctr[12];    // work counters: hist, scan, 8 passes, final
+    uint32_t epoch;         // look-back epoch base of this call
+    uint32_t lb_clear;      // 1: epochs wrapped, clear the look-back words
 };
 
 struct SegTune {
-    int ipt_a = 4;      // short class: 64*ipt_a keys per wave
-    int ipt_b = 16;     // medium class and long-class tiles: 256*ipt_b keys
-    int grid_mult = 4;  // persistent workgroups per CU
-    int b_max = 0;      // 0: the medium capacity
+    int ipt_a = 4;        // short class: 64*ipt_a keys per wave
+    int ipt_b = 16;       // medium class and long-class tiles: 256*ipt_b keys
+    int grid_mult = 4;    // persistent workgroups per CU
+    int b_max = 0;        // 0: the medium capacity
+    int xl_min = 32768;   // shortest segment of the huge class
 };
 
-__device__ __forceinline__ int seg_bucket(uint32_t len, uint32_t a_max, uint32_t b_max) {
+__device__ __forceinline__ int seg_bucket(uint32_t len, uint32_t a_max, uint32_t b_max, uint32_t xl_min) {
     if (len <= 1) return -1;
     if (len <= a_max) return B_SHORT;
     if (len <= b_max) return B_MED;
+    if (len >= xl_min) return B_XL;
     const int lg = 31 - __builtin_clz(len);
-    return 31 - lg < NB_LONG ? 31 - lg : NB_LONG - 1;
+    return 32 - lg < NB_LONG ? 32 - lg : NB_LONG;
 }
 
 __global__ void k_seg_setargs(SegArgs *a, SegArgs v) { *a = v; }
 
+// Also advances the look-back epoch (30-bit; 16 per call): on wrap the
+// words are cleared by k_xl_lbclear before any pass uses them.
 __global__ void k_seg_reset(SegState *st) {
     const int t = threadIdx.x;
     if (t < NB) {
         st->count[t] = 0;
         st->cursor[t] = 0;
     }
+    if (t < 12) st->xl_ctr[t] = 0;
     if (t == 0) {
         st->next_item = 0;
         st->nitems = 0;
+        uint32_t e = st->epoch + 16;
+        st->lb_clear = 0;
+        if (e < 16 || e + 16 >= (1u << 30)) {
+            e = 16;
+            st->lb_clear = 1;
+        }
+        st->epoch = e;
     }
 }
 
@@ -94,7 +132,7 @@ __global__ __launch_bounds__(256) void k_seg_count(const SegArgs *ap, SegState *
         if (hi < lo || lo < a.base || hi > a.end) {
             atomicOr(&st->error, 1u);
         } else {
-            const int b = seg_bucket((uint32_t)(hi - lo), a.a_max, a.b_max);
+            const int b = seg_bucket((uint32_t)(hi - lo), a.a_max, a.b_max, a.xl_min);
             if (b >= 0) atomicAdd(&s_c[b], 1u);
         }
     }
@@ -112,6 +150,7 @@ __global__ void k_seg_scan(SegState *st) {
     st->start[NB] = run;
     // short segments are taken SEG_W at a time (one per wave)
     st->nitems = st->start[B_SHORT] + (st->count[B_SHORT] + SEG_W - 1) / SEG_W;
+    st->xl_count = st->count[B_XL];
 }
 
 __global__ __launch_bounds__(256) void k_seg_place(const SegArgs *ap, SegState *st) {
@@ -124,7 +163,7 @@ __global__ __launch_bounds__(256) void k_seg_place(const SegArgs *ap, SegState *
     uint32_t mine = 0;
     if (s < a.nseg) {
         const int64_t lo = a.off[s], hi = a.off[s + 1];
-        if (hi >= lo && lo >= a.base && hi <= a.end) b = seg_bucket((uint32_t)(hi - lo), a.a_max, a.b_max);
+        if (hi >= lo && lo >= a.base && hi <= a.end) b = seg_bucket((uint32_t)(hi - lo), a.a_max, a.b_max, a.xl_min);
         if (b >= 0) mine = atomicAdd(&s_c[b], 1u);
     }
     __syncthreads();
@@ -151,9 +190,10 @@ __global__ __launch_bounds__(SEG_W * 64) void k_seg_sort(const SegArgs *ap, SegS
     U *tmp = (U *)a.tmp;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t nitems = st->nitems;
+    const uint32_t first = st->start[B_XL + 1];  // huge segments are sorted by the k_xl_* kernels
     const uint32_t med0 = st->start[B_MED], short0 = st->start[B_SHORT], nshort = st->count[B_SHORT];
     while (true) {
-        if (tid == 0) s_item = atomicAdd(&st->next_item, 1u);
+        if (tid == 0) s_item = first + atomicAdd(&st->next_item, 1u);
         __syncthreads();
         const uint32_t item = s_item;
         __syncthreads();
@@ -174,6 +214,304 @@ __global__ __launch_bounds__(SEG_W * 64) void k_seg_sort(const SegArgs *ap, SegS
             }
         }
         __syncthreads();
+    }
+}
+
+// ------------------------------------------------------- huge segments
+// Tiles of all huge segments are numbered consecutively, segment by
+// segment; xl_pre[i] is the first tile of huge segment i.
+
+__device__ __forceinline__ uint32_t xl_seg_of(const uint32_t *pre, uint32_t cnt, uint32_t tile) {
+    uint32_t lo = 0, hi = cnt;  // largest i < cnt with pre[i] <= tile
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (pre[mid] <= tile) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(1024) void k_xl_prefix(const SegArgs *ap, SegState *st) {
+    const SegArgs a = *ap;
+    __shared__ uint32_t s_wsum[16];
+    __shared__ uint32_t s_carry;
+    const uint32_t cnt = min(st->xl_count, a.xl_cap);
+    const uint32_t first = st->start[B_XL];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) s_carry = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < cnt; base += 1024) {
+        const uint32_t i = base + tid;
+        uint32_t v = 0;
+        if (i < cnt) {
+            const int64_t s = a.list[first + i];
+            const int64_t len = a.off[s + 1] - a.off[s];
+            v = (uint32_t)((len + XL_TILE - 1) / XL_TILE);
+        }
+        const uint32_t incl = wave_incl_scan(v);
+        if (lane == 63) s_wsum[w] = incl;
+        __syncthreads();
+        uint32_t pre = s_carry;
+        for (int ww = 0; ww < w; ++ww) pre += s_wsum[ww];
+        if (i < cnt) a.xl_pre[i] = pre + incl - v;
+        __syncthreads();
+        if (tid == 1023) s_carry = pre + incl;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        a.xl_pre[cnt] = s_carry;
+        st->xl_tiles = s_carry;
+        st->xl_count = cnt;
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_xl_zero(const SegArgs *ap, const SegState *st) {
+    const SegArgs a = *ap;
+    const size_t words = (size_t)st->xl_count * P * RADIX;
+    for (size_t i = blockIdx.x * 256ull + threadIdx.x; i < words; i += (size_t)gridDim.x * 256) a.xl_hist[i] = 0;
+    if (st->lb_clear) {
+        for (size_t i = blockIdx.x * 256ull + threadIdx.x; i < a.xl_lb_words; i += (size_t)gridDim.x * 256)
+            a.xl_lb[i] = 0;
+    }
+}
+
+// Digit counts of every place per huge segment: work items of XL_HT tiles,
+// LDS counters flushed whenever the items' tiles move to another segment.
+template <int DT>
+__global__ __launch_bounds__(256) void k_xl_hist(const SegArgs *ap, SegState *st) {
+    using U = typename KT<DT>::U;
+    constexpr int P = (int)sizeof(U);
+    __shared__ uint32_t s_h[P * RADIX];
+    __shared__ uint32_t s_item, s_seg;
+    const SegArgs a = *ap;
+    const U *keys = (const U *)a.keys;
+    const uint32_t cnt = st->xl_count, ntiles = st->xl_tiles, first = st->start[B_XL];
+    const uint32_t nitems = (ntiles + XL_HT - 1) / XL_HT;
+    const int tid = threadIdx.x;
+    while (true) {
+        if (tid == 0) s_item = atomicAdd(&st->xl_ctr[0], 1u);
+        for (int i = tid; i < P * RADIX; i += 256) s_h[i] = 0;
+        __syncthreads();
+        const uint32_t item = s_item;
+        if (item >= nitems) break;
+        const uint32_t g0 = item * XL_HT, g1 = min(g0 + XL_HT, ntiles);
+        int cur = -1;
+        for (uint32_t g = g0; g < g1; ++g) {
+            if (tid == 0) s_seg = xl_seg_of(a.xl_pre, cnt, g);
+            __syncthreads();
+            const int i = (int)s_seg;
+            if (cur >= 0 && i != cur) {
+                for (int k = tid; k < P * RADIX; k += 256)
+                    if (s_h[k]) {
+                        atomicAdd(&a.xl_hist[(size_t)cur * P * RADIX + k], s_h[k]);
+                        s_h[k] = 0;
+                    }
+                __syncthreads();
+            }
+            cur = i;
+            const int64_t s = a.list[first + i];
+            const int64_t lo = a.off[s], len = a.off[s + 1] - lo;
+            const uint32_t tb = (g - a.xl_pre[i]) * (uint32_t)XL_TILE;
+            const uint32_t tv = (uint32_t)min((int64_t)XL_TILE, len - (int64_t)tb);
+            for (uint32_t e = tid; e < tv; e += 256) {
+                const U t = KT<DT>::image(keys[lo + tb + e]);
+                const uint64_t act = ballot64(true);
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    const uint32_t d = (uint32_t)(t >> (8 * p)) & (RADIX - 1);
+                    const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+                    if (ballot64(d == d0) == act) {
+                        if (count_below(act) == 0) atomicAdd(&s_h[p * RADIX + d0], (uint32_t)__popcll(act));
+                    } else {
+                        atomicAdd(&s_h[p * RADIX + d], 1u);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (cur >= 0)
+            for (int k = tid; k < P * RADIX; k += 256)
+                if (s_h[k]) atomicAdd(&a.xl_hist[(size_t)cur * P * RADIX + k], s_h[k]);
+        __syncthreads();
+    }
+}
+
+// Per huge segment: exclusive digit offsets (in place of the counts),
+// trivial places, and the index of every active pass.
+template <int P>
+__global__ __launch_bounds__(256) void k_xl_scan(const SegArgs *ap, SegState *st) {
+    __shared__ uint32_t s_buf[RADIX], s_wsum[4];
+    __shared__ int s_active[8];
+    const SegArgs a = *ap;
+    const uint32_t cnt = st->xl_count, first = st->start[B_XL];
+    const int tid = threadIdx.x;
+    for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+        const int64_t s = a.list[first + i];
+        const uint32_t len = (uint32_t)(a.off[s + 1] - a.off[s]);
+        for (int p = 0; p < P; ++p) {
+            uint32_t *h = a.xl_hist + ((size_t)i * P + p) * RADIX;
+            const uint32_t c = h[tid];
+            const int trivial = __syncthreads_or(c == len);
+            s_buf[tid] = c;
+            __syncthreads();
+            block_exscan<256, RADIX>(s_buf, s_buf, s_wsum, tid);
+            h[tid] = s_buf[tid];
+            if (tid == 0) s_active[p] = !trivial;
+            __syncthreads();
+        }
+        if (tid == 0) {
+            XlDesc d{};
+            uint32_t q = 0;
+            for (int p = 0; p < P; ++p) {
+                if (s_active[p]) {
+                    d.j[p] = (uint8_t)q++;
+                    d.mask |= 1u << p;
+                }
+            }
+            d.q = q;
+            a.xl_desc[i] = d;
+        }
+        __syncthreads();
+    }
+}
+
+// One digit place over the tiles of every huge segment (persistent grid,
+// tiles taken in order).  Same tile work as the global one-sweep pass, with
+// the look-back stopping at the segment's first tile and offsets relative
+// to the segment; the segment ping-pongs with its scratch copy.
+template <int DT>
+__global__ __launch_bounds__(XL_W * 64) void k_xl_pass(const SegArgs *ap, SegState *st, int place) {
+    using U = typename KT<DT>::U;
+    constexpr int W = XL_W, IPT = XL_IPT, B = W * 64, TILE = XL_TILE;
+    constexpr int P = (int)sizeof(U);
+    constexpr size_t RAW = (size_t)TILE * sizeof(U) > (size_t)W * RADIX * 2 ? (size_t)TILE * sizeof(U)
+                                                                            : (size_t)W * RADIX * 2;
+    __shared__ __align__(16) uint8_t s_raw[RAW];
+    __shared__ uint32_t s_tot[RADIX], s_start[RADIX], s_glob[RADIX], s_wsum[W];
+    __shared__ uint32_t s_tile, s_seg;
+    uint16_t *s_cnt = reinterpret_cast<uint16_t *>(s_raw);
+    U *s_keys = reinterpret_cast<U *>(s_raw);
+    const SegArgs a = *ap;
+    U *keys = (U *)a.keys;
+    U *tmp = (U *)a.tmp;
+    const uint32_t cnt = st->xl_count, ntiles = st->xl_tiles, first = st->start[B_XL];
+    const uint32_t epoch = st->epoch + (uint32_t)place;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    while (true) {
+        if (tid == 0) {
+            s_tile = atomicAdd(&st->xl_ctr[2 + place], 1u);
+            s_seg = s_tile < ntiles ? xl_seg_of(a.xl_pre, cnt, s_tile) : 0u;
+        }
+        __syncthreads();
+        const uint32_t tile = s_tile, i = s_seg;
+        __syncthreads();
+        if (tile >= ntiles) break;
+        const XlDesc desc = a.xl_desc[i];
+        if (!((desc.mask >> place) & 1u)) continue;
+        const int64_t s = a.list[first + i];
+        const int64_t lo = a.off[s], len = a.off[s + 1] - lo;
+        const uint32_t lt = tile - a.xl_pre[i];
+        const uint32_t tbase = lt * (uint32_t)TILE;
+        const uint32_t tvalid = (uint32_t)min((int64_t)TILE, len - (int64_t)tbase);
+        const int jj_pass = desc.j[place];
+        const U *src = (jj_pass & 1) ? tmp + (lo - a.base) : keys + lo;
+        U *dst = (jj_pass & 1) ? keys + lo : tmp + (lo - a.base);
+        const int shift = 8 * place;
+
+        U k[IPT];
+        uint32_t dg[IPT], rk[IPT];
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const uint32_t e = striped_elem<IPT>(w, j, lane);
+            k[j] = e < tvalid ? src[tbase + e] : U(0);
+            dg[j] = e < tvalid ? (uint32_t)(KT<DT>::image(k[j]) >> shift) & (RADIX - 1) : 0u;
+        }
+        rank_match<RADIX_BITS, W, IPT, uint16_t>(dg, tvalid, rk, s_cnt, s_tot, tid);
+        uint64_t *lb = a.xl_lb + (size_t)tile * RADIX;
+        for (int d = tid; d < RADIX; d += B)
+            lb_store(lb + d, lb_pack(epoch, lt == 0 ? LB_INC : LB_AGG, s_tot[d]));
+        block_exscan<B, RADIX>(s_tot, s_start, s_wsum, tid);
+        rank_finish<RADIX_BITS, W, IPT, uint16_t>(dg, rk, s_cnt, s_start, tid);
+        {
+            constexpr int K = B / RADIX;
+            const int d = tid / K, kk = tid % K;
+            uint32_t excl = 0;
+            if (lt > 0) {
+                int64_t p = (int64_t)lt - 1;  // local tile index of the predecessor
+                while (true) {
+                    const int64_t pt = p - kk;
+                    uint64_t wv = pt >= 0 ? lb_load(a.xl_lb + (size_t)(tile - lt + pt) * RADIX + d)
+                                          : lb_pack(epoch, LB_INC, 0u);
+                    uint32_t fl = (uint32_t)(wv >> 32) & 3u;
+                    if ((uint32_t)(wv >> 34) != epoch) fl = 0;
+                    uint32_t inc_at = fl == LB_INC ? (uint32_t)kk : (uint32_t)K;
+                    uint32_t notready_at = fl == 0 ? (uint32_t)kk : (uint32_t)K;
+#pragma unroll
+                    for (int o = 1; o < K; o <<= 1) {
+                        inc_at = min(inc_at, (uint32_t)__shfl_xor((int)inc_at, o, 64));
+                        notready_at = min(notready_at, (uint32_t)__shfl_xor((int)notready_at, o, 64));
+                    }
+                    const uint32_t need = inc_at < (uint32_t)K ? inc_at : (uint32_t)K - 1;
+                    if (notready_at <= need) {
+                        __builtin_amdgcn_s_sleep(1);
+                        continue;
+                    }
+                    uint32_t c = (uint32_t)kk <= need ? (uint32_t)wv : 0u;
+#pragma unroll
+                    for (int o = 1; o < K; o <<= 1) c += (uint32_t)__shfl_xor((int)c, o, 64);
+                    excl += c;
+                    if (inc_at < (uint32_t)K) break;
+                    p -= K;
+                }
+                if (kk == 0) lb_store(lb + d, lb_pack(epoch, LB_INC, excl + s_tot[d]));
+            }
+            if (kk == 0) s_glob[d] = a.xl_hist[((size_t)i * P + place) * RADIX + d] + excl - s_start[d];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const uint32_t e = striped_elem<IPT>(w, j, lane);
+            if (e < tvalid) s_keys[rk[j]] = k[j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const uint32_t e = (uint32_t)(j * B + tid);
+            if (e < tvalid) {
+                const U key = s_keys[e];
+                const uint32_t d = (uint32_t)(KT<DT>::image(key) >> shift) & (RADIX - 1);
+                dst[s_glob[d] + e] = key;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Huge segments that ran an odd number of passes end in the scratch copy.
+template <int DT>
+__global__ __launch_bounds__(256) void k_xl_final(const SegArgs *ap, SegState *st) {
+    using U = typename KT<DT>::U;
+    __shared__ uint32_t s_tile, s_seg;
+    const SegArgs a = *ap;
+    U *keys = (U *)a.keys;
+    const U *tmp = (const U *)a.tmp;
+    const uint32_t cnt = st->xl_count, ntiles = st->xl_tiles, first = st->start[B_XL];
+    while (true) {
+        if (threadIdx.x == 0) {
+            s_tile = atomicAdd(&st->xl_ctr[10], 1u);
+            s_seg = s_tile < ntiles ? xl_seg_of(a.xl_pre, cnt, s_tile) : 0u;
+        }
+        __syncthreads();
+        const uint32_t tile = s_tile, i = s_seg;
+        __syncthreads();
+        if (tile >= ntiles) break;
+        if (!(a.xl_desc[i].q & 1u)) continue;
+        const int64_t s = a.list[first + i];
+        const int64_t lo = a.off[s], len = a.off[s + 1] - lo;
+        const uint32_t tbase = (tile - a.xl_pre[i]) * (uint32_t)XL_TILE;
+        const uint32_t tv = (uint32_t)min((int64_t)XL_TILE, len - (int64_t)tbase);
+        for (uint32_t e = threadIdx.x; e < tv; e += 256) keys[lo + tbase + e] = tmp[lo - a.base + tbase + e];
     }
 }
 
@@ -220,23 +558,25 @@ static void load_tune_table() {
         g_tune[i].ipt_b = json_int(txt, names[i], "ipt_b", g_tune[i].ipt_b);
         g_tune[i].grid_mult = json_int(txt, names[i], "grid_mult", g_tune[i].grid_mult);
         g_tune[i].b_max = json_int(txt, names[i], "b_max", g_tune[i].b_max);
+        g_tune[i].xl_min = json_int(txt, names[i], "xl_min", g_tune[i].xl_min);
     }
 }
 
 static bool tune_valid(int kb, const SegTune &t) {
     const bool a_ok = t.ipt_a == 2 || t.ipt_a == 4;
     const bool b_ok = t.ipt_b == 8 || t.ipt_b == 16 || (kb == 32 && t.ipt_b == 32);
-    return a_ok && b_ok && t.grid_mult >= 1 && t.grid_mult <= 16 && t.b_max >= 0;
+    return a_ok && b_ok && t.grid_mult >= 1 && t.grid_mult <= 16 && t.b_max >= 0 && t.xl_min >= 4096;
 }
 
 }  // namespace ak
 
 // Sets the segmented-sort tuning for 32- or 64-bit keys (autotuner hook).
-extern "C" ak_status ak_seg_set_tuning(int key_bits, int ipt_a, int ipt_b, int grid_mult, int b_max) {
+extern "C" ak_status ak_seg_set_tuning(int key_bits, int ipt_a, int ipt_b, int grid_mult, int b_max,
+                                       int xl_min) {
     using namespace ak;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     load_tune_table();
-    SegTune t{ipt_a, ipt_b, grid_mult, b_max};
+    SegTune t{ipt_a, ipt_b, grid_mult, b_max, xl_min};
     if ((key_bits != 32 && key_bits != 64) || !tune_valid(key_bits, t)) {
         set_error("invalid segmented-sort tuning");
         return AK_ERR_INVALID_ARG;
@@ -287,6 +627,26 @@ static ak_status launch_seg_sort(const SegTune &t, dim3 grid, hipStream_t s, con
     return AK_OK;
 }
 
+template <int DT>
+static ak_status launch_xl(int grid, hipStream_t s, SegArgs *a, SegState *st) {
+    constexpr int P = key_bits(DT) / 8;
+    hipLaunchKernelGGL(k_xl_prefix, dim3(1), dim3(1024), 0, s, a, st);
+    AK_LAUNCH_CHECK("k_xl_prefix");
+    hipLaunchKernelGGL((k_xl_zero<P>), dim3(grid), dim3(256), 0, s, a, st);
+    AK_LAUNCH_CHECK("k_xl_zero");
+    hipLaunchKernelGGL((k_xl_hist<DT>), dim3(grid), dim3(256), 0, s, a, st);
+    AK_LAUNCH_CHECK("k_xl_hist");
+    hipLaunchKernelGGL((k_xl_scan<P>), dim3(grid), dim3(256), 0, s, a, st);
+    AK_LAUNCH_CHECK("k_xl_scan");
+    for (int p = 0; p < P; ++p) {
+        hipLaunchKernelGGL((k_xl_pass<DT>), dim3(grid), dim3(XL_W * 64), 0, s, a, st, p);
+        AK_LAUNCH_CHECK("k_xl_pass");
+    }
+    hipLaunchKernelGGL((k_xl_final<DT>), dim3(grid), dim3(256), 0, s, a, st);
+    AK_LAUNCH_CHECK("k_xl_final");
+    return AK_OK;
+}
+
 static ak_status seg_launch_all(int dt, const SegTune &t, int64_t nseg, int grid, hipStream_t s, SegArgs *a,
                                 SegState *st) {
     const unsigned g = (unsigned)((nseg + 255) / 256);
@@ -298,6 +658,17 @@ static ak_status seg_launch_all(int dt, const SegTune &t, int64_t nseg, int grid
     AK_LAUNCH_CHECK("k_seg_scan");
     hipLaunchKernelGGL(k_seg_place, dim3(g), dim3(256), 0, s, a, st);
     AK_LAUNCH_CHECK("k_seg_place");
+    ak_status r;
+    switch (dt) {
+    case AK_I32: r = launch_xl<AK_I32>(grid, s, a, st); break;
+    case AK_I64: r = launch_xl<AK_I64>(grid, s, a, st); break;
+    case AK_U32: r = launch_xl<AK_U32>(grid, s, a, st); break;
+    case AK_U64: r = launch_xl<AK_U64>(grid, s, a, st); break;
+    case AK_F32: r = launch_xl<AK_F32>(grid, s, a, st); break;
+    case AK_F64: r = launch_xl<AK_F64>(grid, s, a, st); break;
+    default: r = AK_ERR_UNSUPPORTED_DTYPE;
+    }
+    if (r != AK_OK) return r;
     switch (dt) {
     case AK_I32: return launch_seg_sort<AK_I32>(t, dim3(grid), s, a, st);
     case AK_I64: return launch_seg_sort<AK_I64>(t, dim3(grid), s, a, st);
@@ -343,8 +714,20 @@ ak_status segmented_sort(Workspace *ws, int dt, void *keys, const int64_t *offse
 
     ak_status r;
     const size_t kb = (size_t)dtype_bytes(dt);
+    const int P = (int)kb;
+    const uint32_t xl_min = (uint32_t)std::max(t.xl_min, (int)b_max + 1);
+    const uint32_t xl_cap = (uint32_t)std::min<int64_t>(nseg, n / xl_min + 1);
+    const size_t off_pre = ((size_t)nseg * 4 + 255) & ~size_t(255);
+    const size_t off_desc = off_pre + (((size_t)(xl_cap + 1) * 4 + 255) & ~size_t(255));
+    const size_t off_hist = off_desc + (((size_t)xl_cap * sizeof(XlDesc) + 255) & ~size_t(255));
+    const size_t misc2_need = off_hist + (size_t)xl_cap * P * RADIX * 4;
+    const size_t lb_words = ((size_t)n / XL_TILE + xl_cap + 1) * RADIX;
     if ((r = ws_reserve(ws, &ws->misc, &ws->misc_bytes, (size_t)n * kb)) != AK_OK) return r;
-    if ((r = ws_reserve(ws, &ws->misc2, &ws->misc2_bytes, (size_t)nseg * 4)) != AK_OK) return r;
+    if ((r = ws_reserve(ws, &ws->misc2, &ws->misc2_bytes, misc2_need)) != AK_OK) return r;
+    if (lb_words * 8 > ws->aux_bytes[3]) {
+        if ((r = ws_reserve(ws, &ws->aux[3], &ws->aux_bytes[3], lb_words * 8)) != AK_OK) return r;
+        AK_HIP(hipMemsetAsync(ws->aux[3], 0, ws->aux_bytes[3], s));
+    }
 
     std::lock_guard<std::mutex> lk(g_seg_mu);
     SegCache &c = g_seg[ws];
@@ -364,6 +747,13 @@ ak_status segmented_sort(Workspace *ws, int dt, void *keys, const int64_t *offse
     v.end = ends[1];
     v.a_max = a_max;
     v.b_max = b_max;
+    v.xl_min = xl_min;
+    v.xl_cap = xl_cap;
+    v.xl_pre = (uint32_t *)((char *)ws->misc2 + off_pre);
+    v.xl_desc = (XlDesc *)((char *)ws->misc2 + off_desc);
+    v.xl_hist = (uint32_t *)((char *)ws->misc2 + off_hist);
+    v.xl_lb = (uint64_t *)ws->aux[3];
+    v.xl_lb_words = ws->aux_bytes[3] / 8;
     hipLaunchKernelGGL(k_seg_setargs, dim3(1), dim3(1), 0, s, c.args, v);
     AK_LAUNCH_CHECK("k_seg_setargs");
 
@@ -385,6 +775,7 @@ ak_status segmented_sort(Workspace *ws, int dt, void *keys, const int64_t *offse
         if (ie != hipSuccess) return hip_fail(ie, "hipGraphInstantiate");
         it = c.graphs.emplace(key, ex).first;
     }
+    ProfScope ps("segmented_graph", s);
     AK_HIP(hipGraphLaunch(it->second, s));
     return AK_OK;
 }

@@ -101,3 +101,30 @@ def test_workload4_full_size():
         a, b = int(offh[s]), int(offh[s + 1])
         src = to_host(orig[a:b], "u32")
         assert np.array_equal(to_host(keys[a:b], "u32"), oracle.sort(src)), s
+
+
+@pytest.mark.parametrize("dt", ["u32", "f64", "i64"])
+def test_huge_segments_under_tunings(dt):
+    """Segments above the many-workgroup threshold (several thresholds),
+    including constant ones and ones where only the lowest byte varies
+    (one active pass: the result ends in the scratch copy)."""
+    rng = np.random.default_rng(17)
+    lens = [40_000, 100_000, 5_000, 70_000, 65_536, 9000, 0, 33_000]
+    parts = []
+    for i, L in enumerate(lens):
+        if i == 3:
+            parts.append(np.full(L, random_keys(dt, 1, rng, "uniform")[0]))
+        elif i == 4:
+            parts.append((rng.integers(0, 200, size=L)).astype(bits(random_keys(dt, 1, rng)).dtype)
+                         .view(random_keys(dt, 1, rng).dtype))
+        else:
+            parts.append(random_keys(dt, L, rng, "mixed"))
+    k = np.concatenate(parts)
+    off = _offsets(lens)
+    kb = 32 if dt in ("u32", "i32", "f32") else 64
+    try:
+        for xl in (4096, 32768, 1 << 20):
+            ak.seg_set_tuning(kb, 4, 16, 4, 0, xl)
+            assert np.array_equal(bits(_seg(k, off, dt)), bits(oracle.segsort(k, off))), xl
+    finally:
+        ak.seg_set_tuning(kb, 4, 16, 4, 0, 32768)
