@@ -14,22 +14,23 @@ namespace ak {
 // between the lowest and highest varying bit, store once.  `in` may equal
 // `out`: every key is read before any is written.  With VAL the output is
 // the permutation (vout[i] = input index of the i-th smallest key).
+// Sorts the first `len` keys of a tile already held in registers in the
+// wave-striped layout (k[j] of lane l in wave w is element w*64*IPT + j*64
+// + l); writes them sorted to out[0..len) (or, with VAL, the input indices
+// to vout).
 template <int DT, bool VAL, int W, int IPT>
-__device__ __forceinline__ void lds_sort_tile(const typename KT<DT>::U *in, typename KT<DT>::U *out,
+__device__ __forceinline__ void lds_sort_regs(typename KT<DT>::U (&k)[IPT], typename KT<DT>::U *out,
                                               uint32_t *vout, uint32_t len,
                                               SmallSmem<typename KT<DT>::U, VAL, W, IPT> &sm, int tid) {
     using U = typename KT<DT>::U;
     constexpr int B = W * 64;
     const int lane = tid & 63, w = tid >> 6;
-    U k[IPT];
     uint32_t v[IPT], dg[IPT], rk[IPT];
     uint64_t vor = 0, vand = ~0ull;
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         const uint32_t e = striped_elem<IPT>(w, j, lane);
-        k[j] = U(0);
         if (e < len) {
-            k[j] = in[e];
             const uint64_t t = (uint64_t)KT<DT>::image(k[j]);
             vor |= t;
             vand &= t;
@@ -78,6 +79,23 @@ __device__ __forceinline__ void lds_sort_tile(const typename KT<DT>::U *in, type
             else vout[e] = v[j];
         }
     }
+}
+
+// Loads up to W*64*IPT keys from `in` and sorts them on chip (`in` may
+// equal `out`: every key is read before any is written).
+template <int DT, bool VAL, int W, int IPT>
+__device__ __forceinline__ void lds_sort_tile(const typename KT<DT>::U *in, typename KT<DT>::U *out,
+                                              uint32_t *vout, uint32_t len,
+                                              SmallSmem<typename KT<DT>::U, VAL, W, IPT> &sm, int tid) {
+    using U = typename KT<DT>::U;
+    const int lane = tid & 63, w = tid >> 6;
+    U k[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const uint32_t e = striped_elem<IPT>(w, j, lane);
+        k[j] = e < len ? in[e] : U(0);
+    }
+    lds_sort_regs<DT, VAL, W, IPT>(k, out, vout, len, sm, tid);
 }
 
 }  // namespace ak

@@ -352,14 +352,29 @@ __global__ __launch_bounds__(W * 64) void k_chunk_sort(typename KT<DT>::U *keys,
     __syncthreads();
     uint32_t pos = sm.bound[0];
     const uint32_t end = sm.bound[1];
+    const int lane = tid & 63, w = tid >> 6;
     uint32_t nchunks = 0;
     while (pos < end) {
         const uint32_t len = std::min<uint32_t>(CAP, end - pos);
+        // one read of the chunk: registers (striped) for the sort, codes in
+        // LDS for the cut
+        U k[IPT];
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const uint32_t e = striped_elem<IPT>(w, j, lane);
+            k[j] = e < len ? keys[pos + e] : U(0);
+        }
         uint32_t cut = end;
         if (pos + len < end) {
-            // codes of keys pos .. pos+len (one past the chunk)
-            for (uint32_t e = tid; e <= len; e += B) sm.code[e] = code_at<DT>(keys, pos + e, h, lv, cb, scale);
-            if (tid == 0) sm.cut = 0;
+#pragma unroll
+            for (int j = 0; j < IPT; ++j) {
+                const uint32_t e = striped_elem<IPT>(w, j, lane);
+                if (e < len) sm.code[e] = rmi_code(h, lv, KT<DT>::image(k[j]), cb, scale);
+            }
+            if (tid == 0) {
+                sm.code[len] = code_at<DT>(keys, pos + len, h, lv, cb, scale);
+                sm.cut = 0;
+            }
             __syncthreads();
             uint32_t best = 0;
             for (uint32_t e = 1 + tid; e <= len; e += B)
@@ -383,7 +398,7 @@ __global__ __launch_bounds__(W * 64) void k_chunk_sort(typename KT<DT>::U *keys,
             cut = pos + q;
             __syncthreads();
         }
-        lds_sort_tile<DT, false, W, IPT>(keys + pos, keys + pos, nullptr, cut - pos, sm.sort, tid);
+        lds_sort_regs<DT, false, W, IPT>(k, keys + pos, nullptr, cut - pos, sm.sort, tid);
         ++nchunks;
         pos = cut;
         __syncthreads();

@@ -76,13 +76,18 @@ __device__ __forceinline__ void rank_match(const uint32_t (&dg)[IPT], uint32_t n
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         const bool valid = striped_elem<IPT>(w, j, lane) < nvalid;
-        uint64_t peers = ballot64(valid);
+        const uint64_t vm = ballot64(valid);
+        uint32_t plo = (uint32_t)vm, phi = (uint32_t)(vm >> 32);
 #pragma unroll
         for (int b = 0; b < RB; ++b) {
-            const bool bit = (dg[j] >> b) & 1u;
-            const uint64_t m = ballot64(bit);
-            peers &= bit ? m : ~m;
+            // t = all ones if this lane's bit b is set; lanes agreeing on the
+            // bit keep their peer bit: peers &= ~(ballot ^ t)
+            const uint32_t t = (uint32_t)__builtin_amdgcn_sbfe((int32_t)dg[j], b, 1);
+            const uint64_t m = ballot64(t != 0u);
+            plo &= ~((uint32_t)m ^ t);
+            phi &= ~((uint32_t)(m >> 32) ^ t);
         }
+        const uint64_t peers = ((uint64_t)phi << 32) | plo;
         const uint32_t below = count_below(peers);
         const uint32_t c = cnt[dg[j]];
         rk[j] = c + below;

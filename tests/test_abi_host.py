@@ -1,0 +1,76 @@
+"""Host-side checks of the C ABI (no GPU needed): libak.so loads, exports
+every function include/ak.h declares, and rejects bad arguments before any
+device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ak.h")
+
+
+def _lib():
+    import paper_2507_16710_amd as ak
+    if not os.path.exists(ak.LIB_PATH):
+        from paper_2507_16710_amd import build
+        build.build()
+    return ak.load_library()
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ak_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = _lib()
+    names = declared_functions()
+    assert len(names) >= 25
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_argument_errors_without_device_work():
+    lib = _lib()
+    vp = ctypes.c_void_p
+    fake = vp(0x1000)     # never dereferenced: rejected before any launch
+    assert lib.ak_sort(fake, -1, 2, None) == 1
+    assert lib.ak_sort(None, 10, 2, None) == 1
+    assert lib.ak_sort(fake, 10, 0, None) == 2
+    assert lib.ak_sort(fake, 10, 7, None) == 2
+    assert lib.ak_sort(fake, 1 << 32, 2, None) == 1
+    assert lib.ak_sort(fake, 0, 2, None) == 0           # n == 0: no launch
+    assert lib.ak_sortperm(fake, None, 10, 2, None) == 1
+    assert lib.ak_sortperm(fake, fake, 10, 2, None) == 1  # keys and perm overlap
+    assert lib.ak_segmented_sort(fake, fake, -1, 3, None) == 1
+    assert lib.ak_segmented_sort(fake, fake, 0, 3, None) == 0
+    assert lib.ak_segmented_sort(None, fake, 5, 3, None) == 1
+    bad = (ctypes.c_int32 * 8)(4095, 12, 0, 0, 0, 0, 0, 0)   # leaves not a power of two
+    assert lib.ak_sort_learned(fake, 10, 4, bad, None, None) == 1
+    assert lib.ak_rmi_codes(fake, 10, 4, fake, 25, fake, None) == 1
+    assert lib.ak_learned_sample(fake, 10, 4, 0, -1, fake, None) == 1
+    assert lib.ak_seg_set_tuning(32, 3, 16, 4, 0, 32768) == 1
+    assert lib.ak_seg_set_tuning(64, 4, 32, 4, 0, 32768) == 1   # 32 keys/lane: 32-bit only
+    msg = lib.ak_last_error()
+    assert msg and b"tuning" in msg
+    assert lib.ak_status_string(3) == b"out of device memory"
+
+
+def test_temp_bytes_predictable():
+    """Scratch sizes are known from n alone (paper Sec. II-B: temporaries
+    are exposed and predictable)."""
+    lib = _lib()
+    for dt in (1, 2, 3, 4, 5, 6):
+        kb = 8 if dt in (2, 4, 6) else 4
+        assert lib.ak_temp_bytes(0, 100, dt) == 0                 # on-chip path
+        n = 10_000_000
+        s = lib.ak_temp_bytes(0, n, dt)
+        p = lib.ak_temp_bytes(1, n, dt)
+        assert n * kb <= s <= n * kb * 1.2
+        assert p >= s + n * kb + n * 4
+        assert lib.ak_temp_bytes(2, n, dt) >= n * kb
+        assert lib.ak_temp_bytes(3, n, dt) >= s
+    assert lib.ak_rmi_model_floats(4096) == 8 + 8 * 4096

@@ -7,6 +7,7 @@ comparator, exhaustive permutations, closed forms, and invariants that are
 shown to reject planted mistakes.
 """
 import itertools
+import os
 import zlib
 
 import numpy as np
@@ -60,10 +61,10 @@ def test_exhaustive_permutations_small(dt):
 
 
 def test_float_order_closed_form():
-    """-Inf < -max < -1 < -min_normal < -denorm < -0 < +0 < denorm < ... < +Inf < NaN."""
-    order = np.array([0xFF800000, 0xFF7FFFFF, 0xBF800000, 0x80800000, 0x80000001,
-                      0x80000000, 0x00000000, 0x00000001, 0x00800000, 0x3F800000,
-                      0x7F7FFFFF, 0x7F800000], dtype=np.uint32)
+    """Shuffles of the golden float32 order sort back to it."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "float32_total_order.txt")
+    vals = [int(l.split()[0], 16) for l in open(path) if l.strip() and not l.startswith("#")]
+    order = np.array(vals, dtype=np.uint32)
     rng = np.random.default_rng(11)
     for _ in range(20):
         shuf = rng.permutation(order)
