@@ -321,7 +321,7 @@ def leaf_grad_scaled(model: Model, sorted_keys: np.ndarray) -> np.ndarray:
     s = leaf_scales(model, sorted_keys).astype(np.float64)
     out = np.zeros((model.L, 7))
     out[:, 0] = loss
-    out[:, 1] = grad[:, 0] / s
+    out[:, 1] = grad[:, 0] * s      # a = a'*s, so dL/da' = s * dL/da
     out[:, 2] = grad[:, 1]
     out[:, 3] = hess[:, 0] * s * s
     out[:, 4] = hess[:, 1] * s

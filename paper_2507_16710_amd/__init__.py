@@ -256,8 +256,7 @@ def profile_enable(on: bool = True) -> None:
 def profile_read() -> dict:
     """{kernel name: (launches, total ms)} since the last read."""
     lib = load_library()
-    need = lib.ak_profile_read(None, 0)
-    buf = ctypes.create_string_buffer(int(need) + 64)
+    buf = ctypes.create_string_buffer(1 << 20)
     lib.ak_profile_read(buf, len(buf))
     out = {}
     for line in buf.value.decode().splitlines():

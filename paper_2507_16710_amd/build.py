@@ -16,6 +16,9 @@ ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed fp32 instructions stay off: plain float code only
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # products and sums are rounded one by one (no fused multiply-add):
+         # integer results decided in float32 must not depend on contraction
+         "-ffp-contract=off",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
          "-I", os.path.join(HERE, "..", "include")]
 

@@ -187,6 +187,10 @@ int64_t small_sort_capacity(int dtype);
 
 // -------------------------------------------------------- segmented sort
 ak_status segmented_sort(Workspace *ws, int dtype, void *keys, const int64_t *offsets, int64_t nseg);
+// Sorts disjoint ranges keys[lo[s] .. hi[s]) within keys[0 .. end), with
+// `tmp` as end keys of scratch (ranges with hi <= lo are skipped).
+ak_status segmented_sort_ranges(Workspace *ws, int dtype, void *keys, const int64_t *lo, const int64_t *hi,
+                                int64_t nseg, int64_t end, void *tmp);
 size_t segmented_temp_bytes(int dtype, int64_t n, int64_t nseg);
 
 // ------------------------------------------------------------- learned

@@ -423,27 +423,28 @@ __global__ __launch_bounds__(256) void k_fb_check(const typename KT<DT>::U *keys
     }
 }
 
-// Fallback, step 2: every non-constant run is radix-sorted by one workgroup.
-template <int DT>
-__global__ __launch_bounds__(256) void k_fb_sort(typename KT<DT>::U *keys, typename KT<DT>::U *tmp, const FbRun *fb,
-                                                 LearnedState *ls, const uint32_t *nonconst) {
-    using U = typename KT<DT>::U;
-    __shared__ LongSmem<U, 4, 16> sm;
-    __shared__ uint32_t s_r;
+// Fallback: the runs become [lo, hi) ranges for the segmented sort (unused
+// slots up to the capacity are empty ranges).
+__global__ void k_fb_ranges(const FbRun *fb, LearnedState *ls, int64_t *lo, int64_t *hi, uint32_t cap) {
     const uint32_t nr = ls->fb_count;
-    while (true) {
-        if (threadIdx.x == 0) s_r = atomicAdd(&ls->fb_next, 1u);
-        __syncthreads();
-        const uint32_t r = s_r;
-        __syncthreads();
-        if (r >= nr) break;
-        const FbRun run = fb[r];
-        if (threadIdx.x == 0) {
-            atomicAdd(&ls->fb_keys, (unsigned long long)run.len);
-            if (!nonconst[r]) atomicAdd(&ls->const_keys, (unsigned long long)run.len);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += gridDim.x * blockDim.x) {
+        if (i < nr) {
+            const FbRun r = fb[i];
+            lo[i] = r.start;
+            hi[i] = (int64_t)r.start + r.len;
+            atomicAdd(&ls->fb_keys, (unsigned long long)r.len);
+        } else {
+            lo[i] = 0;
+            hi[i] = 0;
         }
-        if (nonconst[r]) sort_long<DT, 4, 16>(keys + run.start, tmp + run.start, run.len, sm);
     }
+}
+
+// Statistics only: keys of fallback runs that hold one repeated key.
+__global__ void k_fb_const(const FbRun *fb, LearnedState *ls, const uint32_t *nonconst) {
+    const uint32_t nr = ls->fb_count;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nr; i += gridDim.x * blockDim.x)
+        if (!nonconst[i]) atomicAdd(&ls->const_keys, (unsigned long long)fb[i].len);
 }
 
 __global__ void k_learned_reset(LearnedState *ls, uint32_t *nonconst, uint32_t cap) {
@@ -585,7 +586,9 @@ static ak_status learned_t(Workspace *ws, void *keys, int64_t n64, const ak_lear
     const size_t off_state = off_model + (((8 + 8 * (size_t)L) * 4 + 255) & ~size_t(255));
     const size_t off_fb = off_state + 256;
     const size_t off_nc = off_fb + (((size_t)fb_cap * sizeof(FbRun) + 255) & ~size_t(255));
-    const size_t need = off_nc + (size_t)fb_cap * 4 + 256;
+    const size_t off_lo = off_nc + (((size_t)fb_cap * 4 + 255) & ~size_t(255));
+    const size_t off_hi = off_lo + (size_t)fb_cap * 8;
+    const size_t need = off_hi + (size_t)fb_cap * 8 + 256;
     if ((r = ws_reserve(ws, &ws->aux[0], &ws->aux_bytes[0], need)) != AK_OK) return r;
     char *base = (char *)ws->aux[0];
     U *sample = (U *)base;
@@ -593,6 +596,8 @@ static ak_status learned_t(Workspace *ws, void *keys, int64_t n64, const ak_lear
     LearnedState *ls = (LearnedState *)(base + off_state);
     FbRun *fb = (FbRun *)(base + off_fb);
     uint32_t *nonconst = (uint32_t *)(base + off_nc);
+    int64_t *fb_lo = (int64_t *)(base + off_lo);
+    int64_t *fb_hi = (int64_t *)(base + off_hi);
 
     hipLaunchKernelGGL(k_learned_reset, dim3(std::min<uint32_t>((fb_cap + 255) / 256, 1024)), dim3(256), 0, s, ls,
                        nonconst, fb_cap);
@@ -614,14 +619,16 @@ static ak_status learned_t(Workspace *ws, void *keys, int64_t n64, const ak_lear
     hipLaunchKernelGGL((k_chunk_sort<DT, CW, CIPT>), dim3(npieces), dim3(CW * 64), 0, s, (U *)keys, n,
                        (const float *)model, cb, piece, fb, ls);
     AK_LAUNCH_CHECK("k_chunk_sort");
-    // 5. fallback runs
+    // 5. fallback runs: radix-sorted as segments (runs of one repeated key
+    // only cost the histogram read there: every digit place is trivial)
+    const uint32_t fgrid = std::min<uint32_t>((fb_cap + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fb_ranges, dim3(fgrid), dim3(256), 0, s, (const FbRun *)fb, ls, fb_lo, fb_hi, fb_cap);
+    AK_LAUNCH_CHECK("k_fb_ranges");
     if ((r = ws_reserve(ws, &ws->keys0, &ws->keys0_bytes, (size_t)n * sizeof(U))) != AK_OK) return r;
-    hipLaunchKernelGGL((k_fb_check<DT>), dim3(num_cus() * 4), dim3(256), 0, s, (const U *)keys, (const FbRun *)fb,
-                       (const LearnedState *)ls, nonconst);
-    AK_LAUNCH_CHECK("k_fb_check");
-    hipLaunchKernelGGL((k_fb_sort<DT>), dim3(num_cus() * 2), dim3(256), 0, s, (U *)keys, (U *)ws->keys0,
-                       (const FbRun *)fb, ls, (const uint32_t *)nonconst);
-    AK_LAUNCH_CHECK("k_fb_sort");
+    {
+        ProfScope ps_fb("fallback_segmented", s);
+        if ((r = segmented_sort_ranges(ws, DT, keys, fb_lo, fb_hi, fb_cap, n, ws->keys0)) != AK_OK) return r;
+    }
 
     if (stats) {
         const int bl = std::min(std::min(cfg->buckets_log2, cb), 14);
@@ -629,6 +636,12 @@ static ak_status learned_t(Workspace *ws, void *keys, int64_t n64, const ak_lear
         if ((r = ws_reserve(ws, &ws->aux[2], &ws->aux_bytes[2], (size_t)nb * 4)) != AK_OK) return r;
         uint32_t *hist = (uint32_t *)ws->aux[2];
         AK_HIP(hipMemsetAsync(hist, 0, (size_t)nb * 4, s));
+        hipLaunchKernelGGL((k_fb_check<DT>), dim3(num_cus() * 4), dim3(256), 0, s, (const U *)keys,
+                           (const FbRun *)fb, (const LearnedState *)ls, nonconst);
+        AK_LAUNCH_CHECK("k_fb_check");
+        hipLaunchKernelGGL(k_fb_const, dim3(fgrid), dim3(256), 0, s, (const FbRun *)fb, ls,
+                           (const uint32_t *)nonconst);
+        AK_LAUNCH_CHECK("k_fb_const");
         hipLaunchKernelGGL((k_bucket_hist<DT>), dim3(num_cus() * 4), dim3(256), (size_t)nb * 4, s, (const U *)keys,
                            n, (const float *)model, cb, cb - bl, nb, hist);
         AK_LAUNCH_CHECK("k_bucket_hist");

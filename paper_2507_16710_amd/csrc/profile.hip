@@ -65,6 +65,7 @@ ak_status ak_profile_enable(int on) {
 // Waits for the recorded launches, then writes one line per kernel name,
 // "name count total_ms\n", into buf (truncated to len bytes, always
 // NUL-terminated) and forgets the records.  Returns the bytes needed.
+// (Call it once with a large buffer: the records are gone afterwards.)
 size_t ak_profile_read(char *buf, size_t len) {
     std::lock_guard<std::mutex> lk(g_mu);
     std::map<std::string, std::pair<long, double>> agg;

@@ -246,39 +246,12 @@ __global__ __launch_bounds__(W * 64) void k_onesweep(OnesweepArgs a) {
     block_exscan<B, RADIX>(s_tot, s_start, s_wsum, tid);
     rank_finish<RADIX_BITS, W, IPT, uint16_t>(dg, rk, s_cnt, s_start, tid);
 
-    // decoupled look-back, K predecessors per round trip: thread (d, kk)
-    // reads tile p - kk; the group sums the counts down to the nearest
-    // inclusive prefix, or all K if none is inclusive, and repeats.
+    // decoupled look-back, K*LB_M predecessors per round trip
     {
         const int d = tid / K, kk = tid % K;
         uint32_t excl = 0;
         if (tile > 0) {
-            int64_t p = (int64_t)tile - 1;
-            while (true) {
-                const int64_t pt = p - kk;
-                uint64_t wv = pt >= 0 ? lb_load(a.lookback + (size_t)pt * RADIX + d) : lb_pack(epoch, LB_INC, 0u);
-                uint32_t fl = (uint32_t)(wv >> 32) & 3u;
-                if ((uint32_t)(wv >> 34) != epoch) fl = 0;
-                // nearest inclusive predecessor within the window
-                uint32_t inc_at = fl == LB_INC ? (uint32_t)kk : (uint32_t)K;
-                uint32_t notready_at = fl == 0 ? (uint32_t)kk : (uint32_t)K;
-#pragma unroll
-                for (int o = 1; o < K; o <<= 1) {
-                    inc_at = min(inc_at, (uint32_t)__shfl_xor((int)inc_at, o, 64));
-                    notready_at = min(notready_at, (uint32_t)__shfl_xor((int)notready_at, o, 64));
-                }
-                const uint32_t need = inc_at < (uint32_t)K ? inc_at : (uint32_t)K - 1;
-                if (notready_at <= need) {
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                uint32_t c = (uint32_t)kk <= need ? (uint32_t)wv : 0u;
-#pragma unroll
-                for (int o = 1; o < K; o <<= 1) c += (uint32_t)__shfl_xor((int)c, o, 64);
-                excl += c;
-                if (inc_at < (uint32_t)K) break;
-                p -= K;
-            }
+            excl = lookback_prefix<K, LB_M>(a.lookback + d, (int64_t)tile - 1, epoch, kk);
             if (kk == 0) lb_store(lb + d, lb_pack(epoch, LB_INC, excl + s_tot[d]));
         }
         if (kk == 0) s_glob[d] = a.st->base[a.place][d] + excl - s_start[d];

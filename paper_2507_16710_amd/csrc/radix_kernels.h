@@ -20,15 +20,17 @@ struct OnesweepArgs {
 // One-sweep tile shapes (W waves x IPT keys per lane).  A few shapes are
 // compiled per (key width, with values); os_variant() picks one at run time
 // (default from the tuning sweep; $AK_OS_VARIANT overrides it).
+constexpr int LB_M = 4;  // look-back words read per thread per round trip
+
 struct OsShape {
     int w, ipt;
 };
 constexpr int OS_NVAR = 4;
 constexpr OsShape OS_SHAPES[2][2][OS_NVAR] = {
     // 32-bit keys: keys only, with values
-    {{{8, 12}, {16, 8}, {16, 12}, {8, 16}}, {{8, 12}, {16, 8}, {16, 6}, {8, 8}}},
+    {{{16, 8}, {16, 6}, {16, 12}, {16, 16}}, {{8, 12}, {16, 8}, {16, 6}, {16, 4}}},
     // 64-bit keys: keys only, with values
-    {{{8, 8}, {16, 4}, {16, 6}, {8, 12}}, {{8, 6}, {16, 4}, {8, 8}, {16, 6}}},
+    {{{16, 4}, {16, 3}, {16, 6}, {16, 8}}, {{16, 4}, {8, 6}, {16, 3}, {16, 6}}},
 };
 int os_variant(int dt, bool val);
 inline int os_tile(int dt, bool val) {

@@ -51,7 +51,8 @@ struct XlDesc {
 
 struct SegArgs {
     void *keys;
-    const int64_t *off;
+    const int64_t *off;  // segment s is keys[off[s] .. hi[s])
+    const int64_t *hi;   // (CSR offsets: hi = off + 1)
     void *tmp;          // scratch, same layout as keys[off[0] ..)
     int32_t *list;      // segment ids, grouped by bucket
     int64_t nseg;
@@ -128,7 +129,7 @@ __global__ __launch_bounds__(256) void k_seg_count(const SegArgs *ap, SegState *
     __syncthreads();
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s < a.nseg) {
-        const int64_t lo = a.off[s], hi = a.off[s + 1];
+        const int64_t lo = a.off[s], hi = a.hi[s];
         if (hi < lo || lo < a.base || hi > a.end) {
             atomicOr(&st->error, 1u);
         } else {
@@ -162,7 +163,7 @@ __global__ __launch_bounds__(256) void k_seg_place(const SegArgs *ap, SegState *
     int b = -1;
     uint32_t mine = 0;
     if (s < a.nseg) {
-        const int64_t lo = a.off[s], hi = a.off[s + 1];
+        const int64_t lo = a.off[s], hi = a.hi[s];
         if (hi >= lo && lo >= a.base && hi <= a.end) b = seg_bucket((uint32_t)(hi - lo), a.a_max, a.b_max, a.xl_min);
         if (b >= 0) mine = atomicAdd(&s_c[b], 1u);
     }
@@ -200,7 +201,7 @@ __global__ __launch_bounds__(SEG_W * 64) void k_seg_sort(const SegArgs *ap, SegS
         if (item >= nitems) break;
         if (item < short0) {
             const int64_t s = a.list[item];
-            const int64_t lo = a.off[s], len = a.off[s + 1] - lo;
+            const int64_t lo = a.off[s], len = a.hi[s] - lo;
             if (item < med0)
                 sort_long<DT, SEG_W, IPT_B>(keys + lo, tmp + (lo - a.base), (uint32_t)len, sm.lng);
             else
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(SEG_W * 64) void k_seg_sort(const SegArgs *ap, SegS
             const uint32_t g = (item - short0) * SEG_W + w;
             if (g < nshort) {
                 const int64_t s = a.list[short0 + g];
-                const int64_t lo = a.off[s], len = a.off[s + 1] - lo;
+                const int64_t lo = a.off[s], len = a.hi[s] - lo;
                 lds_sort_tile<DT, false, 1, IPT_A>(keys + lo, keys + lo, nullptr, (uint32_t)len, sm.shrt[w], lane);
             }
         }
@@ -245,7 +246,7 @@ __global__ __launch_bounds__(1024) void k_xl_prefix(const SegArgs *ap, SegState 
         uint32_t v = 0;
         if (i < cnt) {
             const int64_t s = a.list[first + i];
-            const int64_t len = a.off[s + 1] - a.off[s];
+            const int64_t len = a.hi[s] - a.off[s];
             v = (uint32_t)((len + XL_TILE - 1) / XL_TILE);
         }
         const uint32_t incl = wave_incl_scan(v);
@@ -311,7 +312,7 @@ __global__ __launch_bounds__(256) void k_xl_hist(const SegArgs *ap, SegState *st
             }
             cur = i;
             const int64_t s = a.list[first + i];
-            const int64_t lo = a.off[s], len = a.off[s + 1] - lo;
+            const int64_t lo = a.off[s], len = a.hi[s] - lo;
             const uint32_t tb = (g - a.xl_pre[i]) * (uint32_t)XL_TILE;
             const uint32_t tv = (uint32_t)min((int64_t)XL_TILE, len - (int64_t)tb);
             for (uint32_t e = tid; e < tv; e += 256) {
@@ -348,7 +349,7 @@ __global__ __launch_bounds__(256) void k_xl_scan(const SegArgs *ap, SegState *st
     const int tid = threadIdx.x;
     for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
         const int64_t s = a.list[first + i];
-        const uint32_t len = (uint32_t)(a.off[s + 1] - a.off[s]);
+        const uint32_t len = (uint32_t)(a.hi[s] - a.off[s]);
         for (int p = 0; p < P; ++p) {
             uint32_t *h = a.xl_hist + ((size_t)i * P + p) * RADIX;
             const uint32_t c = h[tid];
@@ -410,7 +411,7 @@ __global__ __launch_bounds__(XL_W * 64) void k_xl_pass(const SegArgs *ap, SegSta
         const XlDesc desc = a.xl_desc[i];
         if (!((desc.mask >> place) & 1u)) continue;
         const int64_t s = a.list[first + i];
-        const int64_t lo = a.off[s], len = a.off[s + 1] - lo;
+        const int64_t lo = a.off[s], len = a.hi[s] - lo;
         const uint32_t lt = tile - a.xl_pre[i];
         const uint32_t tbase = lt * (uint32_t)TILE;
         const uint32_t tvalid = (uint32_t)min((int64_t)TILE, len - (int64_t)tbase);
@@ -438,32 +439,7 @@ __global__ __launch_bounds__(XL_W * 64) void k_xl_pass(const SegArgs *ap, SegSta
             const int d = tid / K, kk = tid % K;
             uint32_t excl = 0;
             if (lt > 0) {
-                int64_t p = (int64_t)lt - 1;  // local tile index of the predecessor
-                while (true) {
-                    const int64_t pt = p - kk;
-                    uint64_t wv = pt >= 0 ? lb_load(a.xl_lb + (size_t)(tile - lt + pt) * RADIX + d)
-                                          : lb_pack(epoch, LB_INC, 0u);
-                    uint32_t fl = (uint32_t)(wv >> 32) & 3u;
-                    if ((uint32_t)(wv >> 34) != epoch) fl = 0;
-                    uint32_t inc_at = fl == LB_INC ? (uint32_t)kk : (uint32_t)K;
-                    uint32_t notready_at = fl == 0 ? (uint32_t)kk : (uint32_t)K;
-#pragma unroll
-                    for (int o = 1; o < K; o <<= 1) {
-                        inc_at = min(inc_at, (uint32_t)__shfl_xor((int)inc_at, o, 64));
-                        notready_at = min(notready_at, (uint32_t)__shfl_xor((int)notready_at, o, 64));
-                    }
-                    const uint32_t need = inc_at < (uint32_t)K ? inc_at : (uint32_t)K - 1;
-                    if (notready_at <= need) {
-                        __builtin_amdgcn_s_sleep(1);
-                        continue;
-                    }
-                    uint32_t c = (uint32_t)kk <= need ? (uint32_t)wv : 0u;
-#pragma unroll
-                    for (int o = 1; o < K; o <<= 1) c += (uint32_t)__shfl_xor((int)c, o, 64);
-                    excl += c;
-                    if (inc_at < (uint32_t)K) break;
-                    p -= K;
-                }
+                excl = lookback_prefix<K, 4>(a.xl_lb + (size_t)(tile - lt) * RADIX + d, (int64_t)lt - 1, epoch, kk);
                 if (kk == 0) lb_store(lb + d, lb_pack(epoch, LB_INC, excl + s_tot[d]));
             }
             if (kk == 0) s_glob[d] = a.xl_hist[((size_t)i * P + place) * RADIX + d] + excl - s_start[d];
@@ -508,7 +484,7 @@ __global__ __launch_bounds__(256) void k_xl_final(const SegArgs *ap, SegState *s
         if (tile >= ntiles) break;
         if (!(a.xl_desc[i].q & 1u)) continue;
         const int64_t s = a.list[first + i];
-        const int64_t lo = a.off[s], len = a.off[s + 1] - lo;
+        const int64_t lo = a.off[s], len = a.hi[s] - lo;
         const uint32_t tbase = (tile - a.xl_pre[i]) * (uint32_t)XL_TILE;
         const uint32_t tv = (uint32_t)min((int64_t)XL_TILE, len - (int64_t)tbase);
         for (uint32_t e = threadIdx.x; e < tv; e += 256) keys[lo + tbase + e] = tmp[lo - a.base + tbase + e];
@@ -684,22 +660,13 @@ size_t segmented_temp_bytes(int dt, int64_t n, int64_t nseg) {
     return (size_t)n * dtype_bytes(dt) + (size_t)(nseg > 0 ? nseg : 0) * 4 + sizeof(SegArgs) + sizeof(SegState);
 }
 
-ak_status segmented_sort(Workspace *ws, int dt, void *keys, const int64_t *offsets, int64_t nseg) {
+// Sorts the ranges keys[lo[s] .. hi[s]) (base <= lo <= hi <= end, ranges
+// disjoint) through the captured launch sequence; `tmp` holds end - base
+// keys of scratch laid out like keys[base ..).
+static ak_status seg_run(Workspace *ws, int dt, void *keys, const int64_t *lo, const int64_t *hi, int64_t nseg,
+                         int64_t base, int64_t end, void *tmp) {
     hipStream_t s = ws->stream;
-    if (nseg >= (int64_t(1) << 31)) {
-        set_error("nseg >= 2^31");
-        return AK_ERR_INVALID_ARG;
-    }
-    int64_t ends[2] = {0, 0};
-    AK_HIP(hipMemcpyAsync(&ends[0], offsets, 8, hipMemcpyDeviceToHost, s));
-    AK_HIP(hipMemcpyAsync(&ends[1], offsets + nseg, 8, hipMemcpyDeviceToHost, s));
-    AK_HIP(hipStreamSynchronize(s));
-    const int64_t n = ends[1] - ends[0];
-    if (ends[0] < 0 || n < 0 || n >= (int64_t(1) << 32)) {
-        set_error("offsets[nseg] - offsets[0] must be in [0, 2^32) and offsets[0] >= 0");
-        return AK_ERR_INVALID_ARG;
-    }
-    if (n == 0) return AK_OK;
+    const int64_t n = end - base;
     SegTune t;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -722,7 +689,10 @@ ak_status segmented_sort(Workspace *ws, int dt, void *keys, const int64_t *offse
     const size_t off_hist = off_desc + (((size_t)xl_cap * sizeof(XlDesc) + 255) & ~size_t(255));
     const size_t misc2_need = off_hist + (size_t)xl_cap * P * RADIX * 4;
     const size_t lb_words = ((size_t)n / XL_TILE + xl_cap + 1) * RADIX;
-    if ((r = ws_reserve(ws, &ws->misc, &ws->misc_bytes, (size_t)n * kb)) != AK_OK) return r;
+    if (!tmp) {
+        if ((r = ws_reserve(ws, &ws->misc, &ws->misc_bytes, (size_t)n * kb)) != AK_OK) return r;
+        tmp = ws->misc;
+    }
     if ((r = ws_reserve(ws, &ws->misc2, &ws->misc2_bytes, misc2_need)) != AK_OK) return r;
     if (lb_words * 8 > ws->aux_bytes[3]) {
         if ((r = ws_reserve(ws, &ws->aux[3], &ws->aux_bytes[3], lb_words * 8)) != AK_OK) return r;
@@ -739,12 +709,13 @@ ak_status segmented_sort(Workspace *ws, int dt, void *keys, const int64_t *offse
     }
     SegArgs v{};
     v.keys = keys;
-    v.off = offsets;
-    v.tmp = ws->misc;
+    v.off = lo;
+    v.hi = hi;
+    v.tmp = tmp;
     v.list = (int32_t *)ws->misc2;
     v.nseg = nseg;
-    v.base = ends[0];
-    v.end = ends[1];
+    v.base = base;
+    v.end = end;
     v.a_max = a_max;
     v.b_max = b_max;
     v.xl_min = xl_min;
@@ -778,6 +749,31 @@ ak_status segmented_sort(Workspace *ws, int dt, void *keys, const int64_t *offse
     ProfScope ps("segmented_graph", s);
     AK_HIP(hipGraphLaunch(it->second, s));
     return AK_OK;
+}
+
+ak_status segmented_sort(Workspace *ws, int dt, void *keys, const int64_t *offsets, int64_t nseg) {
+    hipStream_t s = ws->stream;
+    if (nseg >= (int64_t(1) << 31)) {
+        set_error("nseg >= 2^31");
+        return AK_ERR_INVALID_ARG;
+    }
+    int64_t ends[2] = {0, 0};
+    AK_HIP(hipMemcpyAsync(&ends[0], offsets, 8, hipMemcpyDeviceToHost, s));
+    AK_HIP(hipMemcpyAsync(&ends[1], offsets + nseg, 8, hipMemcpyDeviceToHost, s));
+    AK_HIP(hipStreamSynchronize(s));
+    const int64_t n = ends[1] - ends[0];
+    if (ends[0] < 0 || n < 0 || n >= (int64_t(1) << 32)) {
+        set_error("offsets[nseg] - offsets[0] must be in [0, 2^32) and offsets[0] >= 0");
+        return AK_ERR_INVALID_ARG;
+    }
+    if (n == 0) return AK_OK;
+    return seg_run(ws, dt, keys, offsets, offsets + 1, nseg, ends[0], ends[1], nullptr);
+}
+
+ak_status segmented_sort_ranges(Workspace *ws, int dt, void *keys, const int64_t *lo, const int64_t *hi,
+                                int64_t nseg, int64_t end, void *tmp) {
+    if (nseg <= 0 || end <= 0) return AK_OK;
+    return seg_run(ws, dt, keys, lo, hi, nseg, 0, end, tmp);
 }
 
 // Device error flag of the segmented sort on this workspace (cleared).

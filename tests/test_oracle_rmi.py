@@ -137,6 +137,35 @@ def test_root_routes_monotone_equal_width():
     assert np.all(np.abs(leaf - np.minimum(np.floor(f * 64), 63)) <= 1)
 
 
+def test_scaled_gradient_finite_differences():
+    """The kernels report the gradient in each leaf's scaled coordinate
+    (a' = a/s, dx' = dx*s); check it against finite differences in a'."""
+    rng = np.random.default_rng(12)
+    keys = np.sort(rng.lognormal(30, 3, size=8000).astype(np.uint64))
+    mdl = rmi.fit(keys, 32)
+    mdl.a = (mdl.a * np.float32(1.03)).astype(np.float32)
+    out = rmi.leaf_grad_scaled(mdl, keys)
+    st, en, _ = rmi.leaf_ranges(mdl, keys)
+    x, _ = rmi.features(keys)
+    checked = 0
+    for i in range(32):
+        s, e = st[i], en[i]
+        if e - s < 3:
+            continue
+        sc = float(out[i, 6])
+        dxs = (x[s:e] - mdl.x0[i]).astype(np.float32).astype(np.float64) * sc
+        y = np.arange(s, e) / keys.size
+        f = lambda ap, b: ((ap * dxs + b - y) ** 2).sum()
+        ap0, b0 = float(mdl.a[i]) / sc, float(mdl.b[i])
+        h = max(abs(ap0), 1e-9) * 1e-6
+        fd = (f(ap0 + h, b0) - f(ap0 - h, b0)) / (2 * h)
+        assert np.isclose(out[i, 1], fd, rtol=1e-5, atol=1e-10), (i, out[i, 1], fd)
+        assert np.isclose(out[i, 3], 2 * (dxs ** 2).sum(), rtol=1e-12)
+        assert 1.0 <= np.abs(dxs).max() < 2.0          # the scale brings max|dx'| into [1, 2)
+        checked += 1
+    assert checked >= 10
+
+
 @pytest.mark.parametrize("dist", ["uniform", "lognormal", "zipf", "f32"])
 def test_codes_monotone_and_balanced(dist):
     rng = np.random.default_rng(8)
