@@ -164,14 +164,18 @@ ak_status ak_sort_learned(void *keys, int64_t n, ak_dtype dtype, const ak_learne
 
 /* -------------------------------------------- learned-model building blocks
  * Exposed so that every step can be checked on its own.  Model buffers are
- * DEVICE float arrays of ak_rmi_model_floats(leaves) floats laid out as
- * [rc, ra, rb, leaves, 0, 0, 0, 0] followed by one 8-float record per leaf
- * [a, b, x0, lo, hi, 0, 0, 0].  For a key with order-preserving unsigned
- * image t: x = float(t) (round to nearest even), r = float(bits of x);
+ * DEVICE float arrays of ak_rmi_model_floats(leaves) = 8 + 4*(leaves+1)
+ * floats laid out as [rc, ra, rb, leaves, 0, 0, 0, 0] followed by leaves+1
+ * records [a, b, x0, lo] (record `leaves` is a sentinel with lo = 1).  For a
+ * key with order-preserving unsigned image t: x = float(t) (round to
+ * nearest even), r = float(bits of x);
  * leaf = clamp(floor(ra*(r - rc) + rb), 0, leaves-1);
- * F = clamp(a*(x - x0) + b, lo, hi); code = min(floor(F * 2^code_bits),
- * 2^code_bits - 1).  Every float operation is single precision, rounded to
- * nearest even, multiply then add (never fused). */
+ * F = clamp(a*(x - x0) + b, lo[leaf], lo[leaf+1]);
+ * code = min(floor(F * 2^code_bits), 2^code_bits - 1).  The upper clamp of
+ * a leaf is the lower clamp of the next, so with a >= 0 and nondecreasing lo
+ * the code never decreases as the key grows.  Every float operation is
+ * single precision, rounded to nearest even, multiply then add (never
+ * fused). */
 size_t ak_rmi_model_floats(int32_t leaves);
 
 /* out[j] = keys[floor(splitmix64(seed, j) * n / 2^64)] for j < m, where

@@ -123,7 +123,9 @@ def features(keys: np.ndarray):
 
 # ------------------------------------------------------------------- model
 class Model:
-    """RMI parameters, all float32 (the dtype the GPU evaluates in)."""
+    """RMI parameters, all float32 (the dtype the GPU evaluates in).  The
+    upper clamp of leaf i is the lower clamp of leaf i+1 (1 for the last
+    leaf), so the leaves' output ranges nest by construction."""
 
     def __init__(self, L: int):
         self.L = int(L)
@@ -134,15 +136,19 @@ class Model:
         self.b = np.zeros(L, np.float32)
         self.x0 = np.zeros(L, np.float32)
         self.lo = np.zeros(L, np.float32)
-        self.hi = np.ones(L, np.float32)
+
+    @property
+    def hi(self) -> np.ndarray:
+        return np.concatenate([self.lo[1:], [np.float32(1)]]).astype(np.float32)
 
     def as_array(self) -> np.ndarray:
-        """Packed layout [rc, ra, rb, L, pad x4, then per leaf (a, b, x0, lo,
-        hi, 0, 0, 0)] -- the device model buffer layout."""
+        """Device layout: [rc, ra, rb, L, 0 x4], then L+1 records
+        (a, b, x0, lo), the last a sentinel with lo = 1."""
         head = np.array([self.rc, self.ra, self.rb, np.float32(self.L), 0, 0, 0, 0], np.float32)
-        leaves = np.zeros((self.L, 8), np.float32)
-        leaves[:, 0], leaves[:, 1], leaves[:, 2] = self.a, self.b, self.x0
-        leaves[:, 3], leaves[:, 4] = self.lo, self.hi
+        leaves = np.zeros((self.L + 1, 4), np.float32)
+        leaves[:self.L, 0], leaves[:self.L, 1], leaves[:self.L, 2] = self.a, self.b, self.x0
+        leaves[:self.L, 3] = self.lo
+        leaves[self.L] = (0, 1, 0, 1)
         return np.concatenate([head, leaves.ravel()])
 
     @staticmethod
@@ -151,8 +157,8 @@ class Model:
         L = int(arr[3])
         m = Model(L)
         m.rc, m.ra, m.rb = arr[0], arr[1], arr[2]
-        lv = arr[8:8 + 8 * L].reshape(L, 8)
-        m.a, m.b, m.x0, m.lo, m.hi = (lv[:, i].copy() for i in range(5))
+        lv = arr[8:8 + 4 * (L + 1)].reshape(L + 1, 4)
+        m.a, m.b, m.x0, m.lo = (lv[:L, i].copy() for i in range(4))
         return m
 
 
@@ -172,7 +178,7 @@ def cdf(model: Model, keys: np.ndarray) -> np.ndarray:
     leaf = route(model, r)
     dx = (x - model.x0[leaf]).astype(f32)
     F = ((model.a[leaf] * dx).astype(f32) + model.b[leaf]).astype(f32)
-    return np.minimum(np.maximum(F, model.lo[leaf]), model.hi[leaf])
+    return np.minimum(np.maximum(F, model.lo[leaf]), model.hi[leaf])   # hi = next leaf's lo
 
 
 def codes(model: Model, keys: np.ndarray, cb: int) -> np.ndarray:
@@ -236,8 +242,7 @@ def fit_leaves(model: Model, sorted_keys: np.ndarray) -> None:
     f32 = np.float32
     for i in range(model.L):
         s, e = int(st[i]), int(en[i])
-        model.lo[i] = f32(f32(s) / f32(m))
-        model.hi[i] = f32(f32(e) / f32(m))
+        model.lo[i] = f32(f32(s) / f32(m))     # the upper clamp is lo[i+1] = en/m
         if e == s:
             model.a[i], model.b[i], model.x0[i] = 0, model.lo[i], 0
             continue
@@ -260,11 +265,12 @@ def untrained(keys_min, keys_max, L: int) -> Model:
     the smallest and largest key; every key in leaf 0."""
     mdl = Model(L)
     x = to_f32_rne(key_image(np.array([keys_min, keys_max])))
-    width = np.float64(x[1]) - np.float64(x[0])
-    mdl.x0[:] = x[0]
-    mdl.a[0] = np.float32(1.0 / width) if width > 0 else np.float32(0)
-    mdl.lo[:] = 0
-    mdl.hi[:] = 1
+    width = np.float32(x[1] - x[0])
+    mdl.x0[0] = x[0]
+    mdl.a[0] = np.float32(np.float32(1.0) / np.float32(width)) if width > 0 else np.float32(0)
+    mdl.lo[0] = 0
+    mdl.lo[1:] = 1          # unused leaves; leaf 0 clamps to [0, 1]
+    mdl.b[1:] = 1
     return mdl
 
 

@@ -326,7 +326,7 @@ ak_status ak_sort_learned(void *keys, int64_t n, ak_dtype dtype, const ak_learne
     return learned_sort(ws, dtype, keys, n, &c, stats);
 }
 
-size_t ak_rmi_model_floats(int32_t leaves) { return leaves > 0 ? 8 + 8 * (size_t)leaves : 0; }
+size_t ak_rmi_model_floats(int32_t leaves) { return leaves > 0 ? 8 + 4 * ((size_t)leaves + 1) : 0; }
 
 ak_status ak_learned_sample(const void *keys, int64_t n, ak_dtype dtype, uint64_t seed, int64_t m, void *out,
                             ak_stream_t stream) {

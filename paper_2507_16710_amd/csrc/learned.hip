@@ -79,14 +79,11 @@ __global__ void k_rmi_untrained(const typename KT<DT>::U *sorted, uint32_t m, in
         h.L = (float)L;
         *reinterpret_cast<RmiHead *>(model) = h;
     }
-    if (i < L) {
-        RmiLeaf lf{};
-        lf.x0 = x0;
+    if (i <= L) {
         const float width = __fsub_rn(x1, x0);
-        lf.a = (i == 0 && width > 0.f) ? __fdiv_rn(1.0f, width) : 0.f;
-        lf.b = 0.f;
-        lf.lo = 0.f;
-        lf.hi = 1.f;
+        RmiLeaf lf;
+        if (i == 0) lf = make_float4(width > 0.f ? __fdiv_rn(1.0f, width) : 0.f, 0.f, x0, 0.f);
+        else lf = make_float4(0.f, 1.f, 0.f, 1.f);
         reinterpret_cast<RmiLeaf *>(model + 8)[i] = lf;
     }
 }
@@ -109,48 +106,47 @@ __global__ void k_rmi_bounds(const typename KT<DT>::U *sorted, uint32_t m, const
     st[i] = lo;
 }
 
-// Leaf setup: output range [st/m, en/m], centre x0 = middle sample, slope
-// scale s = 2^-e with 2^e <= max |x - x0| over the leaf (a power of two, so
-// scaled and unscaled products round identically), a = b = 0.
+// Leaf setup: lower clamp st/m (the upper one is the next leaf's lower
+// clamp, en/m; the sentinel record L has lo = 1), centre x0 = middle
+// sample, a = b = 0, and the slope scale s = 2^-e with 2^e <= max |x - x0|
+// < 2^(e+1) over the leaf's samples (a power of two, so scaled and
+// unscaled products round identically; 1 for an empty or flat leaf).
 template <int DT>
-__global__ void k_rmi_leaf_init(const typename KT<DT>::U *sorted, uint32_t m, const uint32_t *st, float *model) {
+__device__ __forceinline__ float leaf_scale_of(const typename KT<DT>::U *sorted, uint32_t s, uint32_t e, float x0) {
+    if (e <= s) return 1.f;
+    const float d0 = fabsf(__fsub_rn(to_f32(KT<DT>::image(sorted[s])), x0));
+    const float d1 = fabsf(__fsub_rn(to_f32(KT<DT>::image(sorted[e - 1])), x0));
+    const float dm = fmaxf(d0, d1);
+    return dm > 0.f ? ldexpf(1.0f, -ilogbf(dm)) : 1.f;
+}
+
+template <int DT>
+__global__ void k_rmi_leaf_init(const typename KT<DT>::U *sorted, uint32_t m, const uint32_t *st, float *model,
+                                float *scales) {
     const int L = (int)reinterpret_cast<const RmiHead *>(model)->L;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= L) return;
+    if (i > L) return;
     RmiLeaf *lf = reinterpret_cast<RmiLeaf *>(model + 8) + i;
-    const uint32_t s = st[i], e = st[i + 1];
-    RmiLeaf v{};
-    v.lo = __fdiv_rn((float)s, (float)m);
-    v.hi = __fdiv_rn((float)e, (float)m);
-    v.pad0 = 1.f;
-    if (e == s) {
-        v.b = v.lo;
-    } else {
-        v.x0 = to_f32(KT<DT>::image(sorted[s + (e - s - 1) / 2]));
-        const float d0 = fabsf(__fsub_rn(to_f32(KT<DT>::image(sorted[s])), v.x0));
-        const float d1 = fabsf(__fsub_rn(to_f32(KT<DT>::image(sorted[e - 1])), v.x0));
-        const float dm = fmaxf(d0, d1);
-        v.pad0 = dm > 0.f ? ldexpf(1.0f, -ilogbf(dm)) : 1.f;
+    if (i == L) {
+        *lf = make_float4(0.f, 1.f, 0.f, __fdiv_rn((float)m, (float)m));
+        return;
     }
-    *lf = v;
+    const uint32_t s = st[i], e = st[i + 1];
+    const float lo = __fdiv_rn((float)s, (float)m);
+    float x0 = 0.f;
+    if (e > s) x0 = to_f32(KT<DT>::image(sorted[s + (e - s - 1) / 2]));
+    *lf = make_float4(0.f, e > s ? 0.f : lo, x0, lo);
+    scales[i] = leaf_scale_of<DT>(sorted, s, e, x0);
 }
 
 // Scale of every leaf for given parameters (as in k_rmi_leaf_init).
 template <int DT>
-__global__ void k_leaf_scale(const typename KT<DT>::U *sorted, const uint32_t *st, float *model) {
+__global__ void k_leaf_scale(const typename KT<DT>::U *sorted, const uint32_t *st, const float *model,
+                             float *scales) {
     const int L = (int)reinterpret_cast<const RmiHead *>(model)->L;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= L) return;
-    RmiLeaf *lf = reinterpret_cast<RmiLeaf *>(model + 8) + i;
-    const uint32_t s = st[i], e = st[i + 1];
-    float sc = 1.f;
-    if (e > s) {
-        const float d0 = fabsf(__fsub_rn(to_f32(KT<DT>::image(sorted[s])), lf->x0));
-        const float d1 = fabsf(__fsub_rn(to_f32(KT<DT>::image(sorted[e - 1])), lf->x0));
-        const float dm = fmaxf(d0, d1);
-        sc = dm > 0.f ? ldexpf(1.0f, -ilogbf(dm)) : 1.f;
-    }
-    lf->pad0 = sc;
+    scales[i] = leaf_scale_of<DT>(sorted, st[i], st[i + 1], reinterpret_cast<const RmiLeaf *>(model + 8)[i].z);
 }
 
 template <int B>
@@ -171,19 +167,20 @@ __device__ __forceinline__ float block_sum_f(float v, float *s_red) {
 // (in the leaf's scaled coordinates a' = a/s, dx' = dx*s), and the loss.
 template <int DT>
 __global__ __launch_bounds__(256) void k_rmi_fwd(const typename KT<DT>::U *sorted, uint32_t m, const uint32_t *st,
-                                                 const float *model, float *resid, float *stats) {
+                                                 const float *model, const float *scales, float *resid,
+                                                 float *stats) {
     __shared__ float s_red[4];
     const int i = blockIdx.x;
-    const RmiLeaf lf = reinterpret_cast<const RmiLeaf *>(model + 8)[i];
+    const RmiLeaf lf = reinterpret_cast<const RmiLeaf *>(model + 8)[i];  // a, b, x0, lo
     const uint32_t s = st[i], e = st[i + 1];
-    const float sc = lf.pad0;
-    const float a_s = __fdiv_rn(lf.a, sc);  // exact: sc is a power of two
+    const float sc = scales[i];
+    const float a_s = __fdiv_rn(lf.x, sc);  // exact: sc is a power of two
     const float fm = (float)m;
     float loss = 0.f;
     for (uint32_t j = s + threadIdx.x; j < e; j += 256) {
-        const float dx = __fmul_rn(__fsub_rn(to_f32(KT<DT>::image(sorted[j])), lf.x0), sc);
+        const float dx = __fmul_rn(__fsub_rn(to_f32(KT<DT>::image(sorted[j])), lf.z), sc);
         const float y = __fdiv_rn((float)j, fm);
-        const float r = __fsub_rn(__fadd_rn(__fmul_rn(a_s, dx), lf.b), y);
+        const float r = __fsub_rn(__fadd_rn(__fmul_rn(a_s, dx), lf.y), y);
         resid[j] = r;
         loss = __fadd_rn(loss, __fmul_rn(r, r));
     }
@@ -195,15 +192,16 @@ __global__ __launch_bounds__(256) void k_rmi_fwd(const typename KT<DT>::U *sorte
 // (Gauss-Newton = exact Hessian for this least-squares loss).
 template <int DT>
 __global__ __launch_bounds__(256) void k_rmi_bwd(const typename KT<DT>::U *sorted, uint32_t m, const uint32_t *st,
-                                                 const float *model, const float *resid, float *stats) {
+                                                 const float *model, const float *scales, const float *resid,
+                                                 float *stats) {
     __shared__ float s_red[4];
     const int i = blockIdx.x;
     const RmiLeaf lf = reinterpret_cast<const RmiLeaf *>(model + 8)[i];
     const uint32_t s = st[i], e = st[i + 1];
-    const float sc = lf.pad0;
+    const float sc = scales[i];
     float ga = 0.f, gb = 0.f, hxx = 0.f, hx = 0.f;
     for (uint32_t j = s + threadIdx.x; j < e; j += 256) {
-        const float dx = __fmul_rn(__fsub_rn(to_f32(KT<DT>::image(sorted[j])), lf.x0), sc);
+        const float dx = __fmul_rn(__fsub_rn(to_f32(KT<DT>::image(sorted[j])), lf.z), sc);
         const float r = resid[j];
         ga = __fadd_rn(ga, __fmul_rn(r, dx));
         gb = __fadd_rn(gb, r);
@@ -229,14 +227,14 @@ __global__ __launch_bounds__(256) void k_rmi_bwd(const typename KT<DT>::U *sorte
 // Newton step per leaf on the quadratic loss, projected onto a' >= 0 (the
 // monotone set): if the step would make the slope negative, the slope is
 // set to 0 and b takes its optimum for that slope.
-__global__ void k_rmi_update(float *model, const uint32_t *st, const float *stats) {
+__global__ void k_rmi_update(float *model, const uint32_t *st, const float *scales, const float *stats) {
     const int L = (int)reinterpret_cast<const RmiHead *>(model)->L;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= L || st[i + 1] == st[i]) return;
     RmiLeaf *lf = reinterpret_cast<RmiLeaf *>(model + 8) + i;
     const float *g = stats + 8 * i;
-    const float sc = lf->pad0;
-    float a = __fdiv_rn(lf->a, sc), b = lf->b;
+    const float sc = scales[i];
+    float a = __fdiv_rn(lf->x, sc), b = lf->y;
     const float ga = g[1], gb = g[2], h00 = g[3], h01 = g[4], h11 = g[5];
     const float det = h00 * h11 - h01 * h01;
     float na, nb;
@@ -251,19 +249,20 @@ __global__ void k_rmi_update(float *model, const uint32_t *st, const float *stat
         nb = b - (gb - h01 * a) / h11;
         na = 0.f;
     }
-    lf->a = __fmul_rn(na, sc);
-    lf->b = nb;
+    lf->x = __fmul_rn(na, sc);
+    lf->y = nb;
 }
 
 // ------------------------------------------------------------ inference
 template <int DT>
 __global__ __launch_bounds__(256) void k_rmi_codes(const typename KT<DT>::U *keys, uint32_t n, const float *model,
-                                                   int cb, uint32_t *codes) {
-    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
-    if (i >= n) return;
-    const RmiHead h = *reinterpret_cast<const RmiHead *>(model);
-    codes[i] = rmi_code(h, reinterpret_cast<const RmiLeaf *>(model + 8), KT<DT>::image(keys[i]), cb,
-                        (float)(1u << cb));
+                                                   int cb, uint32_t *codes, int staged) {
+    extern __shared__ float4 s_leaves[];
+    const RmiHead h = rmi_head(model);
+    const RmiLeaf *lv = rmi_stage(model, staged ? s_leaves : nullptr);
+    const float scale = (float)(1u << cb);
+    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u)
+        codes[i] = rmi_code(h, lv, KT<DT>::image(keys[i]), cb, scale);
 }
 
 // ------------------------------------------------------ chunk sorting
@@ -326,38 +325,41 @@ __device__ uint32_t piece_boundary(const typename KT<DT>::U *keys, uint32_t n, u
 template <typename U, int W, int IPT>
 struct ChunkSmem {
     SmallSmem<U, false, W, IPT> sort;
-    uint32_t code[W * 64 * IPT + 1];
+    uint32_t wlast[W];  // code of every wave's last element
     uint32_t cut;
     uint32_t bound[2];
+    uint32_t code0;
 };
 
 // One workgroup per piece of the code-ordered array: cuts it at code
 // changes into chunks of at most W*64*IPT keys and sorts each on chip.
+// The model's leaf table is staged in LDS (dynamic shared memory).
 template <int DT, int W, int IPT>
 __global__ __launch_bounds__(W * 64) void k_chunk_sort(typename KT<DT>::U *keys, uint32_t n, const float *model,
-                                                       int cb, uint32_t piece, FbRun *fb, LearnedState *ls) {
+                                                       int cb, uint32_t piece, FbRun *fb, LearnedState *ls,
+                                                       int staged) {
     using U = typename KT<DT>::U;
     constexpr int B = W * 64, CAP = B * IPT;
     __shared__ ChunkSmem<U, W, IPT> sm;
-    const int tid = threadIdx.x;
-    const RmiHead h = *reinterpret_cast<const RmiHead *>(model);
-    const RmiLeaf *lv = reinterpret_cast<const RmiLeaf *>(model + 8);
+    extern __shared__ float4 s_leaves[];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const RmiHead h = rmi_head(model);
+    const RmiLeaf *glv = rmi_leaves(model);
+    const RmiLeaf *lv = rmi_stage(model, staged ? s_leaves : nullptr);
     const float scale = (float)(1u << cb);
     const uint64_t p0 = (uint64_t)blockIdx.x * piece;
     const uint64_t p1 = std::min<uint64_t>(p0 + piece, n);
     if (tid == 0) {
-        sm.bound[0] = piece_boundary<DT>(keys, n, (uint32_t)p0, h, lv, cb, scale);
-        sm.bound[1] = piece_boundary<DT>(keys, n, (uint32_t)p1, h, lv, cb, scale);
+        sm.bound[0] = piece_boundary<DT>(keys, n, (uint32_t)p0, h, glv, cb, scale);
+        sm.bound[1] = piece_boundary<DT>(keys, n, (uint32_t)p1, h, glv, cb, scale);
     }
     __syncthreads();
     uint32_t pos = sm.bound[0];
     const uint32_t end = sm.bound[1];
-    const int lane = tid & 63, w = tid >> 6;
     uint32_t nchunks = 0;
     while (pos < end) {
         const uint32_t len = std::min<uint32_t>(CAP, end - pos);
-        // one read of the chunk: registers (striped) for the sort, codes in
-        // LDS for the cut
+        // one read of the chunk: registers (striped) for the sort and the cut
         U k[IPT];
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
@@ -366,26 +368,48 @@ __global__ __launch_bounds__(W * 64) void k_chunk_sort(typename KT<DT>::U *keys,
         }
         uint32_t cut = end;
         if (pos + len < end) {
+            // code of every element; the element before lane 0 of item j is
+            // lane 63 of item j-1 (or the previous wave's last element)
+            uint32_t c[IPT];
 #pragma unroll
             for (int j = 0; j < IPT; ++j) {
                 const uint32_t e = striped_elem<IPT>(w, j, lane);
-                if (e < len) sm.code[e] = rmi_code(h, lv, KT<DT>::image(k[j]), cb, scale);
+                c[j] = e < len ? rmi_code(h, lv, KT<DT>::image(k[j]), cb, scale) : 0xFFFFFFFFu;
             }
+            if (lane == 63) sm.wlast[w] = c[IPT - 1];
             if (tid == 0) {
-                sm.code[len] = code_at<DT>(keys, pos + len, h, lv, cb, scale);
                 sm.cut = 0;
+                sm.code0 = c[0];
             }
             __syncthreads();
             uint32_t best = 0;
-            for (uint32_t e = 1 + tid; e <= len; e += B)
-                if (sm.code[e] != sm.code[e - 1]) best = e;
+#pragma unroll
+            for (int j = 0; j < IPT; ++j) {
+                const uint32_t e = striped_elem<IPT>(w, j, lane);
+                uint32_t prev = __shfl_up(c[j], 1, 64);
+                if (j > 0) {
+                    const uint32_t prevj = __shfl(c[j > 0 ? j - 1 : 0], 63, 64);
+                    if (lane == 0) prev = prevj;
+                } else if (lane == 0) {
+                    prev = w > 0 ? sm.wlast[w - 1] : c[0];
+                }
+                if (e > 0 && e < len && c[j] != prev) best = e;
+            }
             if (best) atomicMax(&sm.cut, best);
+            __syncthreads();
+            if (tid == 0) {
+                // the last element of the chunk and the one after it
+                const uint32_t e_last = len - 1;
+                const uint32_t cl = rmi_code(h, lv, KT<DT>::image(keys[pos + e_last]), cb, scale);
+                const uint32_t cn = rmi_code(h, lv, KT<DT>::image(keys[pos + len]), cb, scale);
+                if (cn != cl) sm.cut = len;
+            }
             __syncthreads();
             const uint32_t q = sm.cut;
             if (q == 0) {
                 // one code spans past the chunk: hand the whole run to the fallback
                 if (tid == 0) {
-                    const uint32_t run_end = next_code_change<DT>(keys, end, pos + len, sm.code[0], h, lv, cb, scale);
+                    const uint32_t run_end = next_code_change<DT>(keys, end, pos + len, sm.code0, h, glv, cb, scale);
                     const uint32_t slot = atomicAdd(&ls->fb_count, 1u);
                     fb[slot] = FbRun{pos, run_end - pos};
                     sm.cut = run_end;
@@ -453,15 +477,18 @@ __global__ void k_learned_reset(LearnedState *ls, uint32_t *nonconst, uint32_t c
     for (uint32_t k = i; k < cap; k += gridDim.x * blockDim.x) nonconst[k] = 0;
 }
 
-// Top-level bucket histogram (statistics only).
+// Top-level bucket histogram (statistics only); the counters follow the
+// staged leaf table in dynamic LDS.
 template <int DT>
 __global__ __launch_bounds__(256) void k_bucket_hist(const typename KT<DT>::U *keys, uint32_t n, const float *model,
-                                                     int cb, int shift, int nb, uint32_t *hist) {
-    extern __shared__ uint32_t s_h[];
+                                                     int cb, int shift, int nb, uint32_t *hist, int staged) {
+    extern __shared__ float4 s_dyn[];
+    const int L = (int)rmi_head(model).L;
+    uint32_t *s_h = reinterpret_cast<uint32_t *>(s_dyn + (staged ? L + 1 : 0));
     for (int i = threadIdx.x; i < nb; i += 256) s_h[i] = 0;
+    const RmiHead h = rmi_head(model);
+    const RmiLeaf *lv = rmi_stage(model, staged ? s_dyn : nullptr);
     __syncthreads();
-    const RmiHead h = *reinterpret_cast<const RmiHead *>(model);
-    const RmiLeaf *lv = reinterpret_cast<const RmiLeaf *>(model + 8);
     const float scale = (float)(1u << cb);
     for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u)
         atomicAdd(&s_h[rmi_code(h, lv, KT<DT>::image(keys[i]), cb, scale) >> shift], 1u);
@@ -483,42 +510,80 @@ static int code_bits(int64_t n) {
     return std::min(24, std::max(12, lg - 7));
 }
 
+static inline size_t model_floats(int L) { return 8 + 4 * ((size_t)L + 1); }
+
+// Fit scratch: leaf starts (L+1), scales (L), residuals (m), per-leaf sums
+// (8 L); 256-byte aligned pieces in aux[1].
+struct FitBufs {
+    uint32_t *st;
+    float *scales, *resid, *stats;
+    float *model_copy;
+};
+static ak_status fit_scratch(Workspace *ws, uint32_t m, int L, bool with_model, FitBufs *f) {
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t o_sc = al((size_t)(L + 1) * 4);
+    const size_t o_res = o_sc + al((size_t)L * 4);
+    const size_t o_stats = o_res + al((size_t)m * 4);
+    const size_t o_model = o_stats + al((size_t)L * 32);
+    const size_t need = o_model + (with_model ? model_floats(L) * 4 : 0) + 256;
+    ak_status r = ws_reserve(ws, &ws->aux[1], &ws->aux_bytes[1], need);
+    if (r != AK_OK) return r;
+    char *base = (char *)ws->aux[1];
+    f->st = (uint32_t *)base;
+    f->scales = (float *)(base + o_sc);
+    f->resid = (float *)(base + o_res);
+    f->stats = (float *)(base + o_stats);
+    f->model_copy = (float *)(base + o_model);
+    return AK_OK;
+}
+
 template <int DT>
 static ak_status fit_t(Workspace *ws, const void *sorted, uint32_t m, int L, int iters, float *model,
                        bool untrained) {
     using U = typename KT<DT>::U;
     hipStream_t s = ws->stream;
-    ak_status r;
-    const size_t need = (size_t)(L + 1) * 4 + 256 + (size_t)m * 4 + 256 + (size_t)L * 32;
-    if ((r = ws_reserve(ws, &ws->aux[1], &ws->aux_bytes[1], need)) != AK_OK) return r;
-    char *base = (char *)ws->aux[1];
-    uint32_t *st = (uint32_t *)base;
-    float *resid = (float *)(base + (((size_t)(L + 1) * 4 + 255) & ~size_t(255)));
-    float *stats = (float *)((char *)resid + (((size_t)m * 4 + 255) & ~size_t(255)));
     const U *srt = (const U *)sorted;
     const unsigned lg = (unsigned)((L + 256) / 256);
+    ProfScope ps("rmi_fit", s);
     if (untrained) {
         hipLaunchKernelGGL((k_rmi_untrained<DT>), dim3(lg), dim3(256), 0, s, srt, m, L, model);
         AK_LAUNCH_CHECK("k_rmi_untrained");
         return AK_OK;
     }
+    FitBufs f;
+    ak_status r = fit_scratch(ws, m, L, false, &f);
+    if (r != AK_OK) return r;
     hipLaunchKernelGGL((k_rmi_root<DT>), dim3(1), dim3(64), 0, s, srt, m, L, model);
     AK_LAUNCH_CHECK("k_rmi_root");
-    hipLaunchKernelGGL((k_rmi_bounds<DT>), dim3(lg), dim3(256), 0, s, srt, m, (const float *)model, st);
+    hipLaunchKernelGGL((k_rmi_bounds<DT>), dim3(lg), dim3(256), 0, s, srt, m, (const float *)model, f.st);
     AK_LAUNCH_CHECK("k_rmi_bounds");
-    hipLaunchKernelGGL((k_rmi_leaf_init<DT>), dim3(lg), dim3(256), 0, s, srt, m, (const uint32_t *)st, model);
+    hipLaunchKernelGGL((k_rmi_leaf_init<DT>), dim3(lg), dim3(256), 0, s, srt, m, (const uint32_t *)f.st, model,
+                       f.scales);
     AK_LAUNCH_CHECK("k_rmi_leaf_init");
     for (int it = 0; it < iters; ++it) {
-        hipLaunchKernelGGL((k_rmi_fwd<DT>), dim3(L), dim3(256), 0, s, srt, m, (const uint32_t *)st,
-                           (const float *)model, resid, stats);
+        hipLaunchKernelGGL((k_rmi_fwd<DT>), dim3(L), dim3(256), 0, s, srt, m, (const uint32_t *)f.st,
+                           (const float *)model, (const float *)f.scales, f.resid, f.stats);
         AK_LAUNCH_CHECK("k_rmi_fwd");
-        hipLaunchKernelGGL((k_rmi_bwd<DT>), dim3(L), dim3(256), 0, s, srt, m, (const uint32_t *)st,
-                           (const float *)model, (const float *)resid, stats);
+        hipLaunchKernelGGL((k_rmi_bwd<DT>), dim3(L), dim3(256), 0, s, srt, m, (const uint32_t *)f.st,
+                           (const float *)model, (const float *)f.scales, (const float *)f.resid, f.stats);
         AK_LAUNCH_CHECK("k_rmi_bwd");
-        hipLaunchKernelGGL(k_rmi_update, dim3(lg), dim3(256), 0, s, model, (const uint32_t *)st,
-                           (const float *)stats);
+        hipLaunchKernelGGL(k_rmi_update, dim3(lg), dim3(256), 0, s, model, (const uint32_t *)f.st,
+                           (const float *)f.scales, (const float *)f.stats);
         AK_LAUNCH_CHECK("k_rmi_update");
     }
+    return AK_OK;
+}
+
+static ak_status read_leaves(hipStream_t s, const float *model, int *L) {
+    float head[8];
+    AK_HIP(hipMemcpyAsync(head, model, sizeof(head), hipMemcpyDeviceToHost, s));
+    AK_HIP(hipStreamSynchronize(s));
+    const float lf = head[3];
+    if (!(lf >= 1.f && lf <= 65536.f) || lf != (float)(int)lf) {
+        set_error("model has a bad leaf count");
+        return AK_ERR_INVALID_ARG;
+    }
+    *L = (int)lf;
     return AK_OK;
 }
 
@@ -526,36 +591,25 @@ template <int DT>
 static ak_status leaf_grad_t(Workspace *ws, const void *sorted, uint32_t m, const float *model_in, float *out) {
     using U = typename KT<DT>::U;
     hipStream_t s = ws->stream;
-    float head[8];
-    AK_HIP(hipMemcpyAsync(head, model_in, sizeof(head), hipMemcpyDeviceToHost, s));
-    AK_HIP(hipStreamSynchronize(s));
-    const int L = (int)head[3];
-    if (L <= 0 || L > 65536) {
-        set_error("model has a bad leaf count");
-        return AK_ERR_INVALID_ARG;
-    }
-    ak_status r;
-    const size_t mbytes = (8 + 8 * (size_t)L) * 4;
-    const size_t need = (size_t)(L + 1) * 4 + 256 + (size_t)m * 4 + 256 + mbytes;
-    if ((r = ws_reserve(ws, &ws->aux[1], &ws->aux_bytes[1], need)) != AK_OK) return r;
-    char *base = (char *)ws->aux[1];
-    uint32_t *st = (uint32_t *)base;
-    float *resid = (float *)(base + (((size_t)(L + 1) * 4 + 255) & ~size_t(255)));
-    float *model = (float *)((char *)resid + (((size_t)m * 4 + 255) & ~size_t(255)));
-    // the scale of each leaf is derived from the samples (as in a fit); the
-    // given parameters (a, b, x0) are used as they are
-    AK_HIP(hipMemcpyAsync(model, model_in, mbytes, hipMemcpyDeviceToDevice, s));
+    int L = 0;
+    ak_status r = read_leaves(s, model_in, &L);
+    if (r != AK_OK) return r;
+    FitBufs f;
+    if ((r = fit_scratch(ws, m, L, false, &f)) != AK_OK) return r;
     const U *srt = (const U *)sorted;
     const unsigned lg = (unsigned)((L + 256) / 256);
-    hipLaunchKernelGGL((k_rmi_bounds<DT>), dim3(lg), dim3(256), 0, s, srt, m, (const float *)model, st);
+    // leaf ranges and scales come from the samples (as in a fit); the given
+    // parameters (a, b, x0) are used as they are
+    hipLaunchKernelGGL((k_rmi_bounds<DT>), dim3(lg), dim3(256), 0, s, srt, m, model_in, f.st);
     AK_LAUNCH_CHECK("k_rmi_bounds");
-    hipLaunchKernelGGL((k_leaf_scale<DT>), dim3(lg), dim3(256), 0, s, srt, (const uint32_t *)st, model);
+    hipLaunchKernelGGL((k_leaf_scale<DT>), dim3(lg), dim3(256), 0, s, srt, (const uint32_t *)f.st, model_in,
+                       f.scales);
     AK_LAUNCH_CHECK("k_leaf_scale");
-    hipLaunchKernelGGL((k_rmi_fwd<DT>), dim3(L), dim3(256), 0, s, srt, m, (const uint32_t *)st,
-                       (const float *)model, resid, out);
+    hipLaunchKernelGGL((k_rmi_fwd<DT>), dim3(L), dim3(256), 0, s, srt, m, (const uint32_t *)f.st, model_in,
+                       (const float *)f.scales, f.resid, out);
     AK_LAUNCH_CHECK("k_rmi_fwd");
-    hipLaunchKernelGGL((k_rmi_bwd<DT>), dim3(L), dim3(256), 0, s, srt, m, (const uint32_t *)st,
-                       (const float *)model, (const float *)resid, out);
+    hipLaunchKernelGGL((k_rmi_bwd<DT>), dim3(L), dim3(256), 0, s, srt, m, (const uint32_t *)f.st, model_in,
+                       (const float *)f.scales, (const float *)f.resid, out);
     AK_LAUNCH_CHECK("k_rmi_bwd");
     return AK_OK;
 }
@@ -583,7 +637,7 @@ static ak_status learned_t(Workspace *ws, void *keys, int64_t n64, const ak_lear
     ak_status r;
     // aux[0]: sample keys | model | learned state | fallback runs | flags
     const size_t off_model = ((size_t)m * sizeof(U) + 255) & ~size_t(255);
-    const size_t off_state = off_model + (((8 + 8 * (size_t)L) * 4 + 255) & ~size_t(255));
+    const size_t off_state = off_model + ((model_floats(L) * 4 + 255) & ~size_t(255));
     const size_t off_fb = off_state + 256;
     const size_t off_nc = off_fb + (((size_t)fb_cap * sizeof(FbRun) + 255) & ~size_t(255));
     const size_t off_lo = off_nc + (((size_t)fb_cap * 4 + 255) & ~size_t(255));
@@ -610,14 +664,15 @@ static ak_status learned_t(Workspace *ws, void *keys, int64_t n64, const ak_lear
     // 2. fit
     if ((r = fit_t<DT>(ws, sample, m, L, cfg->train_iters, model, cfg->untrained != 0)) != AK_OK) return r;
     // 3. order by code
-    if ((r = code_partition(ws, DT, keys, n, model, cb, 2)) != AK_OK) return r;
+    if ((r = code_partition(ws, DT, keys, n, model, L, cb, 2)) != AK_OK) return r;
     // 4. chunks on chip
     const uint32_t pieces_target = (uint32_t)num_cus() * 16;
     uint32_t piece = std::max<uint32_t>((uint32_t)CAP * 4, (n + pieces_target - 1) / pieces_target);
     const uint32_t npieces = (n + piece - 1) / piece;
+    const size_t stage = rmi_stage_bytes(L);
     ProfScope ps_chunk("chunk_sort", s);
-    hipLaunchKernelGGL((k_chunk_sort<DT, CW, CIPT>), dim3(npieces), dim3(CW * 64), 0, s, (U *)keys, n,
-                       (const float *)model, cb, piece, fb, ls);
+    hipLaunchKernelGGL((k_chunk_sort<DT, CW, CIPT>), dim3(npieces), dim3(CW * 64), stage, s, (U *)keys, n,
+                       (const float *)model, cb, piece, fb, ls, (int)(stage > 0));
     AK_LAUNCH_CHECK("k_chunk_sort");
     // 5. fallback runs: radix-sorted as segments (runs of one repeated key
     // only cost the histogram read there: every digit place is trivial)
@@ -642,8 +697,8 @@ static ak_status learned_t(Workspace *ws, void *keys, int64_t n64, const ak_lear
         hipLaunchKernelGGL(k_fb_const, dim3(fgrid), dim3(256), 0, s, (const FbRun *)fb, ls,
                            (const uint32_t *)nonconst);
         AK_LAUNCH_CHECK("k_fb_const");
-        hipLaunchKernelGGL((k_bucket_hist<DT>), dim3(num_cus() * 4), dim3(256), (size_t)nb * 4, s, (const U *)keys,
-                           n, (const float *)model, cb, cb - bl, nb, hist);
+        hipLaunchKernelGGL((k_bucket_hist<DT>), dim3(num_cus() * 4), dim3(256), stage + (size_t)nb * 4, s,
+                           (const U *)keys, n, (const float *)model, cb, cb - bl, nb, hist, (int)(stage > 0));
         AK_LAUNCH_CHECK("k_bucket_hist");
         LearnedState hls;
         std::vector<uint32_t> hh(nb);
@@ -723,8 +778,13 @@ ak_status rmi_leaf_grad(Workspace *ws, int dt, const void *sorted, int64_t m, co
 template <int DT>
 static ak_status codes_t(hipStream_t s, const void *keys, int64_t n, const float *model, int cb, uint32_t *codes) {
     using U = typename KT<DT>::U;
-    hipLaunchKernelGGL((k_rmi_codes<DT>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (const U *)keys,
-                       (uint32_t)n, model, cb, codes);
+    int L = 0;
+    ak_status r = read_leaves(s, model, &L);
+    if (r != AK_OK) return r;
+    const size_t stage = rmi_stage_bytes(L);
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, (int64_t)num_cus() * 8);
+    hipLaunchKernelGGL((k_rmi_codes<DT>), dim3(grid), dim3(256), stage, s, (const U *)keys, (uint32_t)n, model, cb,
+                       codes, (int)(stage > 0));
     AK_LAUNCH_CHECK("k_rmi_codes");
     return AK_OK;
 }

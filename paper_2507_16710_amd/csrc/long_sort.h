@@ -63,14 +63,31 @@ __device__ void sort_long(typename KT<DT>::U *keys, typename KT<DT>::U *tmp, uin
         const U *src = (j & 1) ? tmp : keys;
         U *dst = (j & 1) ? keys : tmp;
         block_exscan<B, RADIX>(sm.hist[p], sm.run, sm.wsum, tid);
+        // tiles in order; the next tile's keys are loaded while this one is
+        // ranked and scattered
+        U kn[IPT];
+#pragma unroll
+        for (int jj = 0; jj < IPT; ++jj) {
+            const uint32_t e = striped_elem<IPT>(w, jj, lane);
+            kn[jj] = e < len ? src[e] : U(0);
+        }
         for (uint32_t tb = 0; tb < len; tb += TILE) {
             const uint32_t tvalid = min((uint32_t)TILE, len - tb);
             U k[IPT];
             uint32_t dg[IPT], rk[IPT];
 #pragma unroll
+            for (int jj = 0; jj < IPT; ++jj) k[jj] = kn[jj];
+            const uint32_t nb = tb + TILE;
+            if (nb < len) {
+#pragma unroll
+                for (int jj = 0; jj < IPT; ++jj) {
+                    const uint32_t e = striped_elem<IPT>(w, jj, lane);
+                    kn[jj] = nb + e < len ? src[nb + e] : U(0);
+                }
+            }
+#pragma unroll
             for (int jj = 0; jj < IPT; ++jj) {
                 const uint32_t e = striped_elem<IPT>(w, jj, lane);
-                k[jj] = e < tvalid ? src[tb + e] : U(0);
                 dg[jj] = e < tvalid ? (uint32_t)(KT<DT>::image(k[jj]) >> (8 * p)) & (RADIX - 1) : 0u;
             }
             rank_match<RADIX_BITS, W, IPT>(dg, tvalid, rk, sm.cnt, sm.tot, tid);

@@ -81,7 +81,8 @@ __device__ void scan_places(RunState *st, uint32_t n, int nplaces, uint32_t *s_b
 // high places of small keys).
 template <int DT, bool CODE>
 __global__ __launch_bounds__(256) void k_hist(const typename KT<DT>::U *__restrict__ keys, uint32_t n,
-                                              int nplaces, RunState *st, const float *model, int cb) {
+                                              int nplaces, RunState *st, const float *model, int cb, int staged) {
+    extern __shared__ float4 s_leaves[];
     using U = typename KT<DT>::U;
     constexpr int B = 256, ITEMS = 8;
     __shared__ uint32_t s_h[MAX_PLACES * RADIX];
@@ -91,8 +92,8 @@ __global__ __launch_bounds__(256) void k_hist(const typename KT<DT>::U *__restri
     const RmiLeaf *leaves = nullptr;
     float scale = 0.f;
     if (CODE) {
-        h = *reinterpret_cast<const RmiHead *>(model);
-        leaves = reinterpret_cast<const RmiLeaf *>(model + 8);
+        h = rmi_head(model);
+        leaves = rmi_stage(model, staged ? s_leaves : nullptr);
         scale = (float)(1u << cb);
     }
     __syncthreads();
@@ -171,7 +172,7 @@ __global__ __launch_bounds__(W * 64) void k_onesweep(OnesweepArgs a) {
     uint8_t *s_dig = s_raw + (size_t)TILE * sizeof(U) + (VAL ? (size_t)TILE * 4 : 0);
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    if (tid == 0) s_tile = atomicAdd(&a.st->tile_ctr[a.place], 1u);
+    extern __shared__ float4 s_leaves[];
 
     // buffers of this pass: sort mode ping-pongs between the keys and
     // keys0; sortperm mode reads the const keys first, then keys0/keys1,
@@ -198,12 +199,20 @@ __global__ __launch_bounds__(W * 64) void k_onesweep(OnesweepArgs a) {
     const RmiLeaf *leaves = nullptr;
     float scale = 0.f;
     if (CODE) {
-        h = *reinterpret_cast<const RmiHead *>(a.model);
-        leaves = reinterpret_cast<const RmiLeaf *>(a.model + 8);
+        h = rmi_head(a.model);
+        leaves = rmi_stage(a.model, a.staged ? s_leaves : nullptr);
         scale = (float)(1u << a.cb);
     }
+    // Tiles are claimed in order from the pass counter until none is left:
+    // one tile per workgroup for key digits (grid = tiles), several for code
+    // digits (a persistent grid, so the staged model table is reused).  A
+    // tile's predecessors are always held by running workgroups.
+    const uint32_t ntiles = (a.n + TILE - 1) / TILE;
+    while (true) {
+    if (tid == 0) s_tile = atomicAdd(&a.st->tile_ctr[a.place], 1u);
     __syncthreads();
     const uint32_t tile = s_tile;
+    if (tile >= ntiles) break;
     const uint32_t tbase = tile * (uint32_t)TILE;
     const uint32_t tvalid = min((uint32_t)TILE, a.n - tbase);
 
@@ -282,6 +291,8 @@ __global__ __launch_bounds__(W * 64) void k_onesweep(OnesweepArgs a) {
             if (VAL) __builtin_nontemporal_store(s_vals[i], vdst + pos);
         }
     }
+    __syncthreads();  // the tile's LDS is reused by the next claim
+    }
 }
 
 // ---------------------------------------------------------- finalize
@@ -341,14 +352,18 @@ size_t radix_temp_bytes(int dt, int64_t n, bool perm) {
 }
 
 template <int DT, bool VAL, bool CODE, int V>
-static void launch_pass_v(hipStream_t s, uint32_t tiles, const OnesweepArgs &a) {
+static void launch_pass_v(hipStream_t s, uint32_t tiles, const OnesweepArgs &a, size_t stage) {
     constexpr OsShape sh = OS_SHAPES[key_bits(DT) == 64][VAL][V];
-    hipLaunchKernelGGL((k_onesweep<DT, VAL, sh.w, sh.ipt, CODE>), dim3(tiles), dim3(sh.w * 64), 0, s, a);
+    // code digits: persistent grid (the staged table leaves room for one
+    // workgroup per CU); key digits: one workgroup per tile
+    const uint32_t grid = CODE ? std::min<uint32_t>(tiles, (uint32_t)num_cus() * (stage ? 1 : 2)) : tiles;
+    hipLaunchKernelGGL((k_onesweep<DT, VAL, sh.w, sh.ipt, CODE>), dim3(grid), dim3(sh.w * 64), stage, s, a);
 }
 
 template <int DT, bool VAL, bool CODE>
 static ak_status launch_passes(hipStream_t stream, Workspace *ws, RunState *st, const void *keys_in, void *t0, void *t1,
-                               uint32_t *v0, uint32_t *perm, uint32_t n, int nplaces, const float *model, int cb) {
+                               uint32_t *v0, uint32_t *perm, uint32_t n, int nplaces, const float *model, int cb,
+                               size_t stage) {
     const int var = os_variant(DT, VAL);
     const int TILE = os_tile(DT, VAL);
     const uint32_t tiles = (n + TILE - 1) / TILE;
@@ -363,14 +378,15 @@ static ak_status launch_passes(hipStream_t stream, Workspace *ws, RunState *st, 
     a.n = n;
     a.model = model;
     a.cb = cb;
+    a.staged = stage > 0;
     for (int p = 0; p < nplaces; ++p) {
         a.place = p;
         ProfScope ps(CODE ? "onesweep_code_pass" : (VAL ? "onesweep_pair_pass" : "onesweep_pass"), stream);
         switch (var) {
-        case 0: launch_pass_v<DT, VAL, CODE, 0>(stream, tiles, a); break;
-        case 1: launch_pass_v<DT, VAL, CODE, 1>(stream, tiles, a); break;
-        case 2: launch_pass_v<DT, VAL, CODE, 2>(stream, tiles, a); break;
-        default: launch_pass_v<DT, VAL, CODE, 3>(stream, tiles, a); break;
+        case 0: launch_pass_v<DT, VAL, CODE, 0>(stream, tiles, a, stage); break;
+        case 1: launch_pass_v<DT, VAL, CODE, 1>(stream, tiles, a, stage); break;
+        case 2: launch_pass_v<DT, VAL, CODE, 2>(stream, tiles, a, stage); break;
+        default: launch_pass_v<DT, VAL, CODE, 3>(stream, tiles, a, stage); break;
         }
         AK_LAUNCH_CHECK("k_onesweep");
     }
@@ -382,7 +398,7 @@ static ak_status launch_passes(hipStream_t stream, Workspace *ws, RunState *st, 
 // ones exit at once), and the device-decided copy-back / identity.
 template <int DT, bool CODE>
 static ak_status launch_run(hipStream_t s, Workspace *ws, RunState *st, void *keys, uint32_t *perm, uint32_t n,
-                            int nplaces, const float *model, int cb) {
+                            int nplaces, const float *model, int cb, size_t stage = 0) {
     using U = typename KT<DT>::U;
     const bool pm = perm != nullptr;
     hipLaunchKernelGGL(k_run_init, dim3(1), dim3(256), 0, s, st, ws->epoch_dev);
@@ -390,17 +406,17 @@ static ak_status launch_run(hipStream_t s, Workspace *ws, RunState *st, void *ke
     const uint32_t hgrid = (uint32_t)std::min<int64_t>(((int64_t)n + 2047) / 2048, (int64_t)num_cus() * 8);
     {
         ProfScope ps(CODE ? "code_hist" : "digit_hist", s);
-        hipLaunchKernelGGL((k_hist<DT, CODE>), dim3(hgrid), dim3(256), 0, s, (const U *)keys, n, nplaces, st, model,
-                           cb);
+        hipLaunchKernelGGL((k_hist<DT, CODE>), dim3(hgrid), dim3(256), stage, s, (const U *)keys, n, nplaces, st,
+                           model, cb, (int)(stage > 0));
     }
     AK_LAUNCH_CHECK("k_hist");
     ak_status r;
     if (pm)
         r = launch_passes<DT, true, CODE>(s, ws, st, keys, ws->keys0, ws->keys1, (uint32_t *)ws->vals0, perm, n,
-                                          nplaces, model, cb);
+                                          nplaces, model, cb, stage);
     else
         r = launch_passes<DT, false, CODE>(s, ws, st, keys, ws->keys0, nullptr, nullptr, nullptr, n, nplaces, model,
-                                           cb);
+                                           cb, stage);
     if (r != AK_OK) return r;
     const uint32_t fgrid = (uint32_t)std::min<int64_t>(((int64_t)n + 1023) / 1024, (int64_t)num_cus() * 8);
     if (pm)
@@ -533,7 +549,8 @@ ak_status radix_sort(Workspace *ws, int dt, void *keys, uint32_t *perm, int64_t 
 // after ceil(cb/8) passes the keys are ordered by code, equal codes in
 // input order.
 template <int DT>
-static ak_status code_partition_t(Workspace *ws, void *keys, uint32_t n, const float *model, int cb, int slot) {
+static ak_status code_partition_t(Workspace *ws, void *keys, uint32_t n, const float *model, int L, int cb,
+                                  int slot) {
     using U = typename KT<DT>::U;
     ak_status r;
     if ((r = ws_reserve(ws, &ws->keys0, &ws->keys0_bytes, (size_t)n * sizeof(U))) != AK_OK) return r;
@@ -543,17 +560,19 @@ static ak_status code_partition_t(Workspace *ws, void *keys, uint32_t n, const f
     uint32_t epoch;
     if ((r = ws_next_epoch(ws, &epoch)) != AK_OK) return r;
     const int nplaces = (cb + RADIX_BITS - 1) / RADIX_BITS;
-    return launch_run<DT, true>(ws->stream, ws, ws->state + slot, keys, nullptr, n, nplaces, model, cb);
+    return launch_run<DT, true>(ws->stream, ws, ws->state + slot, keys, nullptr, n, nplaces, model, cb,
+                                rmi_stage_bytes(L));
 }
 
-ak_status code_partition(Workspace *ws, int dt, void *keys, uint32_t n, const float *model, int cb, int slot) {
+ak_status code_partition(Workspace *ws, int dt, void *keys, uint32_t n, const float *model, int L, int cb,
+                         int slot) {
     switch (dt) {
-    case AK_I32: return code_partition_t<AK_I32>(ws, keys, n, model, cb, slot);
-    case AK_I64: return code_partition_t<AK_I64>(ws, keys, n, model, cb, slot);
-    case AK_U32: return code_partition_t<AK_U32>(ws, keys, n, model, cb, slot);
-    case AK_U64: return code_partition_t<AK_U64>(ws, keys, n, model, cb, slot);
-    case AK_F32: return code_partition_t<AK_F32>(ws, keys, n, model, cb, slot);
-    case AK_F64: return code_partition_t<AK_F64>(ws, keys, n, model, cb, slot);
+    case AK_I32: return code_partition_t<AK_I32>(ws, keys, n, model, L, cb, slot);
+    case AK_I64: return code_partition_t<AK_I64>(ws, keys, n, model, L, cb, slot);
+    case AK_U32: return code_partition_t<AK_U32>(ws, keys, n, model, L, cb, slot);
+    case AK_U64: return code_partition_t<AK_U64>(ws, keys, n, model, L, cb, slot);
+    case AK_F32: return code_partition_t<AK_F32>(ws, keys, n, model, L, cb, slot);
+    case AK_F64: return code_partition_t<AK_F64>(ws, keys, n, model, L, cb, slot);
     }
     return AK_ERR_UNSUPPORTED_DTYPE;
 }

@@ -119,38 +119,42 @@ __device__ __forceinline__ void rank_finish(const uint32_t (&dg)[IPT], uint32_t 
 }
 
 // Decoupled look-back of one digit by a group of K adjacent threads (kk =
-// rank in the group), each reading M predecessor words per round trip, so a
-// round covers K*M tiles.  lbd[p * RADIX] is the word of the tile at local
-// index p; `first` is the local index of the nearest predecessor (>= 0).
-// Sums counts down to (and including) the nearest inclusive prefix and
-// returns that exclusive prefix.  Every predecessor publishes, and local
-// tile 0 publishes an inclusive prefix, so the walk ends.
+// rank in the group).  lbd[p * RADIX] is the word of the tile at local index
+// p; `first` is the local index of the nearest predecessor (>= 0).  The
+// first round reads the K nearest predecessors (one word per thread: the
+// common case ends there); later rounds read M words per thread, K*M tiles
+// per round trip.  Sums counts down to (and including) the nearest
+// inclusive prefix and returns that exclusive prefix.  Every predecessor
+// publishes, and local tile 0 publishes an inclusive prefix, so the walk
+// ends.
 template <int K, int M>
 __device__ __forceinline__ uint32_t lookback_prefix(const uint64_t *lbd, int64_t first, uint32_t epoch, int kk) {
-    constexpr uint32_t WIN = K * M;
     uint32_t excl = 0;
     int64_t p0 = first;
+    int mw = 1;  // words per thread this round
     while (true) {
+        const uint32_t win = (uint32_t)(K * mw);
         uint64_t wv[M];
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            const int64_t p = p0 - (int64_t)(kk * M + m);
-            wv[m] = p >= 0 ? lb_load(lbd + (size_t)p * RADIX) : lb_pack(epoch, LB_INC, 0u);
+            const int64_t p = p0 - (int64_t)(kk * mw + m);
+            wv[m] = (m < mw && p >= 0) ? lb_load(lbd + (size_t)p * RADIX) : lb_pack(epoch, LB_INC, 0u);
         }
-        uint32_t inc_at = WIN, notready_at = WIN;
+        uint32_t inc_at = win, notready_at = win;
 #pragma unroll
         for (int m = M - 1; m >= 0; --m) {
+            if (m >= mw) continue;
             uint32_t fl = (uint32_t)(wv[m] >> 32) & 3u;
             if ((uint32_t)(wv[m] >> 34) != epoch) fl = 0;
-            if (fl == LB_INC) inc_at = (uint32_t)(kk * M + m);
-            if (fl == 0) notready_at = (uint32_t)(kk * M + m);
+            if (fl == LB_INC) inc_at = (uint32_t)(kk * mw + m);
+            if (fl == 0) notready_at = (uint32_t)(kk * mw + m);
         }
 #pragma unroll
         for (int o = 1; o < K; o <<= 1) {
             inc_at = min(inc_at, (uint32_t)__shfl_xor((int)inc_at, o, 64));
             notready_at = min(notready_at, (uint32_t)__shfl_xor((int)notready_at, o, 64));
         }
-        const uint32_t need = inc_at < WIN ? inc_at : WIN - 1;
+        const uint32_t need = inc_at < win ? inc_at : win - 1;
         if (notready_at <= need) {
             __builtin_amdgcn_s_sleep(1);
             continue;
@@ -158,12 +162,13 @@ __device__ __forceinline__ uint32_t lookback_prefix(const uint64_t *lbd, int64_t
         uint32_t c = 0;
 #pragma unroll
         for (int m = 0; m < M; ++m)
-            if ((uint32_t)(kk * M + m) <= need) c += (uint32_t)wv[m];
+            if (m < mw && (uint32_t)(kk * mw + m) <= need) c += (uint32_t)wv[m];
 #pragma unroll
         for (int o = 1; o < K; o <<= 1) c += (uint32_t)__shfl_xor((int)c, o, 64);
         excl += c;
-        if (inc_at < WIN) return excl;
-        p0 -= WIN;
+        if (inc_at < win) return excl;
+        p0 -= win;
+        mw = M;
     }
 }
 

@@ -15,6 +15,7 @@ struct OnesweepArgs {
     uint32_t n;
     int place;
     int cb;               // code bits (code digits only)
+    int staged;           // code digits: model table staged in dynamic LDS
 };
 
 // One-sweep tile shapes (W waves x IPT keys per lane).  A few shapes are
@@ -49,6 +50,7 @@ struct SmallSmem {
     uint64_t red[2 * W];
 };
 
-ak_status code_partition(Workspace *ws, int dt, void *keys, uint32_t n, const float *model, int cb, int slot);
+ak_status code_partition(Workspace *ws, int dt, void *keys, uint32_t n, const float *model, int L, int cb,
+                         int slot);
 
 }  // namespace ak

@@ -1,17 +1,18 @@
 // Device evaluation of the learned CDF model (two-level RMI).
 //
-// Model buffer (floats): head [rc, ra, rb, leaves, 0, 0, 0, 0], then one
-// 8-float record per leaf [a, b, x0, lo, hi, 0, 0, 0].  For a key with
-// order-preserving image t:
+// Model buffer (floats): head [rc, ra, rb, L, 0, 0, 0, 0], then L+1 leaf
+// records [a, b, x0, lo] (16 bytes each; record L is a sentinel whose lo is
+// 1).  For a key with order-preserving image t:
 //   x = float(t)              round to nearest even
 //   r = float(bits(x))        x >= 0, so its bits grow with x: a log-like feature
 //   leaf = clamp(floor(ra*(r - rc) + rb), 0, L-1)
-//   F = clamp(a*(x - x0) + b, lo, hi)          (a >= 0, hi_i <= lo_{i+1})
+//   F = clamp(a*(x - x0) + b, lo[leaf], lo[leaf+1])     (a >= 0)
 //   code = min(floor(F * 2^cb), 2^cb - 1)
-// Every step is a nondecreasing function of t, so the code never decreases
-// as the key grows.  Products and sums are rounded separately (__fmul_rn,
-// __fadd_rn) so the compiler cannot fuse them: the integer results must not
-// depend on contraction.
+// The upper clamp of a leaf is the lower clamp of the next one, so the leaf
+// ranges nest by construction and every step is a nondecreasing function
+// of t: the code never decreases as the key grows.  Products and sums are
+// rounded separately (the library is built without FMA contraction): the
+// integer results must not depend on fusing.
 #pragma once
 
 #include "ak_internal.h"
@@ -22,12 +23,19 @@ struct RmiHead {
     float rc, ra, rb, L;
     float pad[4];
 };
-struct RmiLeaf {
-    float a, b, x0, lo, hi, pad0, pad1, pad2;
-};
+using RmiLeaf = float4;  // a, b, x0, lo
+
+constexpr int RMI_LDS_LEAVES = 4096;  // tables up to this size are staged in LDS
 
 __device__ __forceinline__ float to_f32(uint32_t t) { return (float)t; }
 __device__ __forceinline__ float to_f32(uint64_t t) { return (float)t; }
+
+__device__ __forceinline__ const RmiHead &rmi_head(const float *model) {
+    return *reinterpret_cast<const RmiHead *>(model);
+}
+__device__ __forceinline__ const RmiLeaf *rmi_leaves(const float *model) {
+    return reinterpret_cast<const RmiLeaf *>(model + 8);
+}
 
 template <typename U>
 __device__ __forceinline__ int rmi_leaf(const RmiHead &h, U t, float &x) {
@@ -42,10 +50,10 @@ template <typename U>
 __device__ __forceinline__ float rmi_cdf(const RmiHead &h, const RmiLeaf *leaves, U t) {
     float x;
     const int leaf = rmi_leaf(h, t, x);
-    const float4 p0 = *reinterpret_cast<const float4 *>(&leaves[leaf].a);
-    const float hi = leaves[leaf].hi;
-    float F = __fadd_rn(__fmul_rn(p0.x, __fsub_rn(x, p0.z)), p0.y);
-    return fminf(fmaxf(F, p0.w), hi);
+    const RmiLeaf p = leaves[leaf];
+    const float hi = leaves[leaf + 1].w;
+    const float F = __fadd_rn(__fmul_rn(p.x, __fsub_rn(x, p.z)), p.y);
+    return fminf(fmaxf(F, p.w), hi);
 }
 
 template <typename U>
@@ -55,5 +63,20 @@ __device__ __forceinline__ uint32_t rmi_code(const RmiHead &h, const RmiLeaf *le
     const uint32_t top = (1u << cb) - 1u;
     return c < top ? c : top;
 }
+
+// Copies the L+1 leaf records into LDS (`dst`, room for L+1 float4) with
+// the whole block, then waits for the block.  Returns the table to use:
+// the LDS copy if L <= RMI_LDS_LEAVES, else the global one.
+__device__ __forceinline__ const RmiLeaf *rmi_stage(const float *model, RmiLeaf *dst) {
+    const int L = (int)rmi_head(model).L;
+    const RmiLeaf *src = rmi_leaves(model);
+    if (L > RMI_LDS_LEAVES || dst == nullptr) return src;
+    for (int i = threadIdx.x; i <= L; i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+    return dst;
+}
+
+// LDS bytes a kernel needs to stage the table of an L-leaf model.
+inline size_t rmi_stage_bytes(int L) { return L <= RMI_LDS_LEAVES ? (size_t)(L + 1) * sizeof(float4) : 0; }
 
 }  // namespace ak

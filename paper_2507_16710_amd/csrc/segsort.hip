@@ -61,6 +61,7 @@ struct SegArgs {
     uint32_t a_max, b_max, xl_min;
     uint32_t xl_cap;    // room for huge segments in the arrays below
     uint32_t *xl_pre;   // xl_cap+1 tile prefix of the huge segments
+    uint32_t *xl_tseg;  // huge segment of every tile
     uint32_t *xl_hist;  // xl_cap x places x RADIX digit counts
     XlDesc *xl_desc;    // xl_cap descriptors
     uint64_t *xl_lb;    // look-back words, tiles x RADIX
@@ -222,16 +223,6 @@ __global__ __launch_bounds__(SEG_W * 64) void k_seg_sort(const SegArgs *ap, SegS
 // Tiles of all huge segments are numbered consecutively, segment by
 // segment; xl_pre[i] is the first tile of huge segment i.
 
-__device__ __forceinline__ uint32_t xl_seg_of(const uint32_t *pre, uint32_t cnt, uint32_t tile) {
-    uint32_t lo = 0, hi = cnt;  // largest i < cnt with pre[i] <= tile
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) / 2;
-        if (pre[mid] <= tile) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
 __global__ __launch_bounds__(1024) void k_xl_prefix(const SegArgs *ap, SegState *st) {
     const SegArgs a = *ap;
     __shared__ uint32_t s_wsum[16];
@@ -264,6 +255,15 @@ __global__ __launch_bounds__(1024) void k_xl_prefix(const SegArgs *ap, SegState 
         st->xl_tiles = s_carry;
         st->xl_count = cnt;
     }
+}
+
+// Segment of every tile (one entry per tile, so the passes find their
+// segment with one load instead of a search).
+__global__ __launch_bounds__(256) void k_xl_tilemap(const SegArgs *ap, const SegState *st) {
+    const SegArgs a = *ap;
+    const uint32_t cnt = st->xl_count;
+    for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x)
+        for (uint32_t t = a.xl_pre[i] + threadIdx.x; t < a.xl_pre[i + 1]; t += 256) a.xl_tseg[t] = i;
 }
 
 template <int P>
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(256) void k_xl_hist(const SegArgs *ap, SegState *st
         const uint32_t g0 = item * XL_HT, g1 = min(g0 + XL_HT, ntiles);
         int cur = -1;
         for (uint32_t g = g0; g < g1; ++g) {
-            if (tid == 0) s_seg = xl_seg_of(a.xl_pre, cnt, g);
+            if (tid == 0) s_seg = a.xl_tseg[g];
             __syncthreads();
             const int i = (int)s_seg;
             if (cur >= 0 && i != cur) {
@@ -402,7 +402,7 @@ __global__ __launch_bounds__(XL_W * 64) void k_xl_pass(const SegArgs *ap, SegSta
     while (true) {
         if (tid == 0) {
             s_tile = atomicAdd(&st->xl_ctr[2 + place], 1u);
-            s_seg = s_tile < ntiles ? xl_seg_of(a.xl_pre, cnt, s_tile) : 0u;
+            s_seg = s_tile < ntiles ? a.xl_tseg[s_tile] : 0u;
         }
         __syncthreads();
         const uint32_t tile = s_tile, i = s_seg;
@@ -476,7 +476,7 @@ __global__ __launch_bounds__(256) void k_xl_final(const SegArgs *ap, SegState *s
     while (true) {
         if (threadIdx.x == 0) {
             s_tile = atomicAdd(&st->xl_ctr[10], 1u);
-            s_seg = s_tile < ntiles ? xl_seg_of(a.xl_pre, cnt, s_tile) : 0u;
+            s_seg = s_tile < ntiles ? a.xl_tseg[s_tile] : 0u;
         }
         __syncthreads();
         const uint32_t tile = s_tile, i = s_seg;
@@ -608,6 +608,8 @@ static ak_status launch_xl(int grid, hipStream_t s, SegArgs *a, SegState *st) {
     constexpr int P = key_bits(DT) / 8;
     hipLaunchKernelGGL(k_xl_prefix, dim3(1), dim3(1024), 0, s, a, st);
     AK_LAUNCH_CHECK("k_xl_prefix");
+    hipLaunchKernelGGL(k_xl_tilemap, dim3(grid), dim3(256), 0, s, a, st);
+    AK_LAUNCH_CHECK("k_xl_tilemap");
     hipLaunchKernelGGL((k_xl_zero<P>), dim3(grid), dim3(256), 0, s, a, st);
     AK_LAUNCH_CHECK("k_xl_zero");
     hipLaunchKernelGGL((k_xl_hist<DT>), dim3(grid), dim3(256), 0, s, a, st);
@@ -687,8 +689,10 @@ static ak_status seg_run(Workspace *ws, int dt, void *keys, const int64_t *lo, c
     const size_t off_pre = ((size_t)nseg * 4 + 255) & ~size_t(255);
     const size_t off_desc = off_pre + (((size_t)(xl_cap + 1) * 4 + 255) & ~size_t(255));
     const size_t off_hist = off_desc + (((size_t)xl_cap * sizeof(XlDesc) + 255) & ~size_t(255));
-    const size_t misc2_need = off_hist + (size_t)xl_cap * P * RADIX * 4;
-    const size_t lb_words = ((size_t)n / XL_TILE + xl_cap + 1) * RADIX;
+    const size_t max_tiles = (size_t)n / XL_TILE + xl_cap + 1;
+    const size_t off_tseg = off_hist + (((size_t)xl_cap * P * RADIX * 4 + 255) & ~size_t(255));
+    const size_t misc2_need = off_tseg + max_tiles * 4;
+    const size_t lb_words = max_tiles * RADIX;
     if (!tmp) {
         if ((r = ws_reserve(ws, &ws->misc, &ws->misc_bytes, (size_t)n * kb)) != AK_OK) return r;
         tmp = ws->misc;
@@ -723,6 +727,7 @@ static ak_status seg_run(Workspace *ws, int dt, void *keys, const int64_t *lo, c
     v.xl_pre = (uint32_t *)((char *)ws->misc2 + off_pre);
     v.xl_desc = (XlDesc *)((char *)ws->misc2 + off_desc);
     v.xl_hist = (uint32_t *)((char *)ws->misc2 + off_hist);
+    v.xl_tseg = (uint32_t *)((char *)ws->misc2 + off_tseg);
     v.xl_lb = (uint64_t *)ws->aux[3];
     v.xl_lb_words = ws->aux_bytes[3] / 8;
     hipLaunchKernelGGL(k_seg_setargs, dim3(1), dim3(1), 0, s, c.args, v);
