@@ -73,4 +73,4 @@ def test_temp_bytes_predictable():
         assert p >= s + n * kb + n * 4
         assert lib.ak_temp_bytes(2, n, dt) >= n * kb
         assert lib.ak_temp_bytes(3, n, dt) >= s
-    assert lib.ak_rmi_model_floats(4096) == 8 + 8 * 4096
+    assert lib.ak_rmi_model_floats(4096) == 8 + 4 * (4096 + 1)
