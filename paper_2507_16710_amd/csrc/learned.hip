@@ -333,7 +333,7 @@ struct ChunkSmem {
 
 // One workgroup per piece of the code-ordered array: cuts it at code
 // changes into chunks of at most W*64*IPT keys and sorts each on chip.
-// The model's leaf table is staged in LDS (dynamic shared memory).
+// The model's leaf table can be staged in LDS (dynamic shared memory).
 template <int DT, int W, int IPT>
 __global__ __launch_bounds__(W * 64) void k_chunk_sort(typename KT<DT>::U *keys, uint32_t n, const float *model,
                                                        int cb, uint32_t piece, FbRun *fb, LearnedState *ls,
@@ -669,10 +669,13 @@ static ak_status learned_t(Workspace *ws, void *keys, int64_t n64, const ak_lear
     const uint32_t pieces_target = (uint32_t)num_cus() * 16;
     uint32_t piece = std::max<uint32_t>((uint32_t)CAP * 4, (n + pieces_target - 1) / pieces_target);
     const uint32_t npieces = (n + piece - 1) / piece;
+    // The keys of a chunk lie in a narrow code range, so its model reads hit
+    // one or two leaf records in cache: the table is not staged here, which
+    // keeps the workgroup's LDS small enough for several per CU.
     const size_t stage = rmi_stage_bytes(L);
     ProfScope ps_chunk("chunk_sort", s);
-    hipLaunchKernelGGL((k_chunk_sort<DT, CW, CIPT>), dim3(npieces), dim3(CW * 64), stage, s, (U *)keys, n,
-                       (const float *)model, cb, piece, fb, ls, (int)(stage > 0));
+    hipLaunchKernelGGL((k_chunk_sort<DT, CW, CIPT>), dim3(npieces), dim3(CW * 64), 0, s, (U *)keys, n,
+                       (const float *)model, cb, piece, fb, ls, 0);
     AK_LAUNCH_CHECK("k_chunk_sort");
     // 5. fallback runs: radix-sorted as segments (runs of one repeated key
     // only cost the histogram read there: every digit place is trivial)

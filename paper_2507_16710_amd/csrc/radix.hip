@@ -208,7 +208,9 @@ __global__ __launch_bounds__(W * 64) void k_onesweep(OnesweepArgs a) {
     // digits (a persistent grid, so the staged model table is reused).  A
     // tile's predecessors are always held by running workgroups.
     const uint32_t ntiles = (a.n + TILE - 1) / TILE;
-    while (true) {
+    // (a single claim for key digits: no loop keeps per-thread constants
+    // live across tiles, which would cost registers and occupancy)
+    for (int iter = 0; CODE || iter < 1; ++iter) {
     if (tid == 0) s_tile = atomicAdd(&a.st->tile_ctr[a.place], 1u);
     __syncthreads();
     const uint32_t tile = s_tile;

@@ -62,6 +62,9 @@ struct SegArgs {
     uint32_t xl_cap;    // room for huge segments in the arrays below
     uint32_t *xl_pre;   // xl_cap+1 tile prefix of the huge segments
     uint32_t *xl_tseg;  // huge segment of every tile
+    uint32_t xl_tcap;   // room for tiles in xl_tseg and per place in xl_amap
+    uint32_t *xl_apre;  // (places+1) x (xl_cap+1): tile prefix of the segments with work there
+    uint32_t *xl_amap;  // (places+1) x xl_tcap: segment of every such tile
     uint32_t *xl_hist;  // xl_cap x places x RADIX digit counts
     XlDesc *xl_desc;    // xl_cap descriptors
     uint64_t *xl_lb;    // look-back words, tiles x RADIX
@@ -78,6 +81,7 @@ struct SegState {
     uint32_t xl_count;      // huge segments (<= xl_cap)
     uint32_t xl_tiles;      // their tiles
     uint32_t xl_ctr[12];    // work counters: hist, scan, 8 passes, final
+    uint32_t xl_atiles[9];  // tiles with work per place (index 8: the copy back)
     uint32_t epoch;         // look-back epoch base of this call
     uint32_t lb_clear;      // 1: epochs wrapped, clear the look-back words
 };
@@ -266,6 +270,64 @@ __global__ __launch_bounds__(256) void k_xl_tilemap(const SegArgs *ap, const Seg
         for (uint32_t t = a.xl_pre[i] + threadIdx.x; t < a.xl_pre[i + 1]; t += 256) a.xl_tseg[t] = i;
 }
 
+// A huge segment has work at place p < P if that place is active for it,
+// and at "place" P (the copy back) if it ran an odd number of passes.
+template <int P>
+__device__ __forceinline__ bool xl_has_work(const XlDesc &d, int p) {
+    return p < P ? ((d.mask >> p) & 1u) != 0 : (d.q & 1u) != 0;
+}
+
+// Per place, numbers the tiles of the segments with work there
+// consecutively (so a pass claims only tiles it has to process): one
+// workgroup, a running prefix over the segments for each place.
+template <int P>
+__global__ __launch_bounds__(1024) void k_xl_active(const SegArgs *ap, SegState *st) {
+    const SegArgs a = *ap;
+    __shared__ uint32_t s_wsum[16];
+    __shared__ uint32_t s_carry;
+    const uint32_t cnt = st->xl_count;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int p = 0; p <= P; ++p) {
+        uint32_t *pre = a.xl_apre + (size_t)p * (a.xl_cap + 1);
+        if (tid == 0) s_carry = 0;
+        __syncthreads();
+        for (uint32_t base = 0; base < cnt; base += 1024) {
+            const uint32_t i = base + tid;
+            uint32_t v = 0;
+            if (i < cnt && xl_has_work<P>(a.xl_desc[i], p)) v = a.xl_pre[i + 1] - a.xl_pre[i];
+            const uint32_t incl = wave_incl_scan(v);
+            if (lane == 63) s_wsum[w] = incl;
+            __syncthreads();
+            uint32_t run = s_carry;
+            for (int ww = 0; ww < w; ++ww) run += s_wsum[ww];
+            if (i < cnt) pre[i] = run + incl - v;
+            __syncthreads();
+            if (tid == 1023) s_carry = run + incl;
+            __syncthreads();
+        }
+        if (tid == 0) {
+            pre[cnt] = s_carry;
+            st->xl_atiles[p] = s_carry;
+        }
+        __syncthreads();
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_xl_amap(const SegArgs *ap, const SegState *st) {
+    const SegArgs a = *ap;
+    const uint32_t cnt = st->xl_count;
+    for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+        const XlDesc d = a.xl_desc[i];
+        for (int p = 0; p <= P; ++p) {
+            if (!xl_has_work<P>(d, p)) continue;
+            const uint32_t *pre = a.xl_apre + (size_t)p * (a.xl_cap + 1);
+            uint32_t *map = a.xl_amap + (size_t)p * a.xl_tcap;
+            for (uint32_t t = pre[i] + threadIdx.x; t < pre[i + 1]; t += 256) map[t] = i;
+        }
+    }
+}
+
 template <int P>
 __global__ __launch_bounds__(256) void k_xl_zero(const SegArgs *ap, const SegState *st) {
     const SegArgs a = *ap;
@@ -396,23 +458,25 @@ __global__ __launch_bounds__(XL_W * 64) void k_xl_pass(const SegArgs *ap, SegSta
     const SegArgs a = *ap;
     U *keys = (U *)a.keys;
     U *tmp = (U *)a.tmp;
-    const uint32_t cnt = st->xl_count, ntiles = st->xl_tiles, first = st->start[B_XL];
+    const uint32_t ntiles = st->xl_atiles[place], first = st->start[B_XL];
+    const uint32_t *amap = a.xl_amap + (size_t)place * a.xl_tcap;
+    const uint32_t *apre = a.xl_apre + (size_t)place * (a.xl_cap + 1);
     const uint32_t epoch = st->epoch + (uint32_t)place;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // tiles of the segments active at this place only, in segment order
     while (true) {
         if (tid == 0) {
             s_tile = atomicAdd(&st->xl_ctr[2 + place], 1u);
-            s_seg = s_tile < ntiles ? a.xl_tseg[s_tile] : 0u;
+            s_seg = s_tile < ntiles ? amap[s_tile] : 0u;
         }
         __syncthreads();
         const uint32_t tile = s_tile, i = s_seg;
         __syncthreads();
         if (tile >= ntiles) break;
         const XlDesc desc = a.xl_desc[i];
-        if (!((desc.mask >> place) & 1u)) continue;
         const int64_t s = a.list[first + i];
         const int64_t lo = a.off[s], len = a.hi[s] - lo;
-        const uint32_t lt = tile - a.xl_pre[i];
+        const uint32_t lt = tile - apre[i];
         const uint32_t tbase = lt * (uint32_t)TILE;
         const uint32_t tvalid = (uint32_t)min((int64_t)TILE, len - (int64_t)tbase);
         const int jj_pass = desc.j[place];
@@ -472,20 +536,22 @@ __global__ __launch_bounds__(256) void k_xl_final(const SegArgs *ap, SegState *s
     const SegArgs a = *ap;
     U *keys = (U *)a.keys;
     const U *tmp = (const U *)a.tmp;
-    const uint32_t cnt = st->xl_count, ntiles = st->xl_tiles, first = st->start[B_XL];
+    constexpr int P = (int)sizeof(U);
+    const uint32_t ntiles = st->xl_atiles[P], first = st->start[B_XL];
+    const uint32_t *amap = a.xl_amap + (size_t)P * a.xl_tcap;
+    const uint32_t *apre = a.xl_apre + (size_t)P * (a.xl_cap + 1);
     while (true) {
         if (threadIdx.x == 0) {
             s_tile = atomicAdd(&st->xl_ctr[10], 1u);
-            s_seg = s_tile < ntiles ? a.xl_tseg[s_tile] : 0u;
+            s_seg = s_tile < ntiles ? amap[s_tile] : 0u;
         }
         __syncthreads();
         const uint32_t tile = s_tile, i = s_seg;
         __syncthreads();
         if (tile >= ntiles) break;
-        if (!(a.xl_desc[i].q & 1u)) continue;
         const int64_t s = a.list[first + i];
         const int64_t lo = a.off[s], len = a.hi[s] - lo;
-        const uint32_t tbase = (tile - a.xl_pre[i]) * (uint32_t)XL_TILE;
+        const uint32_t tbase = (tile - apre[i]) * (uint32_t)XL_TILE;
         const uint32_t tv = (uint32_t)min((int64_t)XL_TILE, len - (int64_t)tbase);
         for (uint32_t e = threadIdx.x; e < tv; e += 256) keys[lo + tbase + e] = tmp[lo - a.base + tbase + e];
     }
@@ -616,6 +682,10 @@ static ak_status launch_xl(int grid, hipStream_t s, SegArgs *a, SegState *st) {
     AK_LAUNCH_CHECK("k_xl_hist");
     hipLaunchKernelGGL((k_xl_scan<P>), dim3(grid), dim3(256), 0, s, a, st);
     AK_LAUNCH_CHECK("k_xl_scan");
+    hipLaunchKernelGGL((k_xl_active<P>), dim3(1), dim3(1024), 0, s, a, st);
+    AK_LAUNCH_CHECK("k_xl_active");
+    hipLaunchKernelGGL((k_xl_amap<P>), dim3(grid), dim3(256), 0, s, a, st);
+    AK_LAUNCH_CHECK("k_xl_amap");
     for (int p = 0; p < P; ++p) {
         hipLaunchKernelGGL((k_xl_pass<DT>), dim3(grid), dim3(XL_W * 64), 0, s, a, st, p);
         AK_LAUNCH_CHECK("k_xl_pass");
@@ -691,7 +761,9 @@ static ak_status seg_run(Workspace *ws, int dt, void *keys, const int64_t *lo, c
     const size_t off_hist = off_desc + (((size_t)xl_cap * sizeof(XlDesc) + 255) & ~size_t(255));
     const size_t max_tiles = (size_t)n / XL_TILE + xl_cap + 1;
     const size_t off_tseg = off_hist + (((size_t)xl_cap * P * RADIX * 4 + 255) & ~size_t(255));
-    const size_t misc2_need = off_tseg + max_tiles * 4;
+    const size_t off_apre = off_tseg + ((max_tiles * 4 + 255) & ~size_t(255));
+    const size_t off_amap = off_apre + (((size_t)(P + 1) * (xl_cap + 1) * 4 + 255) & ~size_t(255));
+    const size_t misc2_need = off_amap + (size_t)(P + 1) * max_tiles * 4;
     const size_t lb_words = max_tiles * RADIX;
     if (!tmp) {
         if ((r = ws_reserve(ws, &ws->misc, &ws->misc_bytes, (size_t)n * kb)) != AK_OK) return r;
@@ -728,6 +800,9 @@ static ak_status seg_run(Workspace *ws, int dt, void *keys, const int64_t *lo, c
     v.xl_desc = (XlDesc *)((char *)ws->misc2 + off_desc);
     v.xl_hist = (uint32_t *)((char *)ws->misc2 + off_hist);
     v.xl_tseg = (uint32_t *)((char *)ws->misc2 + off_tseg);
+    v.xl_tcap = (uint32_t)max_tiles;
+    v.xl_apre = (uint32_t *)((char *)ws->misc2 + off_apre);
+    v.xl_amap = (uint32_t *)((char *)ws->misc2 + off_amap);
     v.xl_lb = (uint64_t *)ws->aux[3];
     v.xl_lb_words = ws->aux_bytes[3] / 8;
     hipLaunchKernelGGL(k_seg_setargs, dim3(1), dim3(1), 0, s, c.args, v);
