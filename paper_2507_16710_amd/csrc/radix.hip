@@ -203,41 +203,47 @@ __global__ __launch_bounds__(W * 64) void k_onesweep(OnesweepArgs a) {
         leaves = rmi_stage(a.model, a.staged ? s_leaves : nullptr);
         scale = (float)(1u << a.cb);
     }
-    // Tiles are claimed in order from the pass counter until none is left:
-    // one tile per workgroup for key digits (grid = tiles), several for code
-    // digits (a persistent grid, so the staged model table is reused).  A
-    // tile's predecessors are always held by running workgroups.
+    // Tiles are claimed in order from the pass counter, so a tile's
+    // predecessors are always held by running workgroups.  Key digits: one
+    // tile per workgroup (grid = tiles; a loop would keep per-thread
+    // constants live across tiles, costing registers and occupancy).  Code
+    // digits: a persistent grid that reuses the staged model table; each
+    // workgroup claims its next tile and issues that tile's loads before it
+    // waits in the look-back, so the HBM latency overlaps the wait.
     const uint32_t ntiles = (a.n + TILE - 1) / TILE;
-    // (a single claim for key digits: no loop keeps per-thread constants
-    // live across tiles, which would cost registers and occupancy)
-    for (int iter = 0; CODE || iter < 1; ++iter) {
+    auto load_tile = [&](uint32_t t, U(&kk)[IPT], uint32_t(&vv)[IPT]) {
+        const uint32_t tb = t * (uint32_t)TILE;
+        const uint32_t tv = min((uint32_t)TILE, a.n - tb);
+        const U *sp = src + tb + w * 64 * IPT + lane;
+        if (tv == (uint32_t)TILE) {
+#pragma unroll
+            for (int jj = 0; jj < IPT; ++jj) kk[jj] = __builtin_nontemporal_load(sp + jj * 64);
+        } else {
+#pragma unroll
+            for (int jj = 0; jj < IPT; ++jj) {
+                const uint32_t e = striped_elem<IPT>(w, jj, lane);
+                kk[jj] = e < tv ? __builtin_nontemporal_load(sp + jj * 64) : U(0);
+            }
+        }
+        if (VAL) {
+#pragma unroll
+            for (int jj = 0; jj < IPT; ++jj) {
+                const uint32_t e = striped_elem<IPT>(w, jj, lane);
+                vv[jj] = e >= tv ? 0u : (vsrc ? __builtin_nontemporal_load(vsrc + tb + e) : tb + e);
+            }
+        }
+    };
     if (tid == 0) s_tile = atomicAdd(&a.st->tile_ctr[a.place], 1u);
     __syncthreads();
-    const uint32_t tile = s_tile;
-    if (tile >= ntiles) break;
+    uint32_t tile = s_tile;
+    if (tile >= ntiles) return;
+    U k[IPT];
+    uint32_t v[IPT];
+    load_tile(tile, k, v);
+    while (true) {
     const uint32_t tbase = tile * (uint32_t)TILE;
     const uint32_t tvalid = min((uint32_t)TILE, a.n - tbase);
-
-    U k[IPT];
-    uint32_t v[IPT], dg[IPT], rk[IPT];
-    const U *sp = src + tbase + w * 64 * IPT + lane;
-    if (tvalid == (uint32_t)TILE) {
-#pragma unroll
-        for (int jj = 0; jj < IPT; ++jj) k[jj] = __builtin_nontemporal_load(sp + jj * 64);
-    } else {
-#pragma unroll
-        for (int jj = 0; jj < IPT; ++jj) {
-            const uint32_t e = striped_elem<IPT>(w, jj, lane);
-            k[jj] = e < tvalid ? __builtin_nontemporal_load(sp + jj * 64) : U(0);
-        }
-    }
-    if (VAL) {
-#pragma unroll
-        for (int jj = 0; jj < IPT; ++jj) {
-            const uint32_t e = striped_elem<IPT>(w, jj, lane);
-            v[jj] = e >= tvalid ? 0u : (vsrc ? __builtin_nontemporal_load(vsrc + tbase + e) : tbase + e);
-        }
-    }
+    uint32_t dg[IPT], rk[IPT];
 #pragma unroll
     for (int jj = 0; jj < IPT; ++jj) {
         const uint32_t e = striped_elem<IPT>(w, jj, lane);
@@ -253,9 +259,20 @@ __global__ __launch_bounds__(W * 64) void k_onesweep(OnesweepArgs a) {
     const uint32_t epoch = a.st->epoch_base + (uint32_t)a.place;
     for (int d = tid; d < RADIX; d += B)
         lb_store(lb + d, lb_pack(epoch, tile == 0 ? LB_INC : LB_AGG, s_tot[d]));
+    // the next claim (every thread read s_tile before rank_match's barriers;
+    // block_exscan's barriers publish the new value)
+    if (CODE && tid == 0) s_tile = atomicAdd(&a.st->tile_ctr[a.place], 1u);
 
     block_exscan<B, RADIX>(s_tot, s_start, s_wsum, tid);
     rank_finish<RADIX_BITS, W, IPT, uint16_t>(dg, rk, s_cnt, s_start, tid);
+
+    uint32_t next = ntiles;
+    U kn[IPT];
+    uint32_t vn[IPT];
+    if (CODE) {
+        next = s_tile;
+        if (next < ntiles) load_tile(next, kn, vn);
+    }
 
     // decoupled look-back, K*LB_M predecessors per round trip
     {
@@ -293,7 +310,14 @@ __global__ __launch_bounds__(W * 64) void k_onesweep(OnesweepArgs a) {
             if (VAL) __builtin_nontemporal_store(s_vals[i], vdst + pos);
         }
     }
-    __syncthreads();  // the tile's LDS is reused by the next claim
+    if (!CODE || next >= ntiles) break;
+    __syncthreads();  // the tile's LDS is reused by the next one
+    tile = next;
+#pragma unroll
+    for (int jj = 0; jj < IPT; ++jj) {
+        k[jj] = kn[jj];
+        if (VAL) v[jj] = vn[jj];
+    }
     }
 }
 
@@ -327,15 +351,23 @@ __global__ __launch_bounds__(W * 64) void k_small_sort(const typename KT<DT>::U 
 // ------------------------------------------------------------ driver
 // default shape per (64-bit keys, values), from the tuning sweep
 static const int OS_DEFAULT[2][2] = {{0, 0}, {0, 0}};
+// default shape of the code-digit passes per key width
+static const int OS_CODE_DEFAULT[2] = {0, 0};
+
+static int env_variant(const char *name) {
+    const char *e = getenv(name);
+    const int v = (e && *e) ? atoi(e) : -1;
+    return v >= 0 && v < OS_NVAR ? v : -1;
+}
 
 int os_variant(int dt, bool val) {
-    static int forced = -2;
-    if (forced == -2) {
-        const char *e = getenv("AK_OS_VARIANT");
-        forced = (e && *e) ? atoi(e) : -1;
-        if (forced >= OS_NVAR) forced = -1;
-    }
+    static const int forced = env_variant("AK_OS_VARIANT");
     return forced >= 0 ? forced : OS_DEFAULT[key_bits(dt) == 64][val];
+}
+
+int os_code_variant(int dt) {
+    static const int forced = env_variant("AK_OS_CODE_VARIANT");
+    return forced >= 0 ? forced : OS_CODE_DEFAULT[key_bits(dt) == 64];
 }
 
 constexpr int SMALL_W = 4, SMALL_IPT = 16;
@@ -355,7 +387,7 @@ size_t radix_temp_bytes(int dt, int64_t n, bool perm) {
 
 template <int DT, bool VAL, bool CODE, int V>
 static void launch_pass_v(hipStream_t s, uint32_t tiles, const OnesweepArgs &a, size_t stage) {
-    constexpr OsShape sh = OS_SHAPES[key_bits(DT) == 64][VAL][V];
+    constexpr OsShape sh = CODE ? OS_CODE_SHAPES[key_bits(DT) == 64][V] : OS_SHAPES[key_bits(DT) == 64][VAL][V];
     // code digits: persistent grid (the staged table leaves room for one
     // workgroup per CU); key digits: one workgroup per tile
     const uint32_t grid = CODE ? std::min<uint32_t>(tiles, (uint32_t)num_cus() * (stage ? 1 : 2)) : tiles;
@@ -366,8 +398,8 @@ template <int DT, bool VAL, bool CODE>
 static ak_status launch_passes(hipStream_t stream, Workspace *ws, RunState *st, const void *keys_in, void *t0, void *t1,
                                uint32_t *v0, uint32_t *perm, uint32_t n, int nplaces, const float *model, int cb,
                                size_t stage) {
-    const int var = os_variant(DT, VAL);
-    const int TILE = os_tile(DT, VAL);
+    const int var = CODE ? os_code_variant(DT) : os_variant(DT, VAL);
+    const int TILE = CODE ? os_code_tile(DT) : os_tile(DT, VAL);
     const uint32_t tiles = (n + TILE - 1) / TILE;
     OnesweepArgs a{};
     a.keys = const_cast<void *>(keys_in);
@@ -413,10 +445,12 @@ static ak_status launch_run(hipStream_t s, Workspace *ws, RunState *st, void *ke
     }
     AK_LAUNCH_CHECK("k_hist");
     ak_status r;
-    if (pm)
-        r = launch_passes<DT, true, CODE>(s, ws, st, keys, ws->keys0, ws->keys1, (uint32_t *)ws->vals0, perm, n,
-                                          nplaces, model, cb, stage);
-    else
+    if (pm) {
+        if constexpr (CODE) return AK_ERR_INTERNAL;  // code digits order keys only
+        else
+            r = launch_passes<DT, true, false>(s, ws, st, keys, ws->keys0, ws->keys1, (uint32_t *)ws->vals0, perm,
+                                               n, nplaces, model, cb, stage);
+    } else
         r = launch_passes<DT, false, CODE>(s, ws, st, keys, ws->keys0, nullptr, nullptr, nullptr, n, nplaces, model,
                                            cb, stage);
     if (r != AK_OK) return r;
@@ -556,7 +590,7 @@ static ak_status code_partition_t(Workspace *ws, void *keys, uint32_t n, const f
     using U = typename KT<DT>::U;
     ak_status r;
     if ((r = ws_reserve(ws, &ws->keys0, &ws->keys0_bytes, (size_t)n * sizeof(U))) != AK_OK) return r;
-    const int TILE = tile_keys(DT, false);
+    const int TILE = os_code_tile(DT);
     const size_t tiles = (n + TILE - 1) / TILE;
     if ((r = ws_reserve_lookback(ws, tiles * RADIX * 8)) != AK_OK) return r;
     uint32_t epoch;

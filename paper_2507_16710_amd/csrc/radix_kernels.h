@@ -33,9 +33,21 @@ constexpr OsShape OS_SHAPES[2][2][OS_NVAR] = {
     // 64-bit keys: keys only, with values
     {{{16, 4}, {16, 3}, {16, 6}, {16, 8}}, {{16, 4}, {8, 6}, {16, 3}, {16, 6}}},
 };
+// Shapes of the code-digit passes (keys only; one persistent workgroup per
+// CU next to the staged model table, so registers are not the limit).
+// os_code_variant() picks one ($AK_OS_CODE_VARIANT overrides it).
+constexpr OsShape OS_CODE_SHAPES[2][OS_NVAR] = {
+    {{16, 8}, {16, 6}, {16, 4}, {8, 12}},
+    {{16, 4}, {16, 3}, {16, 6}, {8, 8}},
+};
 int os_variant(int dt, bool val);
+int os_code_variant(int dt);
 inline int os_tile(int dt, bool val) {
     const OsShape s = OS_SHAPES[key_bits(dt) == 64][val][os_variant(dt, val)];
+    return s.w * 64 * s.ipt;
+}
+inline int os_code_tile(int dt) {
+    const OsShape s = OS_CODE_SHAPES[key_bits(dt) == 64][os_code_variant(dt)];
     return s.w * 64 * s.ipt;
 }
 
