@@ -144,6 +144,11 @@ __global__ __launch_bounds__(256) void k_hist(const typename KT<DT>::U *__restri
 // an atomic counter (so every tile's predecessors are already running).
 // LDS: the per-wave 16-bit digit counters of the ranking phase share their
 // bytes with the key staging buffer of the scatter phase.
+// Sort mode with a second scratch buffer and an odd number q >= 3 of
+// active passes: route the passes through both scratch buffers so the last
+// one writes the caller's keys.
+__device__ __forceinline__ bool odd_route(int q, const void *t1) { return t1 != nullptr && (q & 1) && q >= 3; }
+
 template <typename U, bool VAL, bool CODE, int W, int IPT>
 struct OsSmem {
     static constexpr int TILE = W * 64 * IPT;
@@ -183,8 +188,16 @@ __global__ __launch_bounds__(W * 64) void k_onesweep(OnesweepArgs a) {
     const uint32_t *vsrc = nullptr;
     uint32_t *vdst = nullptr;
     if (!VAL) {
-        src = (const U *)((j & 1) ? a.t0 : a.keys);
-        dst = (U *)((j & 1) ? a.keys : a.t0);
+        if (odd_route(q, a.t1)) {
+            // keys -> t0 -> t1 -> t0 ... -> t1 -> keys: the last pass writes
+            // the caller's buffer, so no copy back
+            auto buf = [&](int i) { return (U *)((i == 0 || i == q) ? a.keys : ((i & 1) ? a.t0 : a.t1)); };
+            src = buf(j);
+            dst = buf(j + 1);
+        } else {
+            src = (const U *)((j & 1) ? a.t0 : a.keys);
+            dst = (U *)((j & 1) ? a.keys : a.t0);
+        }
     } else {
         src = (const U *)(j == 0 ? a.keys : (((j - 1) & 1) ? a.t1 : a.t0));
         dst = (U *)((j & 1) ? a.t1 : a.t0);
@@ -322,16 +335,16 @@ __global__ __launch_bounds__(W * 64) void k_onesweep(OnesweepArgs a) {
 }
 
 // ---------------------------------------------------------- finalize
-// Sort mode: after an odd number of active passes the result sits in
-// keys0 and is copied back.  Sortperm mode: with no active pass (all keys
+// Sort mode: after a single active pass (or an odd number without the
+// second scratch buffer) the result sits in keys0 and is copied back.  Sortperm mode: with no active pass (all keys
 // equal) the permutation is the identity.
 template <typename U, bool VAL>
-__global__ __launch_bounds__(256) void k_finalize(const RunState *st, U *keys, const U *t0, uint32_t *perm,
-                                                  uint32_t n) {
+__global__ __launch_bounds__(256) void k_finalize(const RunState *st, U *keys, const U *t0, const U *t1,
+                                                  uint32_t *perm, uint32_t n) {
     const int q = st->q;
     const uint32_t stride = gridDim.x * blockDim.x;
     if (!VAL) {
-        if ((q & 1) == 0) return;
+        if ((q & 1) == 0 || odd_route(q, t1)) return;
         for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
             __builtin_nontemporal_store(__builtin_nontemporal_load(t0 + i), keys + i);
     } else {
@@ -380,8 +393,11 @@ size_t radix_temp_bytes(int dt, int64_t n, bool perm) {
     if (n <= small_sort_capacity(dt)) return 0;
     const size_t kb = (size_t)dtype_bytes(dt);
     const size_t tiles = (size_t)((n + tile_keys(dt, perm) - 1) / tile_keys(dt, perm));
-    size_t b = (size_t)n * kb + tiles * RADIX * 8;
-    if (perm) b += (size_t)n * kb + (size_t)n * 4;
+    // two key-sized ping-pong buffers (sort: the second one lets an odd
+    // number of passes end in the caller's buffer; sortperm: the const keys
+    // are never written), the look-back words, and the index buffer
+    size_t b = 2 * (size_t)n * kb + tiles * RADIX * 8;
+    if (perm) b += (size_t)n * 4;
     return b;
 }
 
@@ -451,16 +467,16 @@ static ak_status launch_run(hipStream_t s, Workspace *ws, RunState *st, void *ke
             r = launch_passes<DT, true, false>(s, ws, st, keys, ws->keys0, ws->keys1, (uint32_t *)ws->vals0, perm,
                                                n, nplaces, model, cb, stage);
     } else
-        r = launch_passes<DT, false, CODE>(s, ws, st, keys, ws->keys0, nullptr, nullptr, nullptr, n, nplaces, model,
+        r = launch_passes<DT, false, CODE>(s, ws, st, keys, ws->keys0, ws->keys1, nullptr, nullptr, n, nplaces, model,
                                            cb, stage);
     if (r != AK_OK) return r;
     const uint32_t fgrid = (uint32_t)std::min<int64_t>(((int64_t)n + 1023) / 1024, (int64_t)num_cus() * 8);
     if (pm)
         hipLaunchKernelGGL((k_finalize<U, true>), dim3(fgrid), dim3(256), 0, s, st, (U *)nullptr, (const U *)nullptr,
-                           perm, n);
+                           (const U *)nullptr, perm, n);
     else
         hipLaunchKernelGGL((k_finalize<U, false>), dim3(fgrid), dim3(256), 0, s, st, (U *)keys,
-                           (const U *)ws->keys0, (uint32_t *)nullptr, n);
+                           (const U *)ws->keys0, (const U *)ws->keys1, (uint32_t *)nullptr, n);
     AK_LAUNCH_CHECK("k_finalize");
     return AK_OK;
 }
@@ -524,10 +540,8 @@ static ak_status radix_sort_t(Workspace *ws, void *keys, uint32_t *perm, int64_t
     const size_t kb = sizeof(U);
     ak_status r;
     if ((r = ws_reserve(ws, &ws->keys0, &ws->keys0_bytes, (size_t)n * kb)) != AK_OK) return r;
-    if (pm) {
-        if ((r = ws_reserve(ws, &ws->keys1, &ws->keys1_bytes, (size_t)n * kb)) != AK_OK) return r;
-        if ((r = ws_reserve(ws, &ws->vals0, &ws->vals0_bytes, (size_t)n * 4)) != AK_OK) return r;
-    }
+    if ((r = ws_reserve(ws, &ws->keys1, &ws->keys1_bytes, (size_t)n * kb)) != AK_OK) return r;
+    if (pm && (r = ws_reserve(ws, &ws->vals0, &ws->vals0_bytes, (size_t)n * 4)) != AK_OK) return r;
     const int TILE = tile_keys(DT, pm);
     const size_t tiles = (n + TILE - 1) / TILE;
     if ((r = ws_reserve_lookback(ws, tiles * RADIX * 8)) != AK_OK) return r;
@@ -590,6 +604,7 @@ static ak_status code_partition_t(Workspace *ws, void *keys, uint32_t n, const f
     using U = typename KT<DT>::U;
     ak_status r;
     if ((r = ws_reserve(ws, &ws->keys0, &ws->keys0_bytes, (size_t)n * sizeof(U))) != AK_OK) return r;
+    if ((r = ws_reserve(ws, &ws->keys1, &ws->keys1_bytes, (size_t)n * sizeof(U))) != AK_OK) return r;
     const int TILE = os_code_tile(DT);
     const size_t tiles = (n + TILE - 1) / TILE;
     if ((r = ws_reserve_lookback(ws, tiles * RADIX * 8)) != AK_OK) return r;

@@ -69,8 +69,8 @@ def test_temp_bytes_predictable():
         n = 10_000_000
         s = lib.ak_temp_bytes(0, n, dt)
         p = lib.ak_temp_bytes(1, n, dt)
-        assert n * kb <= s <= n * kb * 1.2
-        assert p >= s + n * kb + n * 4
+        assert 2 * n * kb <= s <= n * kb * 2.2             # two ping-pong buffers + look-back
+        assert p >= 2 * n * kb + n * 4
         assert lib.ak_temp_bytes(2, n, dt) >= n * kb
         assert lib.ak_temp_bytes(3, n, dt) >= s
     assert lib.ak_rmi_model_floats(4096) == 8 + 4 * (4096 + 1)
