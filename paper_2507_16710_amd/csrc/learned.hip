@@ -334,8 +334,11 @@ struct ChunkSmem {
 // One workgroup per piece of the code-ordered array: cuts it at code
 // changes into chunks of at most W*64*IPT keys and sorts each on chip.
 // The model's leaf table can be staged in LDS (dynamic shared memory).
+// Register budget: W/2 waves per SIMD, i.e. two W-wave workgroups per CU
+// (64 VGPRs at W = 16), so one workgroup's barriers overlap the other's
+// loads.
 template <int DT, int W, int IPT>
-__global__ __launch_bounds__(W * 64) void k_chunk_sort(typename KT<DT>::U *keys, uint32_t n, const float *model,
+__global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(W / 2))) void k_chunk_sort(typename KT<DT>::U *keys, uint32_t n, const float *model,
                                                        int cb, uint32_t piece, FbRun *fb, LearnedState *ls,
                                                        int staged) {
     using U = typename KT<DT>::U;
@@ -632,7 +635,7 @@ static ak_status learned_t(Workspace *ws, void *keys, int64_t n64, const ak_lear
     const int L = cfg->leaves;
     const uint32_t m = (uint32_t)sample_count(n64, cfg->sample_frac);
     const int cb = code_bits(n64);
-    constexpr int CW = 4, CIPT = 16, CAP = CW * 64 * CIPT;
+    constexpr int CW = 16, CIPT = 4, CAP = CW * 64 * CIPT;
     const uint32_t fb_cap = n / CAP + 2;
     ak_status r;
     // aux[0]: sample keys | model | learned state | fallback runs | flags
