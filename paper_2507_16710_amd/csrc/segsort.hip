@@ -1,17 +1,19 @@
 // Batched segmented sort: every segment [off[s], off[s+1]) sorted on its own,
-// all segments in one persistent launch.
+// all segments of a class in one persistent launch.
 //
 // Segments are binned by length into work buckets processed largest first:
 //   huge   (>= xl_min keys)       many workgroups: per-segment digit
 //                                 histograms, then one-sweep passes whose
 //                                 look-back stays inside the segment (tiles of
 //                                 all huge segments share persistent grids)
-//   long   (b_max < len < xl_min) one workgroup, multi-pass LSD radix through
-//                                 a scratch copy (one bucket per power of two,
-//                                 longest first, so the tail is short ones)
+//   long   (b_max < len < xl_min) one 1024-thread workgroup, multi-pass LSD
+//                                 radix through a scratch copy (one bucket per
+//                                 power of two, longest first, so the tail is
+//                                 short ones); its own persistent kernel
 //   medium (a_max < len <= b_max) one workgroup, on-chip sort
 //   short  (2 <= len <= a_max)    one wave per segment, on-chip sort
-// The tile shapes (keys per lane of the short and medium classes) are
+// The on-chip classes share a second persistent kernel.  Their tile shapes
+// (keys per lane of the short and medium classes) are
 // template variants chosen from a tuning table written by the autotuner;
 // the class limits and the persistent grid are runtime knobs of the same
 // table.  The launch sequence (reset, count, scan, place, sort) is captured
@@ -75,8 +77,9 @@ struct SegState {
     uint32_t count[NB];
     uint32_t start[NB + 1];
     uint32_t cursor[NB];
-    uint32_t next_item;
+    uint32_t next_item;     // work counter of the on-chip classes
     uint32_t nitems;
+    uint32_t next_long;     // work counter of the long class
     uint32_t error;
     uint32_t xl_count;      // huge segments (<= xl_cap)
     uint32_t xl_tiles;      // their tiles
@@ -117,6 +120,7 @@ __global__ void k_seg_reset(SegState *st) {
     if (t == 0) {
         st->next_item = 0;
         st->nitems = 0;
+        st->next_long = 0;
         uint32_t e = st->epoch + 16;
         st->lb_clear = 0;
         if (e < 16 || e + 16 >= (1u << 30)) {
@@ -179,11 +183,39 @@ __global__ __launch_bounds__(256) void k_seg_place(const SegArgs *ap, SegState *
     if (b >= 0) a.list[st->start[b] + s_base[b] + mine] = (int32_t)s;
 }
 
+// The long class and the on-chip classes run as two persistent kernels so
+// that each gets its own register budget (one kernel holding all three
+// sorts would need the largest of them, with spills).
+constexpr int LONG_W = 16, LONG_IPT = 4;  // long-class tile: 4096 keys
+
+// WPE: waves per SIMD the register allocation aims for: 8 fits two
+// workgroups per CU (a few registers spill), 4 fits one without spills.
+template <int DT, int WPE>
+__global__ __launch_bounds__(LONG_W * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void k_seg_long(
+    const SegArgs *ap, SegState *st) {
+    using U = typename KT<DT>::U;
+    __shared__ LongSmem<U, LONG_W, LONG_IPT> sm;
+    __shared__ uint32_t s_item;
+    const SegArgs a = *ap;
+    U *keys = (U *)a.keys;
+    U *tmp = (U *)a.tmp;
+    const uint32_t first = st->start[B_XL + 1], med0 = st->start[B_MED];
+    while (true) {
+        if (threadIdx.x == 0) s_item = first + atomicAdd(&st->next_long, 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        __syncthreads();
+        if (item >= med0) break;
+        const int64_t s = a.list[item];
+        const int64_t lo = a.off[s], len = a.hi[s] - lo;
+        sort_long<DT, LONG_W, LONG_IPT>(keys + lo, tmp + (lo - a.base), (uint32_t)len, sm);
+    }
+}
+
 template <typename U, int IPT_A, int IPT_B>
 union SegSmem {
     SmallSmem<U, false, SEG_W, IPT_B> med;
     SmallSmem<U, false, 1, IPT_A> shrt[SEG_W];
-    LongSmem<U, SEG_W, IPT_B> lng;
 };
 
 template <int DT, int IPT_A, int IPT_B>
@@ -193,13 +225,11 @@ __global__ __launch_bounds__(SEG_W * 64) void k_seg_sort(const SegArgs *ap, SegS
     __shared__ uint32_t s_item;
     const SegArgs a = *ap;
     U *keys = (U *)a.keys;
-    U *tmp = (U *)a.tmp;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t nitems = st->nitems;
-    const uint32_t first = st->start[B_XL + 1];  // huge segments are sorted by the k_xl_* kernels
     const uint32_t med0 = st->start[B_MED], short0 = st->start[B_SHORT], nshort = st->count[B_SHORT];
     while (true) {
-        if (tid == 0) s_item = first + atomicAdd(&st->next_item, 1u);
+        if (tid == 0) s_item = med0 + atomicAdd(&st->next_item, 1u);
         __syncthreads();
         const uint32_t item = s_item;
         __syncthreads();
@@ -207,10 +237,7 @@ __global__ __launch_bounds__(SEG_W * 64) void k_seg_sort(const SegArgs *ap, SegS
         if (item < short0) {
             const int64_t s = a.list[item];
             const int64_t lo = a.off[s], len = a.hi[s] - lo;
-            if (item < med0)
-                sort_long<DT, SEG_W, IPT_B>(keys + lo, tmp + (lo - a.base), (uint32_t)len, sm.lng);
-            else
-                lds_sort_tile<DT, false, SEG_W, IPT_B>(keys + lo, keys + lo, nullptr, (uint32_t)len, sm.med, tid);
+            lds_sort_tile<DT, false, SEG_W, IPT_B>(keys + lo, keys + lo, nullptr, (uint32_t)len, sm.med, tid);
         } else {
             const uint32_t g = (item - short0) * SEG_W + w;
             if (g < nshort) {
@@ -669,6 +696,28 @@ static ak_status launch_seg_sort(const SegTune &t, dim3 grid, hipStream_t s, con
     return AK_OK;
 }
 
+// Long-class kernel variant: 0 = two workgroups per CU, 1 = one
+// ($AK_SEG_LONG_VARIANT overrides the default).
+static int seg_long_variant() {
+    static const int v = [] {
+        const char *e = getenv("AK_SEG_LONG_VARIANT");
+        return (e && *e) ? (atoi(e) == 1 ? 1 : 0) : 0;
+    }();
+    return v;
+}
+
+template <int DT>
+static ak_status launch_seg_long(hipStream_t s, const SegArgs *a, SegState *st) {
+    if (seg_long_variant() == 0)
+        hipLaunchKernelGGL((k_seg_long<DT, LONG_W / 2>), dim3((unsigned)num_cus() * 2), dim3(LONG_W * 64), 0, s, a,
+                           st);
+    else
+        hipLaunchKernelGGL((k_seg_long<DT, LONG_W / 4>), dim3((unsigned)num_cus()), dim3(LONG_W * 64), 0, s, a,
+                           st);
+    AK_LAUNCH_CHECK("k_seg_long");
+    return AK_OK;
+}
+
 template <int DT>
 static ak_status launch_xl(int grid, hipStream_t s, SegArgs *a, SegState *st) {
     constexpr int P = key_bits(DT) / 8;
@@ -714,6 +763,16 @@ static ak_status seg_launch_all(int dt, const SegTune &t, int64_t nseg, int grid
     case AK_U64: r = launch_xl<AK_U64>(grid, s, a, st); break;
     case AK_F32: r = launch_xl<AK_F32>(grid, s, a, st); break;
     case AK_F64: r = launch_xl<AK_F64>(grid, s, a, st); break;
+    default: r = AK_ERR_UNSUPPORTED_DTYPE;
+    }
+    if (r != AK_OK) return r;
+    switch (dt) {
+    case AK_I32: r = launch_seg_long<AK_I32>(s, a, st); break;
+    case AK_I64: r = launch_seg_long<AK_I64>(s, a, st); break;
+    case AK_U32: r = launch_seg_long<AK_U32>(s, a, st); break;
+    case AK_U64: r = launch_seg_long<AK_U64>(s, a, st); break;
+    case AK_F32: r = launch_seg_long<AK_F32>(s, a, st); break;
+    case AK_F64: r = launch_seg_long<AK_F64>(s, a, st); break;
     default: r = AK_ERR_UNSUPPORTED_DTYPE;
     }
     if (r != AK_OK) return r;
