@@ -42,18 +42,21 @@ __global__ void k_run_init(RunState *st, uint32_t *epoch_dev) {
 // Exclusive digit offsets per place; a place where one digit holds every
 // key is inactive (its pass would be a copy).  Active passes are numbered
 // so that each pass kernel can pick its source and destination buffers
-// without a host round trip.  Run by one workgroup of 256 threads, reading
-// counts that other workgroups accumulated with device-scope atomics.
+// without a host round trip.  Run by one workgroup of B >= 256 threads,
+// reading counts that other workgroups accumulated with device-scope
+// atomics.
+template <int B>
 __device__ void scan_places(RunState *st, uint32_t n, int nplaces, uint32_t *s_buf, uint32_t *s_wsum,
                             int *s_active) {
     const int tid = threadIdx.x;
     for (int p = 0; p < nplaces; ++p) {
-        const uint32_t c = __hip_atomic_load(&st->hist[p][tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int trivial = __syncthreads_or(c == n);
-        s_buf[tid] = c;
+        const uint32_t c =
+            tid < RADIX ? __hip_atomic_load(&st->hist[p][tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+        const int trivial = __syncthreads_or(tid < RADIX && c == n);
+        if (tid < RADIX) s_buf[tid] = c;
         __syncthreads();
-        block_exscan<256, RADIX>(s_buf, s_buf, s_wsum, tid);
-        st->base[p][tid] = s_buf[tid];
+        block_exscan<B, RADIX>(s_buf, s_buf, s_wsum, tid);
+        if (tid < RADIX) st->base[p][tid] = s_buf[tid];
         if (tid == 0) s_active[p] = !trivial;
         __syncthreads();
     }
@@ -79,12 +82,15 @@ __device__ void scan_places(RunState *st, uint32_t n, int nplaces, uint32_t *s_b
 // hold the same digit adds its lane count once instead of 64 conflicting
 // LDS atomics (long runs of equal digits are the common case for the
 // high places of small keys).
+// Code digits use 1024-thread workgroups: the staged model table (64 KB at
+// 4096 leaves) leaves room for two workgroups per CU.
 template <int DT, bool CODE>
-__global__ __launch_bounds__(256) void k_hist(const typename KT<DT>::U *__restrict__ keys, uint32_t n,
-                                              int nplaces, RunState *st, const float *model, int cb, int staged) {
+__global__ __launch_bounds__(CODE ? 1024 : 256) void k_hist(const typename KT<DT>::U *__restrict__ keys, uint32_t n,
+                                                            int nplaces, RunState *st, const float *model, int cb,
+                                                            int staged) {
     extern __shared__ float4 s_leaves[];
     using U = typename KT<DT>::U;
-    constexpr int B = 256, ITEMS = 8;
+    constexpr int B = CODE ? 1024 : 256, ITEMS = 8;
     __shared__ uint32_t s_h[MAX_PLACES * RADIX];
     const int tid = threadIdx.x;
     for (int i = tid; i < MAX_PLACES * RADIX; i += B) s_h[i] = 0;
@@ -128,7 +134,7 @@ __global__ __launch_bounds__(256) void k_hist(const typename KT<DT>::U *__restri
         if (s_h[i]) atomicAdd(&st->hist[i / RADIX][i % RADIX], s_h[i]);
     // the last workgroup to finish turns the counts into digit offsets
     __shared__ int s_last;
-    __shared__ uint32_t s_wsum[4];
+    __shared__ uint32_t s_wsum[B / 64];
     __shared__ int s_active[MAX_PLACES];
     __threadfence();
     __syncthreads();
@@ -136,7 +142,7 @@ __global__ __launch_bounds__(256) void k_hist(const typename KT<DT>::U *__restri
     __syncthreads();
     if (!s_last) return;
     __threadfence();
-    scan_places(st, n, nplaces, s_h, s_wsum, s_active);
+    scan_places<B>(st, n, nplaces, s_h, s_wsum, s_active);
 }
 
 // ----------------------------------------------------- one-sweep pass
@@ -453,10 +459,12 @@ static ak_status launch_run(hipStream_t s, Workspace *ws, RunState *st, void *ke
     const bool pm = perm != nullptr;
     hipLaunchKernelGGL(k_run_init, dim3(1), dim3(256), 0, s, st, ws->epoch_dev);
     AK_LAUNCH_CHECK("k_run_init");
-    const uint32_t hgrid = (uint32_t)std::min<int64_t>(((int64_t)n + 2047) / 2048, (int64_t)num_cus() * 8);
+    constexpr int HB = CODE ? 1024 : 256;
+    const uint32_t hgrid = (uint32_t)std::min<int64_t>(((int64_t)n + HB * 8 - 1) / (HB * 8),
+                                                       (int64_t)num_cus() * (CODE ? 2 : 8));
     {
         ProfScope ps(CODE ? "code_hist" : "digit_hist", s);
-        hipLaunchKernelGGL((k_hist<DT, CODE>), dim3(hgrid), dim3(256), stage, s, (const U *)keys, n, nplaces, st,
+        hipLaunchKernelGGL((k_hist<DT, CODE>), dim3(hgrid), dim3(HB), stage, s, (const U *)keys, n, nplaces, st,
                            model, cb, (int)(stage > 0));
     }
     AK_LAUNCH_CHECK("k_hist");
