@@ -10,10 +10,10 @@
  * with the Julia Base ordering the library adopts by dispatching onto the
  * Base function names (Sec. II): integers by value; floats with
  * -Inf < ... < -0.0 < +0.0 < ... < +Inf < NaN, all NaNs equal (so they keep
- * their input order).  Temporaries are predictable from the input size and
- * can be queried (Sec. II-B, last paragraph: "all temporary arrays ... are
- * exposed").  Device code cannot throw (Sec. II), so every call returns a
- * status code.
+ * their input order).  The paper exposes every temporary buffer to the
+ * caller and makes its size known from the input size ahead of the call
+ * (Sec. II-B, end); here ak_temp_bytes reports it.  Device code cannot throw
+ * (Sec. II), so every call returns a status code.
  *
  * Conventions for every call:
  *   - Array pointers are DEVICE pointers (hipMalloc / torch CUDA tensors) on

@@ -9,8 +9,8 @@
 // as a merge sort in a portable kernel language; this file instead uses
 // 8-bit LSD radix passes because ballots and per-wave LDS counters are
 // available on gfx950 (the paper names wave-level intrinsics as what radix
-// sort needs, Sec. I-B), and the prefix scan uses the look-back scheme the
-// paper cites for its accumulate (Sec. II-B, "opportunistic look-back").
+// sort needs, Sec. I-B), and the prefix scan across tiles is the decoupled
+// look-back scan that the paper cites for its accumulate (Sec. II-B).
 #include <cstdlib>
 #include <map>
 #include <mutex>
