@@ -26,8 +26,10 @@
  *   - n == 0 (or nseg == 0) returns AK_OK and launches nothing.
  *   - The library keeps one scratch workspace per (device, stream), grown on
  *     demand with hipMalloc (which synchronises the device) and freed by
- *     ak_release_workspace().  Calls issued concurrently on DIFFERENT streams
- *     use different workspaces; calls on one stream are serialised by it.
+ *     ak_release_workspace(), unless the caller binds its own device arena
+ *     to the stream with ak_set_workspace().  Calls issued concurrently on
+ *     DIFFERENT streams use different workspaces; calls on one stream are
+ *     serialised by it.
  *   - Key counts are limited to n < 2^32 (indices and counters are 32-bit).
  */
 #ifndef AK_H
@@ -208,8 +210,34 @@ ak_status ak_rmi_codes(const void *keys, int64_t n, ak_dtype dtype, const float 
 /* --------------------------------------------------------------- scratch */
 typedef enum { AK_OP_SORT = 0, AK_OP_SORTPERM = 1, AK_OP_SEGMENTED = 2, AK_OP_LEARNED = 3 } ak_op;
 
-/* Bytes of device scratch the library holds for one call of `op` on n keys. */
+/* Bytes of device scratch one call of `op` on n keys needs (Sec. II-B: the
+ * temporaries are known ahead of the call from the input size).  The value
+ * is an upper bound, and a caller arena of this size (ak_set_workspace) is
+ * enough for that call.  For AK_OP_SEGMENTED it assumes nseg <= n; use
+ * ak_temp_bytes_segmented for the exact segment count.  Only the current
+ * tuning table changes the segmented and learned figures.  Returns 0 for
+ * n <= 0, an unknown dtype, or sizes sorted on chip without scratch. */
 size_t ak_temp_bytes(ak_op op, int64_t n, ak_dtype dtype);
+size_t ak_temp_bytes_segmented(int64_t n, int64_t nseg, ak_dtype dtype);
+
+/* Binds a caller-owned device arena [dev_ptr, dev_ptr + bytes) as the
+ * scratch of `stream` on the current device.  It waits for the stream, and
+ * then frees the library's scratch buffers of that stream.  From then on,
+ * every call on the stream carves its temporaries from the arena, 256-byte
+ * aligned, starting again at its beginning in each call (earlier calls' work
+ * runs first, in stream order), and allocates no scratch.  A call that needs
+ * more than the arena holds returns AK_ERR_NO_MEMORY, launches nothing and
+ * says how many bytes it needed; ak_temp_bytes gives the size.  The
+ * per-stream run state (a few KB), segmented-sort argument blocks and cached
+ * graphs stay library-owned.
+ *   dev_ptr: 256-byte aligned device memory of >= 4096 bytes, or NULL (with
+ *            bytes == 0) to unbind and return to library-owned scratch.
+ * The caller keeps the arena alive, and leaves it untouched, while it is
+ * bound and until the stream's work on it has finished.  Calls on the
+ * stream must not overlap (they never do when they share one stream).
+ * Errors: misaligned or too small arena, NULL with bytes > 0 ->
+ * AK_ERR_INVALID_ARG, nothing changed.  Synchronises the stream. */
+ak_status ak_set_workspace(void *dev_ptr, size_t bytes, ak_stream_t stream);
 
 /* Synchronises the device and frees every workspace and cached graph. */
 ak_status ak_release_workspace(void);

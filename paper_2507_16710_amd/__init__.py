@@ -82,6 +82,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ak_rmi_leaf_grad": [vp, i64, i32, vp, vp, vp],
         "ak_rmi_codes": [vp, i64, i32, vp, i32, vp, vp],
         "ak_release_workspace": [],
+        "ak_set_workspace": [vp, ctypes.c_size_t, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -94,6 +95,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         getattr(lib, f"ak_segmented_sort_{suf}").restype = i32
     lib.ak_temp_bytes.argtypes = [i32, i64, i32]
     lib.ak_temp_bytes.restype = ctypes.c_size_t
+    lib.ak_temp_bytes_segmented.argtypes = [i64, i64, i32]
+    lib.ak_temp_bytes_segmented.restype = ctypes.c_size_t
     lib.ak_rmi_model_floats.argtypes = [i32]
     lib.ak_rmi_model_floats.restype = ctypes.c_size_t
     lib.ak_profile_enable.argtypes = [i32]
@@ -274,6 +277,24 @@ def seg_set_tuning(key_bits: int, ipt_a: int, ipt_b: int, grid_mult: int = 4, b_
 
 def temp_bytes(op: str, n: int, dtype: str) -> int:
     return int(load_library().ak_temp_bytes(OPS[op], n, DTYPE_CODE[dtype]))
+
+
+def temp_bytes_segmented(n: int, nseg: int, dtype: str) -> int:
+    return int(load_library().ak_temp_bytes_segmented(n, nseg, DTYPE_CODE[dtype]))
+
+
+def set_workspace(arena=None) -> None:
+    """Binds a caller-owned uint8 CUDA tensor as the scratch arena of the
+    current stream (None unbinds).  The caller keeps the tensor alive while
+    it is bound."""
+    if arena is None:
+        _check(load_library().ak_set_workspace(None, 0, torch.cuda.current_stream().cuda_stream),
+               "ak_set_workspace")
+        return
+    if not arena.is_cuda or not arena.is_contiguous():
+        raise ValueError("the arena must be a contiguous CUDA tensor")
+    nbytes = arena.numel() * arena.element_size()
+    _check(load_library().ak_set_workspace(arena.data_ptr(), nbytes, _stream(arena)), "ak_set_workspace")
 
 
 def release_workspace() -> None:

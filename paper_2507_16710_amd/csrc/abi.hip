@@ -42,7 +42,7 @@ __global__ void k_zero_u64(uint64_t *p, size_t n) {
         p[i] = 0;
 }
 
-static ak_status zero_fill(hipStream_t s, void *p, size_t bytes) {
+ak_status zero_fill(hipStream_t s, void *p, size_t bytes) {
     const size_t n = bytes / 8;
     if (!n) return AK_OK;
     const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
@@ -83,9 +83,25 @@ Workspace *get_workspace(hipStream_t stream) {
 
 // Grows *p to at least `need` bytes (rounded up by 1/8 to limit regrowth).
 // The old buffer may still be read by queued work, so the stream is drained
-// before it is freed.
+// before it is freed.  With a caller arena bound, the buffer is carved from
+// it instead (256-byte aligned, in request order; carving restarts at every
+// entry point, so one call's buffers must fit together).
 ak_status ws_reserve(Workspace *ws, void **p, size_t *have, size_t need) {
     if (need <= *have) return AK_OK;
+    if (ws->arena) {
+        const size_t off = (ws->arena_used + 255) & ~size_t(255);
+        if (off > ws->arena_bytes || need > ws->arena_bytes - off) {
+            set_error("workspace arena too small: this call needs at least " + std::to_string(off + need) +
+                      " bytes, the arena has " + std::to_string(ws->arena_bytes));
+            return AK_ERR_NO_MEMORY;
+        }
+        void *np = ws->arena + off;
+        if (np != *p) ++ws->gen;
+        *p = np;
+        *have = need;
+        ws->arena_used = off + need;
+        return AK_OK;
+    }
     size_t sz = need + need / 8 + 4096;
     if (*p) {
         AK_HIP(hipStreamSynchronize(ws->stream));
@@ -141,14 +157,42 @@ uint32_t segmented_take_error(Workspace *ws);
 void segmented_release(Workspace *ws);
 void radix_release(Workspace *ws);
 
+// Forgets every scratch buffer of the workspace, freeing the ones the
+// library allocated (arena buffers belong to the caller).
+static void drop_buffers(Workspace *ws) {
+    void **bufs[] = {&ws->keys0, &ws->keys1, &ws->vals0, (void **)&ws->lookback, &ws->misc, &ws->misc2};
+    size_t *sizes[] = {&ws->keys0_bytes, &ws->keys1_bytes, &ws->vals0_bytes, &ws->lookback_bytes, &ws->misc_bytes,
+                       &ws->misc2_bytes};
+    for (int i = 0; i < 6; ++i) {
+        if (*bufs[i] && !ws->arena) (void)hipFree(*bufs[i]);
+        *bufs[i] = nullptr;
+        *sizes[i] = 0;
+    }
+    for (int i = 0; i < 6; ++i) {
+        if (ws->aux[i] && !ws->arena) (void)hipFree(ws->aux[i]);
+        ws->aux[i] = nullptr;
+        ws->aux_bytes[i] = 0;
+    }
+    ++ws->gen;
+}
+
+// Start of an entry point: with an arena bound, carving restarts at its
+// beginning (work queued by earlier calls on the stream runs first, so
+// reusing the bytes is safe in stream order).  Pointers are kept so that a
+// buffer carved at the same place again keeps its cached graphs.
+void ws_begin_call(Workspace *ws) {
+    if (!ws->arena) return;
+    ws->arena_used = 0;
+    ws->keys0_bytes = ws->keys1_bytes = ws->vals0_bytes = ws->lookback_bytes = 0;
+    ws->misc_bytes = ws->misc2_bytes = 0;
+    for (size_t &b : ws->aux_bytes) b = 0;
+}
+
 static void free_ws(Workspace *ws) {
     segmented_release(ws);
     radix_release(ws);
-    void *bufs[] = {ws->keys0, ws->keys1, ws->vals0, ws->lookback, ws->state, ws->misc, ws->misc2};
-    for (void *b : bufs)
-        if (b) (void)hipFree(b);
-    for (void *b : ws->aux)
-        if (b) (void)hipFree(b);
+    drop_buffers(ws);
+    if (ws->state) (void)hipFree(ws->state);
     delete ws;
 }
 
@@ -185,6 +229,7 @@ static ak_status check_keys(const void *keys, int64_t n, int dtype) {
 static Workspace *ws_or_error(ak_stream_t stream, ak_status *st) {
     Workspace *ws = get_workspace((hipStream_t)stream);
     *st = ws ? AK_OK : AK_ERR_HIP;
+    if (ws) ws_begin_call(ws);
     return ws;
 }
 
@@ -387,13 +432,42 @@ size_t ak_temp_bytes(ak_op op, int64_t n, ak_dtype dtype) {
     switch (op) {
     case AK_OP_SORT: return radix_temp_bytes(dtype, n, false);
     case AK_OP_SORTPERM: return radix_temp_bytes(dtype, n, true);
-    case AK_OP_SEGMENTED: return segmented_temp_bytes(dtype, n, 0);
+    case AK_OP_SEGMENTED: return segmented_temp_bytes(dtype, n, n);
     case AK_OP_LEARNED: {
         ak_learned_cfg c = resolve_cfg(nullptr);
         return learned_temp_bytes(dtype, n, &c);
     }
     }
     return 0;
+}
+
+size_t ak_temp_bytes_segmented(int64_t n, int64_t nseg, ak_dtype dtype) {
+    if (!dtype_ok(dtype) || n <= 0 || nseg <= 0) return 0;
+    return segmented_temp_bytes(dtype, n, nseg);
+}
+
+ak_status ak_set_workspace(void *dev_ptr, size_t bytes, ak_stream_t stream) {
+    if (!dev_ptr && bytes) {
+        set_error("dev_ptr is NULL but bytes > 0");
+        return AK_ERR_INVALID_ARG;
+    }
+    if (dev_ptr && ((uintptr_t)dev_ptr & 255u)) {
+        set_error("the workspace arena must be 256-byte aligned");
+        return AK_ERR_INVALID_ARG;
+    }
+    if (dev_ptr && bytes < 4096) {
+        set_error("the workspace arena must hold at least 4096 bytes");
+        return AK_ERR_INVALID_ARG;
+    }
+    Workspace *ws = get_workspace((hipStream_t)stream);
+    if (!ws) return AK_ERR_HIP;
+    // queued work may still use the current buffers
+    AK_HIP(hipStreamSynchronize(ws->stream));
+    drop_buffers(ws);
+    ws->arena = (char *)dev_ptr;
+    ws->arena_bytes = dev_ptr ? bytes : 0;
+    ws->arena_used = 0;
+    return AK_OK;
 }
 
 ak_status ak_release_workspace(void) {

@@ -163,11 +163,17 @@ struct Workspace {
     void *misc2 = nullptr; size_t misc2_bytes = 0;
     void *aux[6] = {nullptr}; size_t aux_bytes[6] = {0};     // learned-sort scratch
     uint32_t epoch = 0;             // last epoch base handed out
+    char *arena = nullptr;          // caller-owned scratch (ak_set_workspace), else null
+    size_t arena_bytes = 0, arena_used = 0;
 };
 
 Workspace *get_workspace(hipStream_t stream);
 ak_status ws_reserve(Workspace *ws, void **p, size_t *have, size_t need);
 ak_status ws_reserve_lookback(Workspace *ws, size_t need);
+// Called by every entry point before it reserves scratch.
+void ws_begin_call(Workspace *ws);
+// Zeroes `bytes` at p with a fill kernel on s (no memset node in a graph).
+ak_status zero_fill(hipStream_t s, void *p, size_t bytes);
 // Mirrors the device's epoch advance of one run (16 epochs per run; both
 // restart at 16 before 2^30) and clears the look-back words when it wraps.
 ak_status ws_next_epoch(Workspace *ws, uint32_t *epoch);
@@ -192,6 +198,8 @@ ak_status segmented_sort(Workspace *ws, int dtype, void *keys, const int64_t *of
 ak_status segmented_sort_ranges(Workspace *ws, int dtype, void *keys, const int64_t *lo, const int64_t *hi,
                                 int64_t nseg, int64_t end, void *tmp);
 size_t segmented_temp_bytes(int dtype, int64_t n, int64_t nseg);
+size_t segmented_scratch_bytes(int dtype, int64_t n, int64_t nseg, bool with_tmp);
+size_t code_partition_bytes(int dtype, int64_t n);
 
 // ------------------------------------------------------------- learned
 ak_status learned_sort(Workspace *ws, int dtype, void *keys, int64_t n, const ak_learned_cfg *cfg,

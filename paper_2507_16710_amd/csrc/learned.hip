@@ -522,13 +522,19 @@ struct FitBufs {
     float *scales, *resid, *stats;
     float *model_copy;
 };
+static size_t fit_scratch_bytes(uint32_t m, int L, bool with_model) {
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    return al((size_t)(L + 1) * 4) + al((size_t)L * 4) + al((size_t)m * 4) + al((size_t)L * 32) +
+           (with_model ? model_floats(L) * 4 : 0) + 256;
+}
+
 static ak_status fit_scratch(Workspace *ws, uint32_t m, int L, bool with_model, FitBufs *f) {
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
     const size_t o_sc = al((size_t)(L + 1) * 4);
     const size_t o_res = o_sc + al((size_t)L * 4);
     const size_t o_stats = o_res + al((size_t)m * 4);
     const size_t o_model = o_stats + al((size_t)L * 32);
-    const size_t need = o_model + (with_model ? model_floats(L) * 4 : 0) + 256;
+    const size_t need = fit_scratch_bytes(m, L, with_model);
     ak_status r = ws_reserve(ws, &ws->aux[1], &ws->aux_bytes[1], need);
     if (r != AK_OK) return r;
     char *base = (char *)ws->aux[1];
@@ -617,6 +623,16 @@ static ak_status leaf_grad_t(Workspace *ws, const void *sorted, uint32_t m, cons
     return AK_OK;
 }
 
+constexpr int LEARNED_CAP = 4096;  // keys of an on-chip chunk
+
+// aux[0] of one learned call: sample keys | model | learned state |
+// fallback runs | flags | fallback range bounds
+static size_t learned_aux0_bytes(size_t kb, uint32_t m, int L, uint32_t fb_cap) {
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    return al((size_t)m * kb) + al(model_floats(L) * 4) + 256 + al((size_t)fb_cap * sizeof(FbRun)) +
+           al((size_t)fb_cap * 4) + (size_t)fb_cap * 16 + 256;
+}
+
 template <int DT>
 static ak_status learned_t(Workspace *ws, void *keys, int64_t n64, const ak_learned_cfg *cfg,
                            ak_learned_stats *stats) {
@@ -636,6 +652,7 @@ static ak_status learned_t(Workspace *ws, void *keys, int64_t n64, const ak_lear
     const uint32_t m = (uint32_t)sample_count(n64, cfg->sample_frac);
     const int cb = code_bits(n64);
     constexpr int CW = 16, CIPT = 4, CAP = CW * 64 * CIPT;
+    static_assert(CAP == LEARNED_CAP, "chunk capacity");
     const uint32_t fb_cap = n / CAP + 2;
     ak_status r;
     // aux[0]: sample keys | model | learned state | fallback runs | flags
@@ -645,7 +662,7 @@ static ak_status learned_t(Workspace *ws, void *keys, int64_t n64, const ak_lear
     const size_t off_nc = off_fb + (((size_t)fb_cap * sizeof(FbRun) + 255) & ~size_t(255));
     const size_t off_lo = off_nc + (((size_t)fb_cap * 4 + 255) & ~size_t(255));
     const size_t off_hi = off_lo + (size_t)fb_cap * 8;
-    const size_t need = off_hi + (size_t)fb_cap * 8 + 256;
+    const size_t need = learned_aux0_bytes(sizeof(U), m, L, fb_cap);
     if ((r = ws_reserve(ws, &ws->aux[0], &ws->aux_bytes[0], need)) != AK_OK) return r;
     char *base = (char *)ws->aux[0];
     U *sample = (U *)base;
@@ -696,7 +713,7 @@ static ak_status learned_t(Workspace *ws, void *keys, int64_t n64, const ak_lear
         const int nb = 1 << bl;
         if ((r = ws_reserve(ws, &ws->aux[2], &ws->aux_bytes[2], (size_t)nb * 4)) != AK_OK) return r;
         uint32_t *hist = (uint32_t *)ws->aux[2];
-        AK_HIP(hipMemsetAsync(hist, 0, (size_t)nb * 4, s));
+        if ((r = zero_fill(s, hist, (size_t)nb * 4)) != AK_OK) return r;
         hipLaunchKernelGGL((k_fb_check<DT>), dim3(num_cus() * 4), dim3(256), 0, s, (const U *)keys,
                            (const FbRun *)fb, (const LearnedState *)ls, nonconst);
         AK_LAUNCH_CHECK("k_fb_check");
@@ -743,11 +760,23 @@ ak_status learned_sort(Workspace *ws, int dt, void *keys, int64_t n, const ak_le
     AK_DT_SWITCH(dt, learned_t, ws, keys, n, cfg, stats)
 }
 
+// Sum of what one call reserves, in order: sample, model and fallback
+// bookkeeping; fit scratch; the sample's radix sort; the code passes; the
+// fallback's segmented sort over fb_cap ranges (its key scratch is keys0);
+// the statistics histogram.  Buffers that grow within the call (sample
+// sort, then the code passes) are counted at both sizes, which is what a
+// caller arena needs (the library's own buffers grow in place).
 size_t learned_temp_bytes(int dt, int64_t n, const ak_learned_cfg *cfg) {
+    if (n <= small_sort_capacity(dt)) return 0;
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
     const int64_t m = sample_count(n, cfg->sample_frac);
+    const int L = cfg->leaves;
     const size_t kb = (size_t)dtype_bytes(dt);
-    return radix_temp_bytes(dt, n, false) + (size_t)m * kb * 2 + (size_t)m * 4 + (size_t)cfg->leaves * 64 +
-           (size_t)(n / 4096 + 2) * 12;
+    const uint32_t fb_cap = (uint32_t)(n / LEARNED_CAP + 2);
+    const size_t aux0 = al(learned_aux0_bytes(kb, (uint32_t)m, L, fb_cap));
+    const size_t aux1 = al(fit_scratch_bytes((uint32_t)m, L, false));
+    return aux0 + aux1 + radix_temp_bytes(dt, m, false) + code_partition_bytes(dt, n) +
+           segmented_scratch_bytes(dt, n, fb_cap, false) + al((size_t)4 << 14);
 }
 
 template <int DT>

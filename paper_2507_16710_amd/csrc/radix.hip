@@ -395,6 +395,8 @@ int64_t small_sort_capacity(int) { return SMALL_W * 64 * SMALL_IPT; }
 
 static inline int tile_keys(int dt, bool val) { return os_tile(dt, val); }
 
+static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+
 size_t radix_temp_bytes(int dt, int64_t n, bool perm) {
     if (n <= small_sort_capacity(dt)) return 0;
     const size_t kb = (size_t)dtype_bytes(dt);
@@ -402,9 +404,15 @@ size_t radix_temp_bytes(int dt, int64_t n, bool perm) {
     // two key-sized ping-pong buffers (sort: the second one lets an odd
     // number of passes end in the caller's buffer; sortperm: the const keys
     // are never written), the look-back words, and the index buffer
-    size_t b = 2 * (size_t)n * kb + tiles * RADIX * 8;
-    if (perm) b += (size_t)n * 4;
+    size_t b = 2 * al256((size_t)n * kb) + al256(tiles * RADIX * 8);
+    if (perm) b += al256((size_t)n * 4);
     return b;
+}
+
+size_t code_partition_bytes(int dt, int64_t n) {
+    const size_t kb = (size_t)dtype_bytes(dt);
+    const size_t tiles = (size_t)((n + os_code_tile(dt) - 1) / os_code_tile(dt));
+    return 2 * al256((size_t)n * kb) + al256(tiles * RADIX * 8);
 }
 
 template <int DT, bool VAL, bool CODE, int V>

@@ -787,9 +787,54 @@ static ak_status seg_launch_all(int dt, const SegTune &t, int64_t nseg, int grid
     return AK_ERR_UNSUPPORTED_DTYPE;
 }
 
-size_t segmented_temp_bytes(int dt, int64_t n, int64_t nseg) {
-    return (size_t)n * dtype_bytes(dt) + (size_t)(nseg > 0 ? nseg : 0) * 4 + sizeof(SegArgs) + sizeof(SegState);
+// Scratch layout of one call: the class limits from the tuning, and the
+// pieces of misc2 (segment list, huge-segment tile prefix, descriptors,
+// digit counts, tile maps) plus the huge segments' look-back words.
+struct SegLayout {
+    SegTune t;
+    uint32_t a_max, b_max, xl_min, xl_cap;
+    size_t off_pre, off_desc, off_hist, off_tseg, off_apre, off_amap, misc2_need;
+    size_t max_tiles, lb_words;
+};
+
+static SegLayout seg_layout(int dt, int64_t n, int64_t nseg) {
+    SegLayout L;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_tune_table();
+        L.t = g_tune[key_bits(dt) == 64];
+    }
+    if (!tune_valid(key_bits(dt), L.t)) L.t = SegTune{};
+    const SegTune &t = L.t;
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const int P = dtype_bytes(dt);
+    L.a_max = 64u * (uint32_t)t.ipt_a;
+    const uint32_t cap_b = 256u * (uint32_t)t.ipt_b;
+    L.b_max = t.b_max > 0 ? std::min<uint32_t>((uint32_t)t.b_max, cap_b) : cap_b;
+    L.xl_min = (uint32_t)std::max(t.xl_min, (int)L.b_max + 1);
+    L.xl_cap = (uint32_t)std::min<int64_t>(nseg, n / L.xl_min + 1);
+    L.max_tiles = (size_t)n / XL_TILE + L.xl_cap + 1;
+    L.off_pre = al((size_t)nseg * 4);
+    L.off_desc = L.off_pre + al((size_t)(L.xl_cap + 1) * 4);
+    L.off_hist = L.off_desc + al((size_t)L.xl_cap * sizeof(XlDesc));
+    L.off_tseg = L.off_hist + al((size_t)L.xl_cap * P * RADIX * 4);
+    L.off_apre = L.off_tseg + al(L.max_tiles * 4);
+    L.off_amap = L.off_apre + al((size_t)(P + 1) * (L.xl_cap + 1) * 4);
+    L.misc2_need = L.off_amap + (size_t)(P + 1) * L.max_tiles * 4;
+    L.lb_words = L.max_tiles * RADIX;
+    return L;
 }
+
+// Scratch of one batched call over n keys in nseg segments (with_tmp: the
+// key-sized scratch copy too).
+size_t segmented_scratch_bytes(int dt, int64_t n, int64_t nseg, bool with_tmp) {
+    if (n <= 0 || nseg <= 0) return 0;
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const SegLayout L = seg_layout(dt, n, nseg);
+    return (with_tmp ? al((size_t)n * dtype_bytes(dt)) : 0) + al(L.misc2_need) + al(L.lb_words * 8);
+}
+
+size_t segmented_temp_bytes(int dt, int64_t n, int64_t nseg) { return segmented_scratch_bytes(dt, n, nseg, true); }
 
 // Sorts the ranges keys[lo[s] .. hi[s]) (base <= lo <= hi <= end, ranges
 // disjoint) through the captured launch sequence; `tmp` holds end - base
@@ -798,40 +843,19 @@ static ak_status seg_run(Workspace *ws, int dt, void *keys, const int64_t *lo, c
                          int64_t base, int64_t end, void *tmp) {
     hipStream_t s = ws->stream;
     const int64_t n = end - base;
-    SegTune t;
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        load_tune_table();
-        t = g_tune[key_bits(dt) == 64];
-    }
-    if (!tune_valid(key_bits(dt), t)) t = SegTune{};
-    const uint32_t a_max = 64u * (uint32_t)t.ipt_a;
-    const uint32_t cap_b = 256u * (uint32_t)t.ipt_b;
-    const uint32_t b_max = t.b_max > 0 ? std::min<uint32_t>((uint32_t)t.b_max, cap_b) : cap_b;
+    const SegLayout L = seg_layout(dt, n, nseg);
+    const SegTune &t = L.t;
     const int grid = num_cus() * t.grid_mult;
-
     ak_status r;
     const size_t kb = (size_t)dtype_bytes(dt);
-    const int P = (int)kb;
-    const uint32_t xl_min = (uint32_t)std::max(t.xl_min, (int)b_max + 1);
-    const uint32_t xl_cap = (uint32_t)std::min<int64_t>(nseg, n / xl_min + 1);
-    const size_t off_pre = ((size_t)nseg * 4 + 255) & ~size_t(255);
-    const size_t off_desc = off_pre + (((size_t)(xl_cap + 1) * 4 + 255) & ~size_t(255));
-    const size_t off_hist = off_desc + (((size_t)xl_cap * sizeof(XlDesc) + 255) & ~size_t(255));
-    const size_t max_tiles = (size_t)n / XL_TILE + xl_cap + 1;
-    const size_t off_tseg = off_hist + (((size_t)xl_cap * P * RADIX * 4 + 255) & ~size_t(255));
-    const size_t off_apre = off_tseg + ((max_tiles * 4 + 255) & ~size_t(255));
-    const size_t off_amap = off_apre + (((size_t)(P + 1) * (xl_cap + 1) * 4 + 255) & ~size_t(255));
-    const size_t misc2_need = off_amap + (size_t)(P + 1) * max_tiles * 4;
-    const size_t lb_words = max_tiles * RADIX;
     if (!tmp) {
         if ((r = ws_reserve(ws, &ws->misc, &ws->misc_bytes, (size_t)n * kb)) != AK_OK) return r;
         tmp = ws->misc;
     }
-    if ((r = ws_reserve(ws, &ws->misc2, &ws->misc2_bytes, misc2_need)) != AK_OK) return r;
-    if (lb_words * 8 > ws->aux_bytes[3]) {
-        if ((r = ws_reserve(ws, &ws->aux[3], &ws->aux_bytes[3], lb_words * 8)) != AK_OK) return r;
-        AK_HIP(hipMemsetAsync(ws->aux[3], 0, ws->aux_bytes[3], s));
+    if ((r = ws_reserve(ws, &ws->misc2, &ws->misc2_bytes, L.misc2_need)) != AK_OK) return r;
+    if (L.lb_words * 8 > ws->aux_bytes[3]) {
+        if ((r = ws_reserve(ws, &ws->aux[3], &ws->aux_bytes[3], L.lb_words * 8)) != AK_OK) return r;
+        if ((r = zero_fill(s, ws->aux[3], ws->aux_bytes[3])) != AK_OK) return r;
     }
 
     std::lock_guard<std::mutex> lk(g_seg_mu);
@@ -839,7 +863,7 @@ static ak_status seg_run(Workspace *ws, int dt, void *keys, const int64_t *lo, c
     if (!c.args) {
         AK_HIP(hipMalloc((void **)&c.args, sizeof(SegArgs)));
         AK_HIP(hipMalloc((void **)&c.state, sizeof(SegState)));
-        AK_HIP(hipMemsetAsync(c.state, 0, sizeof(SegState), s));
+        if ((r = zero_fill(s, c.state, sizeof(SegState))) != AK_OK) return r;
         AK_HIP(hipStreamCreateWithFlags(&c.capture, hipStreamNonBlocking));
     }
     SegArgs v{};
@@ -851,17 +875,17 @@ static ak_status seg_run(Workspace *ws, int dt, void *keys, const int64_t *lo, c
     v.nseg = nseg;
     v.base = base;
     v.end = end;
-    v.a_max = a_max;
-    v.b_max = b_max;
-    v.xl_min = xl_min;
-    v.xl_cap = xl_cap;
-    v.xl_pre = (uint32_t *)((char *)ws->misc2 + off_pre);
-    v.xl_desc = (XlDesc *)((char *)ws->misc2 + off_desc);
-    v.xl_hist = (uint32_t *)((char *)ws->misc2 + off_hist);
-    v.xl_tseg = (uint32_t *)((char *)ws->misc2 + off_tseg);
-    v.xl_tcap = (uint32_t)max_tiles;
-    v.xl_apre = (uint32_t *)((char *)ws->misc2 + off_apre);
-    v.xl_amap = (uint32_t *)((char *)ws->misc2 + off_amap);
+    v.a_max = L.a_max;
+    v.b_max = L.b_max;
+    v.xl_min = L.xl_min;
+    v.xl_cap = L.xl_cap;
+    v.xl_pre = (uint32_t *)((char *)ws->misc2 + L.off_pre);
+    v.xl_desc = (XlDesc *)((char *)ws->misc2 + L.off_desc);
+    v.xl_hist = (uint32_t *)((char *)ws->misc2 + L.off_hist);
+    v.xl_tseg = (uint32_t *)((char *)ws->misc2 + L.off_tseg);
+    v.xl_tcap = (uint32_t)L.max_tiles;
+    v.xl_apre = (uint32_t *)((char *)ws->misc2 + L.off_apre);
+    v.xl_amap = (uint32_t *)((char *)ws->misc2 + L.off_amap);
     v.xl_lb = (uint64_t *)ws->aux[3];
     v.xl_lb_words = ws->aux_bytes[3] / 8;
     hipLaunchKernelGGL(k_seg_setargs, dim3(1), dim3(1), 0, s, c.args, v);
