@@ -188,6 +188,15 @@ void ws_begin_call(Workspace *ws) {
     for (size_t &b : ws->aux_bytes) b = 0;
 }
 
+// With a caller arena bound, a call whose scratch cannot fit fails before
+// it launches anything.
+ak_status ws_arena_fits(Workspace *ws, size_t need) {
+    if (!ws->arena || need <= ws->arena_bytes) return AK_OK;
+    set_error("workspace arena too small: this call needs " + std::to_string(need) + " bytes, the arena has " +
+              std::to_string(ws->arena_bytes));
+    return AK_ERR_NO_MEMORY;
+}
+
 static void free_ws(Workspace *ws) {
     segmented_release(ws);
     radix_release(ws);
@@ -255,6 +264,7 @@ ak_status ak_sort(void *keys, int64_t n, ak_dtype dtype, ak_stream_t stream) {
     if (r != AK_OK || n == 0) return r;
     Workspace *ws = ws_or_error(stream, &r);
     if (!ws) return r;
+    if ((r = ws_arena_fits(ws, radix_temp_bytes(dtype, n, false))) != AK_OK) return r;
     return radix_sort(ws, dtype, keys, nullptr, n, 0);
 }
 
@@ -273,6 +283,7 @@ ak_status ak_sortperm(const void *keys, uint32_t *perm, int64_t n, ak_dtype dtyp
     }
     Workspace *ws = ws_or_error(stream, &r);
     if (!ws) return r;
+    if ((r = ws_arena_fits(ws, radix_temp_bytes(dtype, n, true))) != AK_OK) return r;
     return radix_sort(ws, dtype, const_cast<void *>(keys), perm, n, 0);
 }
 
@@ -368,6 +379,7 @@ ak_status ak_sort_learned(void *keys, int64_t n, ak_dtype dtype, const ak_learne
     }
     Workspace *ws = ws_or_error(stream, &r);
     if (!ws) return r;
+    if ((r = ws_arena_fits(ws, learned_temp_bytes(dtype, n, &c))) != AK_OK) return r;
     return learned_sort(ws, dtype, keys, n, &c, stats);
 }
 

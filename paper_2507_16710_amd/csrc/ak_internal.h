@@ -172,6 +172,8 @@ ak_status ws_reserve(Workspace *ws, void **p, size_t *have, size_t need);
 ak_status ws_reserve_lookback(Workspace *ws, size_t need);
 // Called by every entry point before it reserves scratch.
 void ws_begin_call(Workspace *ws);
+// AK_OK unless a caller arena is bound and smaller than `need`.
+ak_status ws_arena_fits(Workspace *ws, size_t need);
 // Zeroes `bytes` at p with a fill kernel on s (no memset node in a graph).
 ak_status zero_fill(hipStream_t s, void *p, size_t bytes);
 // Mirrors the device's epoch advance of one run (16 epochs per run; both

@@ -930,6 +930,8 @@ ak_status segmented_sort(Workspace *ws, int dt, void *keys, const int64_t *offse
         return AK_ERR_INVALID_ARG;
     }
     if (n == 0) return AK_OK;
+    ak_status r = ws_arena_fits(ws, segmented_temp_bytes(dt, n, nseg));
+    if (r != AK_OK) return r;
     return seg_run(ws, dt, keys, offsets, offsets + 1, nseg, ends[0], ends[1], nullptr);
 }
 

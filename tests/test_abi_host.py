@@ -56,6 +56,9 @@ def test_argument_errors_without_device_work():
     assert lib.ak_seg_set_tuning(64, 4, 32, 4, 0, 32768) == 1   # 32 keys/lane: 32-bit only
     msg = lib.ak_last_error()
     assert msg and b"tuning" in msg
+    assert lib.ak_set_workspace(None, 4096, None) == 1        # NULL with bytes
+    assert lib.ak_set_workspace(vp(0x1008), 1 << 20, None) == 1   # not 256-byte aligned
+    assert lib.ak_set_workspace(vp(0x1000), 1024, None) == 1      # smaller than 4096 bytes
     assert lib.ak_status_string(3) == b"out of device memory"
 
 
@@ -73,4 +76,8 @@ def test_temp_bytes_predictable():
         assert p >= 2 * n * kb + n * 4
         assert lib.ak_temp_bytes(2, n, dt) >= n * kb
         assert lib.ak_temp_bytes(3, n, dt) >= s
+        # segmented: the bound assumes nseg <= n; more segments need more
+        assert lib.ak_temp_bytes(2, n, dt) == lib.ak_temp_bytes_segmented(n, n, dt)
+        assert lib.ak_temp_bytes_segmented(n, 10, dt) < lib.ak_temp_bytes_segmented(n, 2 * n, dt)
+        assert lib.ak_temp_bytes_segmented(n, 0, dt) == 0
     assert lib.ak_rmi_model_floats(4096) == 8 + 4 * (4096 + 1)
