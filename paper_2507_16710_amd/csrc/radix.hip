@@ -49,9 +49,17 @@ template <int B>
 __device__ void scan_places(RunState *st, uint32_t n, int nplaces, uint32_t *s_buf, uint32_t *s_wsum,
                             int *s_active) {
     const int tid = threadIdx.x;
-    for (int p = 0; p < nplaces; ++p) {
-        const uint32_t c =
-            tid < RADIX ? __hip_atomic_load(&st->hist[p][tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+    // every place's count in flight at once (one round trip, not one per place)
+    uint32_t cnt[MAX_PLACES];
+#pragma unroll
+    for (int p = 0; p < MAX_PLACES; ++p)
+        cnt[p] = (p < nplaces && tid < RADIX)
+                     ? __hip_atomic_load(&st->hist[p][tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                     : 0u;
+#pragma unroll
+    for (int p = 0; p < MAX_PLACES; ++p) {
+        if (p >= nplaces) break;
+        const uint32_t c = cnt[p];
         const int trivial = __syncthreads_or(tid < RADIX && c == n);
         if (tid < RADIX) s_buf[tid] = c;
         __syncthreads();
@@ -274,10 +282,11 @@ __global__ __launch_bounds__(W * 64) void k_onesweep(OnesweepArgs a) {
     rank_match<RADIX_BITS, W, IPT, uint16_t>(dg, tvalid, rk, s_cnt, s_tot, tid);
 
     // publish this tile's digit counts first, so successors can look back
+    // (the first tile of a group is inclusive within its group)
     uint64_t *lb = a.lookback + (size_t)tile * RADIX;
     const uint32_t epoch = a.st->epoch_base + (uint32_t)a.place;
     for (int d = tid; d < RADIX; d += B)
-        lb_store(lb + d, lb_pack(epoch, tile == 0 ? LB_INC : LB_AGG, s_tot[d]));
+        lb_store(lb + d, lb_pack(epoch, tile % LB_GROUP == 0 ? LB_INC : LB_AGG, s_tot[d]));
     // the next claim (every thread read s_tile before rank_match's barriers;
     // block_exscan's barriers publish the new value)
     if (CODE && tid == 0) s_tile = atomicAdd(&a.st->tile_ctr[a.place], 1u);
@@ -293,15 +302,27 @@ __global__ __launch_bounds__(W * 64) void k_onesweep(OnesweepArgs a) {
         if (next < ntiles) load_tile(next, kn, vn);
     }
 
-    // decoupled look-back, K*LB_M predecessors per round trip
+    // two-level decoupled look-back (K*LB_M words per round trip): inside
+    // the tile's group, then over the words of the groups before it
     {
         const int d = tid / K, kk = tid % K;
-        uint32_t excl = 0;
-        if (tile > 0) {
-            excl = lookback_prefix<K, LB_M>(a.lookback + d, (int64_t)tile - 1, epoch, kk);
-            if (kk == 0) lb_store(lb + d, lb_pack(epoch, LB_INC, excl + s_tot[d]));
+        const uint32_t g = tile / LB_GROUP, jl = tile % LB_GROUP;
+        uint64_t *lbg = a.lookback + (size_t)ntiles * RADIX;
+        uint32_t lexcl = 0, gexcl = 0;
+        if (jl > 0) {
+            // stops at the group's first tile at the latest (inclusive word)
+            lexcl = lookback_prefix<K, LB_M>(a.lookback + d, (int64_t)tile - 1, epoch, kk);
+            if (kk == 0) lb_store(lb + d, lb_pack(epoch, LB_INC, lexcl + s_tot[d]));
         }
-        if (kk == 0) s_glob[d] = a.st->base[a.place][d] + excl - s_start[d];
+        const bool glast = jl == LB_GROUP - 1;
+        if (glast && kk == 0)
+            lb_store(lbg + (size_t)g * RADIX + d, lb_pack(epoch, g == 0 ? LB_INC : LB_AGG, lexcl + s_tot[d]));
+        if (g > 0) {
+            gexcl = lookback_prefix<K, LB_M>(lbg + d, (int64_t)g - 1, epoch, kk);
+            if (glast && kk == 0)
+                lb_store(lbg + (size_t)g * RADIX + d, lb_pack(epoch, LB_INC, gexcl + lexcl + s_tot[d]));
+        }
+        if (kk == 0) s_glob[d] = a.st->base[a.place][d] + gexcl + lexcl - s_start[d];
     }
     __syncthreads();  // counters are dead from here on: their bytes hold keys
 
@@ -404,7 +425,7 @@ size_t radix_temp_bytes(int dt, int64_t n, bool perm) {
     // two key-sized ping-pong buffers (sort: the second one lets an odd
     // number of passes end in the caller's buffer; sortperm: the const keys
     // are never written), the look-back words, and the index buffer
-    size_t b = 2 * al256((size_t)n * kb) + al256(tiles * RADIX * 8);
+    size_t b = 2 * al256((size_t)n * kb) + al256(lookback_words(tiles) * 8);
     if (perm) b += al256((size_t)n * 4);
     return b;
 }
@@ -412,7 +433,7 @@ size_t radix_temp_bytes(int dt, int64_t n, bool perm) {
 size_t code_partition_bytes(int dt, int64_t n) {
     const size_t kb = (size_t)dtype_bytes(dt);
     const size_t tiles = (size_t)((n + os_code_tile(dt) - 1) / os_code_tile(dt));
-    return 2 * al256((size_t)n * kb) + al256(tiles * RADIX * 8);
+    return 2 * al256((size_t)n * kb) + al256(lookback_words(tiles) * 8);
 }
 
 template <int DT, bool VAL, bool CODE, int V>
@@ -560,7 +581,7 @@ static ak_status radix_sort_t(Workspace *ws, void *keys, uint32_t *perm, int64_t
     if (pm && (r = ws_reserve(ws, &ws->vals0, &ws->vals0_bytes, (size_t)n * 4)) != AK_OK) return r;
     const int TILE = tile_keys(DT, pm);
     const size_t tiles = (n + TILE - 1) / TILE;
-    if ((r = ws_reserve_lookback(ws, tiles * RADIX * 8)) != AK_OK) return r;
+    if ((r = ws_reserve_lookback(ws, lookback_words(tiles) * 8)) != AK_OK) return r;
     uint32_t epoch;
     if ((r = ws_next_epoch(ws, &epoch)) != AK_OK) return r;
     RunState *st = ws->state + slot;
@@ -623,7 +644,7 @@ static ak_status code_partition_t(Workspace *ws, void *keys, uint32_t n, const f
     if ((r = ws_reserve(ws, &ws->keys1, &ws->keys1_bytes, (size_t)n * sizeof(U))) != AK_OK) return r;
     const int TILE = os_code_tile(DT);
     const size_t tiles = (n + TILE - 1) / TILE;
-    if ((r = ws_reserve_lookback(ws, tiles * RADIX * 8)) != AK_OK) return r;
+    if ((r = ws_reserve_lookback(ws, lookback_words(tiles) * 8)) != AK_OK) return r;
     uint32_t epoch;
     if ((r = ws_next_epoch(ws, &epoch)) != AK_OK) return r;
     const int nplaces = (cb + RADIX_BITS - 1) / RADIX_BITS;

@@ -9,7 +9,7 @@ struct OnesweepArgs {
     void *keys;           // sort: keys (in/out); sortperm: the const keys
     void *t0, *t1;        // key scratch buffers
     uint32_t *v0, *perm;  // value scratch, permutation output
-    uint64_t *lookback;   // tiles x RADIX look-back words
+    uint64_t *lookback;   // tiles x RADIX look-back words, then groups x RADIX group words
     RunState *st;
     const float *model;   // learned model (code digits only)
     uint32_t n;
@@ -22,6 +22,17 @@ struct OnesweepArgs {
 // compiled per (key width, with values); os_variant() picks one at run time
 // (default from the tuning sweep; $AK_OS_VARIANT overrides it).
 constexpr int LB_M = 4;  // look-back words read per thread per round trip
+// Tiles per look-back group.  A tile looks back only inside its group (the
+// group's first tile is inclusive by definition); every group's last tile
+// publishes the group's digit totals, and the prefix of the groups before a
+// tile comes from a second decoupled look-back over those group words.  The
+// inclusive frontier then advances LB_GROUP times faster per round trip.
+#ifndef AK_LB_GROUP
+#define AK_LB_GROUP 16
+#endif
+constexpr int LB_GROUP = AK_LB_GROUP;
+// look-back words of a pass over `tiles` tiles (tile words, then group words)
+inline size_t lookback_words(size_t tiles) { return (tiles + (tiles + LB_GROUP - 1) / LB_GROUP) * 256; }
 
 struct OsShape {
     int w, ipt;
