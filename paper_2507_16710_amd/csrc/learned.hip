@@ -163,21 +163,69 @@ __device__ __forceinline__ float block_sum_f(float v, float *s_red) {
     return t;
 }
 
-// Forward: residual of every sample of leaf blockIdx.x, r = a*dx + b - j/m
-// (in the leaf's scaled coordinates a' = a/s, dx' = dx*s), and the loss.
+// The leaf sums run over work items of at most FIT_CH samples (a leaf's
+// samples split into consecutive pieces), so one leaf holding a large
+// share of the sample (a repeated key) does not leave one workgroup walking
+// it alone.  Every item writes its partial sums, and k_rmi_sum adds a
+// leaf's items in order: the result does not depend on scheduling.
+constexpr uint32_t FIT_CH = 8192;
+
+// item prefix: ipre[i] = first item of leaf i (ipre[L] = item count), one
+// workgroup of 1024 threads
+__global__ __launch_bounds__(1024) void k_fit_items(const uint32_t *st, int L, uint32_t *ipre) {
+    __shared__ uint32_t s_wsum[16];
+    __shared__ uint32_t s_carry;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) s_carry = 0;
+    __syncthreads();
+    for (int base = 0; base < L; base += 1024) {
+        const int i = base + tid;
+        const uint32_t v = i < L ? (st[i + 1] - st[i] + FIT_CH - 1) / FIT_CH : 0u;
+        const uint32_t incl = wave_incl_scan(v);
+        if (lane == 63) s_wsum[w] = incl;
+        __syncthreads();
+        uint32_t run = s_carry;
+        for (int ww = 0; ww < w; ++ww) run += s_wsum[ww];
+        if (i < L) ipre[i] = run + incl - v;
+        __syncthreads();
+        if (tid == 1023) s_carry = run + incl;
+        __syncthreads();
+    }
+    if (tid == 0) ipre[L] = s_carry;
+}
+
+__global__ __launch_bounds__(256) void k_fit_itemmap(const uint32_t *ipre, int L, uint32_t *item_leaf) {
+    for (int i = blockIdx.x; i < L; i += gridDim.x)
+        for (uint32_t k = ipre[i] + threadIdx.x; k < ipre[i + 1]; k += 256) item_leaf[k] = (uint32_t)i;
+}
+
+// the samples [j0, j1) of work item blockIdx.x and its leaf (false: no item)
+__device__ __forceinline__ bool fit_item(const uint32_t *st, const uint32_t *ipre, const uint32_t *item_leaf, int L,
+                                         uint32_t &leaf, uint32_t &j0, uint32_t &j1) {
+    const uint32_t item = blockIdx.x;
+    if (item >= ipre[L]) return false;
+    leaf = item_leaf[item];
+    j0 = st[leaf] + (item - ipre[leaf]) * FIT_CH;
+    j1 = min(j0 + FIT_CH, st[leaf + 1]);
+    return true;
+}
+
+// Forward: residual of every sample, r = a*dx + b - j/m (in the leaf's
+// scaled coordinates a' = a/s, dx' = dx*s), and the item's partial loss.
 template <int DT>
 __global__ __launch_bounds__(256) void k_rmi_fwd(const typename KT<DT>::U *sorted, uint32_t m, const uint32_t *st,
+                                                 const uint32_t *ipre, const uint32_t *item_leaf, int L,
                                                  const float *model, const float *scales, float *resid,
-                                                 float *stats) {
+                                                 float *part) {
     __shared__ float s_red[4];
-    const int i = blockIdx.x;
+    uint32_t i, j0, j1;
+    if (!fit_item(st, ipre, item_leaf, L, i, j0, j1)) return;
     const RmiLeaf lf = reinterpret_cast<const RmiLeaf *>(model + 8)[i];  // a, b, x0, lo
-    const uint32_t s = st[i], e = st[i + 1];
     const float sc = scales[i];
     const float a_s = __fdiv_rn(lf.x, sc);  // exact: sc is a power of two
     const float fm = (float)m;
     float loss = 0.f;
-    for (uint32_t j = s + threadIdx.x; j < e; j += 256) {
+    for (uint32_t j = j0 + threadIdx.x; j < j1; j += 256) {
         const float dx = __fmul_rn(__fsub_rn(to_f32(KT<DT>::image(sorted[j])), lf.z), sc);
         const float y = __fdiv_rn((float)j, fm);
         const float r = __fsub_rn(__fadd_rn(__fmul_rn(a_s, dx), lf.y), y);
@@ -185,22 +233,23 @@ __global__ __launch_bounds__(256) void k_rmi_fwd(const typename KT<DT>::U *sorte
         loss = __fadd_rn(loss, __fmul_rn(r, r));
     }
     loss = block_sum_f<256>(loss, s_red);
-    if (threadIdx.x == 0) stats[8 * i + 0] = loss;
+    if (threadIdx.x == 0) part[8 * blockIdx.x + 0] = loss;
 }
 
-// Backward: gradient of the loss w.r.t. (a', b) and the curvature terms
-// (Gauss-Newton = exact Hessian for this least-squares loss).
+// Backward: the item's partial gradient of the loss w.r.t. (a', b) and
+// curvature terms (Gauss-Newton = exact Hessian for this least-squares loss).
 template <int DT>
-__global__ __launch_bounds__(256) void k_rmi_bwd(const typename KT<DT>::U *sorted, uint32_t m, const uint32_t *st,
+__global__ __launch_bounds__(256) void k_rmi_bwd(const typename KT<DT>::U *sorted, const uint32_t *st,
+                                                 const uint32_t *ipre, const uint32_t *item_leaf, int L,
                                                  const float *model, const float *scales, const float *resid,
-                                                 float *stats) {
+                                                 float *part) {
     __shared__ float s_red[4];
-    const int i = blockIdx.x;
+    uint32_t i, j0, j1;
+    if (!fit_item(st, ipre, item_leaf, L, i, j0, j1)) return;
     const RmiLeaf lf = reinterpret_cast<const RmiLeaf *>(model + 8)[i];
-    const uint32_t s = st[i], e = st[i + 1];
     const float sc = scales[i];
     float ga = 0.f, gb = 0.f, hxx = 0.f, hx = 0.f;
-    for (uint32_t j = s + threadIdx.x; j < e; j += 256) {
+    for (uint32_t j = j0 + threadIdx.x; j < j1; j += 256) {
         const float dx = __fmul_rn(__fsub_rn(to_f32(KT<DT>::image(sorted[j])), lf.z), sc);
         const float r = resid[j];
         ga = __fadd_rn(ga, __fmul_rn(r, dx));
@@ -213,15 +262,38 @@ __global__ __launch_bounds__(256) void k_rmi_bwd(const typename KT<DT>::U *sorte
     hxx = block_sum_f<256>(hxx, s_red);
     hx = block_sum_f<256>(hx, s_red);
     if (threadIdx.x == 0) {
-        float *o = stats + 8 * i;
-        o[1] = 2.f * ga;
-        o[2] = 2.f * gb;
-        o[3] = 2.f * hxx;
-        o[4] = 2.f * hx;
-        o[5] = 2.f * (float)(e - s);
-        o[6] = sc;
-        o[7] = 0.f;
+        float *o = part + 8 * blockIdx.x;
+        o[1] = ga;
+        o[2] = gb;
+        o[3] = hxx;
+        o[4] = hx;
     }
+}
+
+// Per leaf: its items' partial sums added in item order, as
+// stats[8i..8i+7] = loss, dL/da', dL/db, 2*sum dx'^2, 2*sum dx', 2*count, s, 0.
+__global__ void k_rmi_sum(const uint32_t *st, const uint32_t *ipre, int L, const float *scales, const float *part,
+                          float *stats) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L) return;
+    float loss = 0.f, ga = 0.f, gb = 0.f, hxx = 0.f, hx = 0.f;
+    for (uint32_t k = ipre[i]; k < ipre[i + 1]; ++k) {
+        const float *q = part + 8 * k;
+        loss = __fadd_rn(loss, q[0]);
+        ga = __fadd_rn(ga, q[1]);
+        gb = __fadd_rn(gb, q[2]);
+        hxx = __fadd_rn(hxx, q[3]);
+        hx = __fadd_rn(hx, q[4]);
+    }
+    float *o = stats + 8 * i;
+    o[0] = loss;
+    o[1] = 2.f * ga;
+    o[2] = 2.f * gb;
+    o[3] = 2.f * hxx;
+    o[4] = 2.f * hx;
+    o[5] = 2.f * (float)(st[i + 1] - st[i]);
+    o[6] = scales[i];
+    o[7] = 0.f;
 }
 
 // Newton step per leaf on the quadratic loss, projected onto a' >= 0 (the
@@ -520,20 +592,31 @@ static inline size_t model_floats(int L) { return 8 + 4 * ((size_t)L + 1); }
 struct FitBufs {
     uint32_t *st;
     float *scales, *resid, *stats;
+    uint32_t *ipre, *item_leaf;  // work items of the leaf sums
+    float *part;                 // 8 partial sums per item
+    uint32_t max_items;
     float *model_copy;
 };
+// upper bound of the fit's work items (every leaf adds at most one partial piece)
+static inline size_t fit_max_items(uint32_t m, int L) { return (size_t)m / FIT_CH + (size_t)L + 1; }
+
 static size_t fit_scratch_bytes(uint32_t m, int L, bool with_model) {
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t mi = fit_max_items(m, L);
     return al((size_t)(L + 1) * 4) + al((size_t)L * 4) + al((size_t)m * 4) + al((size_t)L * 32) +
-           (with_model ? model_floats(L) * 4 : 0) + 256;
+           al((size_t)(L + 1) * 4) + al(mi * 4) + al(mi * 32) + (with_model ? model_floats(L) * 4 : 0) + 256;
 }
 
 static ak_status fit_scratch(Workspace *ws, uint32_t m, int L, bool with_model, FitBufs *f) {
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t mi = fit_max_items(m, L);
     const size_t o_sc = al((size_t)(L + 1) * 4);
     const size_t o_res = o_sc + al((size_t)L * 4);
     const size_t o_stats = o_res + al((size_t)m * 4);
-    const size_t o_model = o_stats + al((size_t)L * 32);
+    const size_t o_ipre = o_stats + al((size_t)L * 32);
+    const size_t o_ileaf = o_ipre + al((size_t)(L + 1) * 4);
+    const size_t o_part = o_ileaf + al(mi * 4);
+    const size_t o_model = o_part + al(mi * 32);
     const size_t need = fit_scratch_bytes(m, L, with_model);
     ak_status r = ws_reserve(ws, &ws->aux[1], &ws->aux_bytes[1], need);
     if (r != AK_OK) return r;
@@ -542,7 +625,39 @@ static ak_status fit_scratch(Workspace *ws, uint32_t m, int L, bool with_model, 
     f->scales = (float *)(base + o_sc);
     f->resid = (float *)(base + o_res);
     f->stats = (float *)(base + o_stats);
+    f->ipre = (uint32_t *)(base + o_ipre);
+    f->item_leaf = (uint32_t *)(base + o_ileaf);
+    f->part = (float *)(base + o_part);
+    f->max_items = (uint32_t)mi;
     f->model_copy = (float *)(base + o_model);
+    return AK_OK;
+}
+
+// Work items of the leaf sums, from the leaf starts f.st.
+static ak_status fit_items(hipStream_t s, int L, const FitBufs &f) {
+    hipLaunchKernelGGL(k_fit_items, dim3(1), dim3(1024), 0, s, (const uint32_t *)f.st, L, f.ipre);
+    AK_LAUNCH_CHECK("k_fit_items");
+    hipLaunchKernelGGL(k_fit_itemmap, dim3((unsigned)std::min(L, 4096)), dim3(256), 0, s, (const uint32_t *)f.ipre, L,
+                       f.item_leaf);
+    AK_LAUNCH_CHECK("k_fit_itemmap");
+    return AK_OK;
+}
+
+// Loss, gradient and curvature of every leaf into `stats` (8 per leaf).
+template <int DT>
+static ak_status leaf_sums(hipStream_t s, const typename KT<DT>::U *srt, uint32_t m, int L, const float *model,
+                           const FitBufs &f, float *stats) {
+    hipLaunchKernelGGL((k_rmi_fwd<DT>), dim3(f.max_items), dim3(256), 0, s, srt, m, (const uint32_t *)f.st,
+                       (const uint32_t *)f.ipre, (const uint32_t *)f.item_leaf, L, model, (const float *)f.scales,
+                       f.resid, f.part);
+    AK_LAUNCH_CHECK("k_rmi_fwd");
+    hipLaunchKernelGGL((k_rmi_bwd<DT>), dim3(f.max_items), dim3(256), 0, s, srt, (const uint32_t *)f.st,
+                       (const uint32_t *)f.ipre, (const uint32_t *)f.item_leaf, L, model, (const float *)f.scales,
+                       (const float *)f.resid, f.part);
+    AK_LAUNCH_CHECK("k_rmi_bwd");
+    hipLaunchKernelGGL(k_rmi_sum, dim3((unsigned)((L + 255) / 256)), dim3(256), 0, s, (const uint32_t *)f.st,
+                       (const uint32_t *)f.ipre, L, (const float *)f.scales, (const float *)f.part, stats);
+    AK_LAUNCH_CHECK("k_rmi_sum");
     return AK_OK;
 }
 
@@ -569,13 +684,9 @@ static ak_status fit_t(Workspace *ws, const void *sorted, uint32_t m, int L, int
     hipLaunchKernelGGL((k_rmi_leaf_init<DT>), dim3(lg), dim3(256), 0, s, srt, m, (const uint32_t *)f.st, model,
                        f.scales);
     AK_LAUNCH_CHECK("k_rmi_leaf_init");
+    if ((r = fit_items(s, L, f)) != AK_OK) return r;
     for (int it = 0; it < iters; ++it) {
-        hipLaunchKernelGGL((k_rmi_fwd<DT>), dim3(L), dim3(256), 0, s, srt, m, (const uint32_t *)f.st,
-                           (const float *)model, (const float *)f.scales, f.resid, f.stats);
-        AK_LAUNCH_CHECK("k_rmi_fwd");
-        hipLaunchKernelGGL((k_rmi_bwd<DT>), dim3(L), dim3(256), 0, s, srt, m, (const uint32_t *)f.st,
-                           (const float *)model, (const float *)f.scales, (const float *)f.resid, f.stats);
-        AK_LAUNCH_CHECK("k_rmi_bwd");
+        if ((r = leaf_sums<DT>(s, srt, m, L, model, f, f.stats)) != AK_OK) return r;
         hipLaunchKernelGGL(k_rmi_update, dim3(lg), dim3(256), 0, s, model, (const uint32_t *)f.st,
                            (const float *)f.scales, (const float *)f.stats);
         AK_LAUNCH_CHECK("k_rmi_update");
@@ -614,13 +725,8 @@ static ak_status leaf_grad_t(Workspace *ws, const void *sorted, uint32_t m, cons
     hipLaunchKernelGGL((k_leaf_scale<DT>), dim3(lg), dim3(256), 0, s, srt, (const uint32_t *)f.st, model_in,
                        f.scales);
     AK_LAUNCH_CHECK("k_leaf_scale");
-    hipLaunchKernelGGL((k_rmi_fwd<DT>), dim3(L), dim3(256), 0, s, srt, m, (const uint32_t *)f.st, model_in,
-                       (const float *)f.scales, f.resid, out);
-    AK_LAUNCH_CHECK("k_rmi_fwd");
-    hipLaunchKernelGGL((k_rmi_bwd<DT>), dim3(L), dim3(256), 0, s, srt, m, (const uint32_t *)f.st, model_in,
-                       (const float *)f.scales, (const float *)f.resid, out);
-    AK_LAUNCH_CHECK("k_rmi_bwd");
-    return AK_OK;
+    if ((r = fit_items(s, L, f)) != AK_OK) return r;
+    return leaf_sums<DT>(s, srt, m, L, model_in, f, out);
 }
 
 constexpr int LEARNED_CAP = 4096;  // keys of an on-chip chunk
