@@ -401,6 +401,7 @@ struct ChunkSmem {
     uint32_t cut;
     uint32_t bound[2];
     uint32_t code0;
+    uint32_t code_next;  // code of the key after the chunk
 };
 
 // One workgroup per piece of the code-ordered array: cuts it at code
@@ -441,6 +442,8 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(W / 2)))
             const uint32_t e = striped_elem<IPT>(w, j, lane);
             k[j] = e < len ? keys[pos + e] : U(0);
         }
+        // the key after the chunk, loaded beside the chunk (not after it)
+        const U knext = (tid == 0 && pos + len < end) ? keys[pos + len] : U(0);
         uint32_t cut = end;
         if (pos + len < end) {
             // code of every element; the element before lane 0 of item j is
@@ -455,6 +458,7 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(W / 2)))
             if (tid == 0) {
                 sm.cut = 0;
                 sm.code0 = c[0];
+                sm.code_next = rmi_code(h, lv, KT<DT>::image(knext), cb, scale);
             }
             __syncthreads();
             uint32_t best = 0;
@@ -470,15 +474,12 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(W / 2)))
                 }
                 if (e > 0 && e < len && c[j] != prev) best = e;
             }
+            // the chunk ends at a code change if its last element's code
+            // differs from the next key's
+#pragma unroll
+            for (int j = 0; j < IPT; ++j)
+                if (striped_elem<IPT>(w, j, lane) == len - 1 && c[j] != sm.code_next) best = len;
             if (best) atomicMax(&sm.cut, best);
-            __syncthreads();
-            if (tid == 0) {
-                // the last element of the chunk and the one after it
-                const uint32_t e_last = len - 1;
-                const uint32_t cl = rmi_code(h, lv, KT<DT>::image(keys[pos + e_last]), cb, scale);
-                const uint32_t cn = rmi_code(h, lv, KT<DT>::image(keys[pos + len]), cb, scale);
-                if (cn != cl) sm.cut = len;
-            }
             __syncthreads();
             const uint32_t q = sm.cut;
             if (q == 0) {
