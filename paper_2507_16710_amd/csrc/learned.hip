@@ -407,11 +407,11 @@ struct ChunkSmem {
 // One workgroup per piece of the code-ordered array: cuts it at code
 // changes into chunks of at most W*64*IPT keys and sorts each on chip.
 // The model's leaf table can be staged in LDS (dynamic shared memory).
-// Register budget: W/2 waves per SIMD, i.e. two W-wave workgroups per CU
-// (64 VGPRs at W = 16), so one workgroup's barriers overlap the other's
-// loads.
-template <int DT, int W, int IPT>
-__global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(W / 2))) void k_chunk_sort(typename KT<DT>::U *keys, uint32_t n, const float *model,
+// Register budget: WPE waves per SIMD (8: 64 VGPRs, so two 16-wave or four
+// 8-wave workgroups per CU), so one workgroup's barriers overlap the
+// others' loads.
+template <int DT, int W, int IPT, int WPE>
+__global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void k_chunk_sort(typename KT<DT>::U *keys, uint32_t n, const float *model,
                                                        int cb, uint32_t piece, FbRun *fb, LearnedState *ls,
                                                        int staged) {
     using U = typename KT<DT>::U;
@@ -730,7 +730,31 @@ static ak_status leaf_grad_t(Workspace *ws, const void *sorted, uint32_t m, cons
     return leaf_sums<DT>(s, srt, m, L, model_in, f, out);
 }
 
-constexpr int LEARNED_CAP = 4096;  // keys of an on-chip chunk
+// On-chip chunk shapes (waves, keys per lane, register budget in waves per
+// SIMD); $AK_CHUNK_VARIANT picks one (default 0).  The smallest capacity
+// sizes the fallback bookkeeping: a fallback run is longer than a chunk.
+struct ChunkShape {
+    int w, ipt, wpe;
+};
+constexpr ChunkShape CHUNK_SHAPES[3] = {{16, 4, 8}, {8, 4, 8}, {4, 8, 5}};
+constexpr int LEARNED_CAP_MIN = 2048;
+
+static int chunk_variant() {
+    static const int v = [] {
+        const char *e = getenv("AK_CHUNK_VARIANT");
+        const int x = (e && *e) ? atoi(e) : 0;
+        return x >= 0 && x < 3 ? x : 0;
+    }();
+    return v;
+}
+
+template <int DT, int V>
+static void launch_chunk_sort(hipStream_t s, uint32_t npieces, typename KT<DT>::U *keys, uint32_t n,
+                              const float *model, int cb, uint32_t piece, FbRun *fb, LearnedState *ls) {
+    constexpr ChunkShape c = CHUNK_SHAPES[V];
+    hipLaunchKernelGGL((k_chunk_sort<DT, c.w, c.ipt, c.wpe>), dim3(npieces), dim3(c.w * 64), 0, s, keys, n, model,
+                       cb, piece, fb, ls, 0);
+}
 
 // aux[0] of one learned call: sample keys | model | learned state |
 // fallback runs | flags | fallback range bounds
@@ -758,9 +782,9 @@ static ak_status learned_t(Workspace *ws, void *keys, int64_t n64, const ak_lear
     const int L = cfg->leaves;
     const uint32_t m = (uint32_t)sample_count(n64, cfg->sample_frac);
     const int cb = code_bits(n64);
-    constexpr int CW = 16, CIPT = 4, CAP = CW * 64 * CIPT;
-    static_assert(CAP == LEARNED_CAP, "chunk capacity");
-    const uint32_t fb_cap = n / CAP + 2;
+    const int cvar = chunk_variant();
+    const int CAP = CHUNK_SHAPES[cvar].w * 64 * CHUNK_SHAPES[cvar].ipt;
+    const uint32_t fb_cap = n / LEARNED_CAP_MIN + 2;
     ak_status r;
     // aux[0]: sample keys | model | learned state | fallback runs | flags
     const size_t off_model = ((size_t)m * sizeof(U) + 255) & ~size_t(255);
@@ -801,8 +825,11 @@ static ak_status learned_t(Workspace *ws, void *keys, int64_t n64, const ak_lear
     // keeps the workgroup's LDS small enough for several per CU.
     const size_t stage = rmi_stage_bytes(L);
     ProfScope ps_chunk("chunk_sort", s);
-    hipLaunchKernelGGL((k_chunk_sort<DT, CW, CIPT>), dim3(npieces), dim3(CW * 64), 0, s, (U *)keys, n,
-                       (const float *)model, cb, piece, fb, ls, 0);
+    switch (cvar) {
+    case 0: launch_chunk_sort<DT, 0>(s, npieces, (U *)keys, n, (const float *)model, cb, piece, fb, ls); break;
+    case 1: launch_chunk_sort<DT, 1>(s, npieces, (U *)keys, n, (const float *)model, cb, piece, fb, ls); break;
+    default: launch_chunk_sort<DT, 2>(s, npieces, (U *)keys, n, (const float *)model, cb, piece, fb, ls); break;
+    }
     AK_LAUNCH_CHECK("k_chunk_sort");
     // 5. fallback runs: radix-sorted as segments (runs of one repeated key
     // only cost the histogram read there: every digit place is trivial)
@@ -879,7 +906,7 @@ size_t learned_temp_bytes(int dt, int64_t n, const ak_learned_cfg *cfg) {
     const int64_t m = sample_count(n, cfg->sample_frac);
     const int L = cfg->leaves;
     const size_t kb = (size_t)dtype_bytes(dt);
-    const uint32_t fb_cap = (uint32_t)(n / LEARNED_CAP + 2);
+    const uint32_t fb_cap = (uint32_t)(n / LEARNED_CAP_MIN + 2);
     const size_t aux0 = al(learned_aux0_bytes(kb, (uint32_t)m, L, fb_cap));
     const size_t aux1 = al(fit_scratch_bytes((uint32_t)m, L, false));
     return aux0 + aux1 + radix_temp_bytes(dt, m, false) + code_partition_bytes(dt, n) +
