@@ -171,8 +171,11 @@ struct OsSmem {
     static constexpr size_t RAW = KEYS > CNT ? KEYS : CNT;
 };
 
-template <int DT, bool VAL, int W, int IPT, bool CODE>
-__global__ __launch_bounds__(W * 64) void k_onesweep(OnesweepArgs a) {
+// Register budget: two workgroups per CU (W/2 waves per SIMD) for
+// one-tile workgroups, one for the persistent ones (W/4).
+template <int DT, bool VAL, int W, int IPT, bool CODE, bool PERS>
+__global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(PERS ? W / 4 : W / 2))) void k_onesweep(
+    OnesweepArgs a) {
     using U = typename KT<DT>::U;
     using SM = OsSmem<U, VAL, CODE, W, IPT>;
     constexpr int B = W * 64, TILE = B * IPT;
@@ -231,31 +234,32 @@ __global__ __launch_bounds__(W * 64) void k_onesweep(OnesweepArgs a) {
         scale = (float)(1u << a.cb);
     }
     // Tiles are claimed in order from the pass counter, so a tile's
-    // predecessors are always held by running workgroups.  Key digits: one
-    // tile per workgroup (grid = tiles; a loop would keep per-thread
-    // constants live across tiles, costing registers and occupancy).  Code
-    // digits: a persistent grid that reuses the staged model table; each
-    // workgroup claims its next tile and issues that tile's loads before it
-    // waits in the look-back, so the HBM latency overlaps the wait.
+    // predecessors are always held by running workgroups.  PERS = false: one
+    // tile per workgroup (grid = tiles).  PERS (always for code digits, whose
+    // persistent grid reuses the staged model table): each workgroup claims
+    // its next tile and issues that tile's loads before it waits in the
+    // look-back, so the HBM latency overlaps the wait.  A workgroup holds at
+    // most two claims, the tile it works on and the next, so the smallest
+    // unfinished tile always belongs to a workgroup that can finish it.
     const uint32_t ntiles = (a.n + TILE - 1) / TILE;
-    auto load_tile = [&](uint32_t t, U(&kk)[IPT], uint32_t(&vv)[IPT]) {
+    auto load_tile = [&](uint32_t t, int w_, int lane_, U(&kk)[IPT], uint32_t(&vv)[IPT]) {
         const uint32_t tb = t * (uint32_t)TILE;
         const uint32_t tv = min((uint32_t)TILE, a.n - tb);
-        const U *sp = src + tb + w * 64 * IPT + lane;
+        const U *sp = src + tb + w_ * 64 * IPT + lane_;
         if (tv == (uint32_t)TILE) {
 #pragma unroll
             for (int jj = 0; jj < IPT; ++jj) kk[jj] = __builtin_nontemporal_load(sp + jj * 64);
         } else {
 #pragma unroll
             for (int jj = 0; jj < IPT; ++jj) {
-                const uint32_t e = striped_elem<IPT>(w, jj, lane);
+                const uint32_t e = striped_elem<IPT>(w_, jj, lane_);
                 kk[jj] = e < tv ? __builtin_nontemporal_load(sp + jj * 64) : U(0);
             }
         }
         if (VAL) {
 #pragma unroll
             for (int jj = 0; jj < IPT; ++jj) {
-                const uint32_t e = striped_elem<IPT>(w, jj, lane);
+                const uint32_t e = striped_elem<IPT>(w_, jj, lane_);
                 vv[jj] = e >= tv ? 0u : (vsrc ? __builtin_nontemporal_load(vsrc + tb + e) : tb + e);
             }
         }
@@ -266,8 +270,14 @@ __global__ __launch_bounds__(W * 64) void k_onesweep(OnesweepArgs a) {
     if (tile >= ntiles) return;
     U k[IPT];
     uint32_t v[IPT];
-    load_tile(tile, k, v);
+    load_tile(tile, w, lane, k, v);
     while (true) {
+    // Per-thread indices are re-derived each iteration from an opaque copy
+    // of the thread id: hoisted out of the loop they would stay live across
+    // tiles and cost registers (occupancy).
+    int tid = threadIdx.x;
+    if (PERS) asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, w = tid >> 6;
     const uint32_t tbase = tile * (uint32_t)TILE;
     const uint32_t tvalid = min((uint32_t)TILE, a.n - tbase);
     uint32_t dg[IPT], rk[IPT];
@@ -289,7 +299,7 @@ __global__ __launch_bounds__(W * 64) void k_onesweep(OnesweepArgs a) {
         lb_store(lb + d, lb_pack(epoch, tile % LB_GROUP == 0 ? LB_INC : LB_AGG, s_tot[d]));
     // the next claim (every thread read s_tile before rank_match's barriers;
     // block_exscan's barriers publish the new value)
-    if (CODE && tid == 0) s_tile = atomicAdd(&a.st->tile_ctr[a.place], 1u);
+    if (PERS && tid == 0) s_tile = atomicAdd(&a.st->tile_ctr[a.place], 1u);
 
     block_exscan<B, RADIX>(s_tot, s_start, s_wsum, tid);
     rank_finish<RADIX_BITS, W, IPT, uint16_t>(dg, rk, s_cnt, s_start, tid);
@@ -297,9 +307,9 @@ __global__ __launch_bounds__(W * 64) void k_onesweep(OnesweepArgs a) {
     uint32_t next = ntiles;
     U kn[IPT];
     uint32_t vn[IPT];
-    if (CODE) {
+    if (PERS) {
         next = s_tile;
-        if (next < ntiles) load_tile(next, kn, vn);
+        if (next < ntiles) load_tile(next, w, lane, kn, vn);
     }
 
     // two-level decoupled look-back (K*LB_M words per round trip): inside
@@ -350,7 +360,7 @@ __global__ __launch_bounds__(W * 64) void k_onesweep(OnesweepArgs a) {
             if (VAL) __builtin_nontemporal_store(s_vals[i], vdst + pos);
         }
     }
-    if (!CODE || next >= ntiles) break;
+    if (!PERS || next >= ntiles) break;
     __syncthreads();  // the tile's LDS is reused by the next one
     tile = next;
 #pragma unroll
@@ -436,13 +446,31 @@ size_t code_partition_bytes(int dt, int64_t n) {
     return 2 * al256((size_t)n * kb) + al256(lookback_words(tiles) * 8);
 }
 
+// Key-digit passes on a persistent grid ($AK_OS_PERSIST=1) or one workgroup
+// per tile (default).
+static bool os_persist() {
+    static const bool p = [] {
+        const char *e = getenv("AK_OS_PERSIST");
+        return e && *e == '1';
+    }();
+    return p;
+}
+
 template <int DT, bool VAL, bool CODE, int V>
 static void launch_pass_v(hipStream_t s, uint32_t tiles, const OnesweepArgs &a, size_t stage) {
     constexpr OsShape sh = CODE ? OS_CODE_SHAPES[key_bits(DT) == 64][V] : OS_SHAPES[key_bits(DT) == 64][VAL][V];
     // code digits: persistent grid (the staged table leaves room for one
-    // workgroup per CU); key digits: one workgroup per tile
-    const uint32_t grid = CODE ? std::min<uint32_t>(tiles, (uint32_t)num_cus() * (stage ? 1 : 2)) : tiles;
-    hipLaunchKernelGGL((k_onesweep<DT, VAL, sh.w, sh.ipt, CODE>), dim3(grid), dim3(sh.w * 64), stage, s, a);
+    // workgroup per CU); key digits: one workgroup per tile, or a persistent
+    // grid of two workgroups per CU
+    if (CODE) {
+        const uint32_t grid = std::min<uint32_t>(tiles, (uint32_t)num_cus() * (stage ? 1 : 2));
+        hipLaunchKernelGGL((k_onesweep<DT, VAL, sh.w, sh.ipt, true, true>), dim3(grid), dim3(sh.w * 64), stage, s, a);
+    } else if (os_persist()) {
+        const uint32_t grid = std::min<uint32_t>(tiles, (uint32_t)num_cus() * 2);
+        hipLaunchKernelGGL((k_onesweep<DT, VAL, sh.w, sh.ipt, false, true>), dim3(grid), dim3(sh.w * 64), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_onesweep<DT, VAL, sh.w, sh.ipt, false, false>), dim3(tiles), dim3(sh.w * 64), 0, s, a);
+    }
 }
 
 template <int DT, bool VAL, bool CODE>
