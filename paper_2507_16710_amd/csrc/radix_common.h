@@ -94,15 +94,42 @@ __device__ __forceinline__ void rank_match(const uint32_t (&dg)[IPT], uint32_t n
         if (valid && below == 0) cnt[dg[j]] = (C)(c + (uint32_t)__popcll(peers));
     }
     grp_sync<W>();
-    for (int d = tid; d < R; d += B) {
-        uint32_t run = 0;
+    if constexpr (B >= R && W % (B / R) == 0) {
+        // TPD adjacent threads per digit, each scanning W/TPD waves' counters
+        // (independent loads), joined by a shuffle scan inside the group
+        constexpr int TPD = B / R, WPT = W / TPD;
+        const int d = tid / TPD, g = tid % TPD;
+        uint32_t c[WPT];
 #pragma unroll
-        for (int ww = 0; ww < W; ++ww) {
-            const uint32_t c = s_cnt[ww * R + d];
-            s_cnt[ww * R + d] = (C)run;
-            run += c;
+        for (int i = 0; i < WPT; ++i) c[i] = s_cnt[(g * WPT + i) * R + d];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int i = 0; i < WPT; ++i) {
+            const uint32_t t = c[i];
+            c[i] = sum;
+            sum += t;
         }
-        s_tot[d] = run;
+        uint32_t incl = sum;
+#pragma unroll
+        for (int o = 1; o < TPD; o <<= 1) {
+            const uint32_t y = (uint32_t)__shfl_up((int)incl, o, TPD);
+            if (g >= o) incl += y;
+        }
+        const uint32_t base = incl - sum;
+#pragma unroll
+        for (int i = 0; i < WPT; ++i) s_cnt[(g * WPT + i) * R + d] = (C)(base + c[i]);
+        if (g == TPD - 1) s_tot[d] = incl;
+    } else {
+        for (int d = tid; d < R; d += B) {
+            uint32_t run = 0;
+#pragma unroll
+            for (int ww = 0; ww < W; ++ww) {
+                const uint32_t c = s_cnt[ww * R + d];
+                s_cnt[ww * R + d] = (C)run;
+                run += c;
+            }
+            s_tot[d] = run;
+        }
     }
     grp_sync<W>();
 }
