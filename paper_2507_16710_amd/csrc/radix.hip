@@ -171,11 +171,12 @@ struct OsSmem {
     static constexpr size_t RAW = KEYS > CNT ? KEYS : CNT;
 };
 
-// Register budget: two workgroups per CU (W/2 waves per SIMD) for
-// one-tile workgroups, one for the persistent ones (W/4).
+// Register budget: for 64-bit keys two workgroups per CU (W/2 waves per
+// SIMD) for one-tile workgroups, one for the persistent ones (W/4); 32-bit
+// keys use larger tiles that would spill under the tighter budget.
 template <int DT, bool VAL, int W, int IPT, bool CODE, bool PERS>
-__global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(PERS ? W / 4 : W / 2))) void k_onesweep(
-    OnesweepArgs a) {
+__global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(
+    PERS ? W / 4 : (key_bits(DT) == 64 ? W / 2 : 1)))) void k_onesweep(OnesweepArgs a) {
     using U = typename KT<DT>::U;
     using SM = OsSmem<U, VAL, CODE, W, IPT>;
     constexpr int B = W * 64, TILE = B * IPT;
@@ -371,6 +372,213 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(PERS ? W
     }
 }
 
+// ------------------------------------------- reduce-then-scan passes
+// The same stable digit pass without any waiting between workgroups: a
+// read-only kernel counts every chunk's digits, a scan turns the counts
+// into each chunk's output offset per digit (global digit offset plus the
+// counts of the chunks before it), and the scatter kernel walks its chunk's
+// tiles in order, carrying the running offsets in LDS.  One more read of
+// the keys per pass than the one-sweep pass, no look-back.
+
+// Source and destination of pass pd (the one-sweep pass's routing).
+template <typename U, bool VAL>
+__device__ __forceinline__ void pass_route(const OnesweepArgs &a, const PassDesc &pd, const U *&src, U *&dst,
+                                           const uint32_t *&vsrc, uint32_t *&vdst) {
+    const int j = pd.j, q = pd.q;
+    vsrc = nullptr;
+    vdst = nullptr;
+    if (!VAL) {
+        if (odd_route(q, a.t1)) {
+            auto buf = [&](int i) { return (U *)((i == 0 || i == q) ? a.keys : ((i & 1) ? a.t0 : a.t1)); };
+            src = buf(j);
+            dst = buf(j + 1);
+        } else {
+            src = (const U *)((j & 1) ? a.t0 : a.keys);
+            dst = (U *)((j & 1) ? a.keys : a.t0);
+        }
+    } else {
+        src = (const U *)(j == 0 ? a.keys : (((j - 1) & 1) ? a.t1 : a.t0));
+        dst = (U *)((j & 1) ? a.t1 : a.t0);
+        auto vb = [&](int i) { return (((q - 1 - i) & 1) == 0) ? a.perm : a.v0; };
+        vsrc = j == 0 ? nullptr : vb(j - 1);
+        vdst = vb(j);
+    }
+}
+
+// Digit counts of chunk blockIdx.x (TILE * chunk_tiles keys) at this place.
+template <int DT, bool VAL, bool CODE, int TILE>
+__global__ __launch_bounds__(256) void k_rts_count(OnesweepArgs a) {
+    using U = typename KT<DT>::U;
+    constexpr int B = 256;
+    const PassDesc pd = a.st->desc[a.place];
+    if (!pd.active) return;
+    __shared__ uint32_t s_h[RADIX];
+    extern __shared__ float4 s_leaves[];
+    const int tid = threadIdx.x;
+    s_h[tid] = 0;
+    RmiHead h;
+    const RmiLeaf *leaves = nullptr;
+    float scale = 0.f;
+    if (CODE) {
+        h = rmi_head(a.model);
+        leaves = rmi_stage(a.model, a.staged ? s_leaves : nullptr);
+        scale = (float)(1u << a.cb);
+    }
+    const U *src;
+    U *dst;
+    const uint32_t *vsrc;
+    uint32_t *vdst;
+    pass_route<U, VAL>(a, pd, src, dst, vsrc, vdst);
+    const int shift = pd.shift;
+    __syncthreads();
+    const uint32_t c = blockIdx.x;
+    const uint32_t lo = c * a.chunk_tiles * (uint32_t)TILE;
+    const uint32_t hi = min(a.n, lo + a.chunk_tiles * (uint32_t)TILE);
+    constexpr int ITEMS = 8;
+    for (uint32_t base = lo; base < hi; base += B * ITEMS) {
+        U v[ITEMS];
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+            const uint32_t i = base + it * B + tid;
+            v[it] = i < hi ? __builtin_nontemporal_load(src + i) : U(0);
+        }
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+            const uint32_t i = base + it * B + tid;
+            if (i >= hi) break;
+            U t = KT<DT>::image(v[it]);
+            if (CODE) t = (U)rmi_code(h, leaves, t, a.cb, scale);
+            const uint32_t d = (uint32_t)(t >> shift) & (RADIX - 1);
+            const uint64_t act = ballot64(true);
+            const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+            if (ballot64(d == d0) == act) {
+                if (count_below(act) == 0) atomicAdd(&s_h[d0], (uint32_t)__popcll(act));
+            } else {
+                atomicAdd(&s_h[d], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    a.ccnt[(size_t)tid * a.nchunks + c] = s_h[tid];
+}
+
+// Per digit (one workgroup each): exclusive scan of the chunk counts plus
+// the digit's global offset, in place.
+__global__ __launch_bounds__(1024) void k_rts_scan(OnesweepArgs a) {
+    const PassDesc pd = a.st->desc[a.place];
+    if (!pd.active) return;
+    __shared__ uint32_t s_wsum[16];
+    __shared__ uint32_t s_carry;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int d = blockIdx.x;
+    uint32_t *row = a.ccnt + (size_t)d * a.nchunks;
+    if (tid == 0) s_carry = a.st->base[a.place][d];
+    __syncthreads();
+    for (uint32_t b0 = 0; b0 < a.nchunks; b0 += 1024) {
+        const uint32_t i = b0 + tid;
+        const uint32_t v = i < a.nchunks ? row[i] : 0u;
+        const uint32_t incl = wave_incl_scan(v);
+        if (lane == 63) s_wsum[w] = incl;
+        __syncthreads();
+        uint32_t run = s_carry;
+        for (int ww = 0; ww < w; ++ww) run += s_wsum[ww];
+        if (i < a.nchunks) row[i] = run + incl - v;
+        __syncthreads();
+        if (tid == 1023) s_carry = run + incl;
+        __syncthreads();
+    }
+}
+
+// Scatter of chunk blockIdx.x: its tiles in order, each ranked stably on
+// chip and written to the chunk's running digit offsets.
+template <int DT, bool VAL, int W, int IPT, bool CODE>
+__global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(
+    CODE ? W / 4 : (key_bits(DT) == 64 ? W / 2 : 1)))) void k_rts_scatter(OnesweepArgs a) {
+    using U = typename KT<DT>::U;
+    using SM = OsSmem<U, VAL, CODE, W, IPT>;
+    constexpr int B = W * 64, TILE = B * IPT;
+    const PassDesc pd = a.st->desc[a.place];
+    if (!pd.active) return;
+    __shared__ __align__(16) uint8_t s_raw[SM::RAW];
+    __shared__ uint32_t s_tot[RADIX], s_start[RADIX], s_glob[RADIX], s_run[RADIX];
+    __shared__ uint32_t s_wsum[W];
+    uint16_t *s_cnt = reinterpret_cast<uint16_t *>(s_raw);
+    U *s_keys = reinterpret_cast<U *>(s_raw);
+    uint32_t *s_vals = reinterpret_cast<uint32_t *>(s_raw + (size_t)TILE * sizeof(U));
+    uint8_t *s_dig = s_raw + (size_t)TILE * sizeof(U) + (VAL ? (size_t)TILE * 4 : 0);
+    extern __shared__ float4 s_leaves[];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const U *src;
+    U *dst;
+    const uint32_t *vsrc;
+    uint32_t *vdst;
+    pass_route<U, VAL>(a, pd, src, dst, vsrc, vdst);
+    const bool last = pd.j == pd.q - 1;
+    const int shift = pd.shift;
+    RmiHead h;
+    const RmiLeaf *leaves = nullptr;
+    float scale = 0.f;
+    if (CODE) {
+        h = rmi_head(a.model);
+        leaves = rmi_stage(a.model, a.staged ? s_leaves : nullptr);
+        scale = (float)(1u << a.cb);
+    }
+    const uint32_t c = blockIdx.x;
+    for (int d = tid; d < RADIX; d += B) s_run[d] = a.ccnt[(size_t)d * a.nchunks + c];
+    const uint32_t t0 = c * a.chunk_tiles;
+    const uint32_t t1 = min((a.n + TILE - 1) / TILE, t0 + a.chunk_tiles);
+    for (uint32_t tile = t0; tile < t1; ++tile) {
+        const uint32_t tbase = tile * (uint32_t)TILE;
+        const uint32_t tvalid = min((uint32_t)TILE, a.n - tbase);
+        U k[IPT];
+        uint32_t v[IPT], dg[IPT], rk[IPT];
+        const U *sp = src + tbase + w * 64 * IPT + lane;
+#pragma unroll
+        for (int jj = 0; jj < IPT; ++jj) {
+            const uint32_t e = striped_elem<IPT>(w, jj, lane);
+            k[jj] = e < tvalid ? __builtin_nontemporal_load(sp + jj * 64) : U(0);
+            if (VAL) v[jj] = e >= tvalid ? 0u : (vsrc ? __builtin_nontemporal_load(vsrc + tbase + e) : tbase + e);
+        }
+#pragma unroll
+        for (int jj = 0; jj < IPT; ++jj) {
+            const uint32_t e = striped_elem<IPT>(w, jj, lane);
+            U t = KT<DT>::image(k[jj]);
+            if (CODE) t = (U)rmi_code(h, leaves, t, a.cb, scale);
+            dg[jj] = e < tvalid ? (uint32_t)(t >> shift) & (RADIX - 1) : 0u;
+        }
+        rank_match<RADIX_BITS, W, IPT, uint16_t>(dg, tvalid, rk, s_cnt, s_tot, tid);
+        block_exscan<B, RADIX>(s_tot, s_start, s_wsum, tid);
+        rank_finish<RADIX_BITS, W, IPT, uint16_t>(dg, rk, s_cnt, s_start, tid);
+        for (int d = tid; d < RADIX; d += B) {
+            s_glob[d] = s_run[d] - s_start[d];
+            s_run[d] += s_tot[d];
+        }
+        __syncthreads();  // counters are dead from here on: their bytes hold keys
+#pragma unroll
+        for (int jj = 0; jj < IPT; ++jj) {
+            const uint32_t e = striped_elem<IPT>(w, jj, lane);
+            if (e < tvalid) {
+                s_keys[rk[jj]] = k[jj];
+                if (CODE) s_dig[rk[jj]] = (uint8_t)dg[jj];
+                if (VAL) s_vals[rk[jj]] = v[jj];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int jj = 0; jj < IPT; ++jj) {
+            const uint32_t i = (uint32_t)(jj * B + tid);
+            if (i < tvalid) {
+                const U key = s_keys[i];
+                const uint32_t d = CODE ? (uint32_t)s_dig[i] : (uint32_t)(KT<DT>::image(key) >> shift) & (RADIX - 1);
+                const uint32_t pos = s_glob[d] + i;
+                if (!VAL || !last) __builtin_nontemporal_store(key, dst + pos);
+                if (VAL) __builtin_nontemporal_store(s_vals[i], vdst + pos);
+            }
+        }
+        __syncthreads();  // the tile's LDS is reused by the next one
+    }
+}
+
 // ---------------------------------------------------------- finalize
 // Sort mode: after a single active pass (or an odd number without the
 // second scratch buffer) the result sits in keys0 and is copied back.  Sortperm mode: with no active pass (all keys
@@ -428,6 +636,10 @@ static inline int tile_keys(int dt, bool val) { return os_tile(dt, val); }
 
 static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// Bytes of the chunk counts of a reduce-then-scan pass over `tiles` tiles
+// (at most one chunk per tile).
+static size_t rts_bytes(size_t tiles) { return tiles * RADIX * 4; }
+
 size_t radix_temp_bytes(int dt, int64_t n, bool perm) {
     if (n <= small_sort_capacity(dt)) return 0;
     const size_t kb = (size_t)dtype_bytes(dt);
@@ -435,7 +647,7 @@ size_t radix_temp_bytes(int dt, int64_t n, bool perm) {
     // two key-sized ping-pong buffers (sort: the second one lets an odd
     // number of passes end in the caller's buffer; sortperm: the const keys
     // are never written), the look-back words, and the index buffer
-    size_t b = 2 * al256((size_t)n * kb) + al256(lookback_words(tiles) * 8);
+    size_t b = 2 * al256((size_t)n * kb) + al256(lookback_words(tiles) * 8) + al256(rts_bytes(tiles));
     if (perm) b += al256((size_t)n * 4);
     return b;
 }
@@ -443,7 +655,7 @@ size_t radix_temp_bytes(int dt, int64_t n, bool perm) {
 size_t code_partition_bytes(int dt, int64_t n) {
     const size_t kb = (size_t)dtype_bytes(dt);
     const size_t tiles = (size_t)((n + os_code_tile(dt) - 1) / os_code_tile(dt));
-    return 2 * al256((size_t)n * kb) + al256(lookback_words(tiles) * 8);
+    return 2 * al256((size_t)n * kb) + al256(lookback_words(tiles) * 8) + al256(rts_bytes(tiles));
 }
 
 // Key-digit passes on a persistent grid ($AK_OS_PERSIST=1) or one workgroup
@@ -456,8 +668,39 @@ static bool os_persist() {
     return p;
 }
 
+// Reduce-then-scan passes ($AK_OS_RTS=1) instead of one-sweep passes.
+static bool os_rts() {
+    static const bool p = [] {
+        const char *e = getenv("AK_OS_RTS");
+        return e && *e == '1';
+    }();
+    return p;
+}
+
+// Tiles per reduce-then-scan chunk: enough chunks for four workgroups per
+// CU, at most 16 tiles each.
+static uint32_t rts_chunk_tiles(uint32_t tiles) {
+    const uint32_t want = (uint32_t)num_cus() * 4;
+    return std::max<uint32_t>(1, std::min<uint32_t>(16, (tiles + want - 1) / want));
+}
+
+template <int DT, bool VAL, bool CODE, int V>
+static void launch_rts_v(hipStream_t s, uint32_t tiles, OnesweepArgs a, size_t stage) {
+    constexpr OsShape sh = CODE ? OS_CODE_SHAPES[key_bits(DT) == 64][V] : OS_SHAPES[key_bits(DT) == 64][VAL][V];
+    constexpr int TILE = sh.w * 64 * sh.ipt;
+    a.chunk_tiles = rts_chunk_tiles(tiles);
+    a.nchunks = (tiles + a.chunk_tiles - 1) / a.chunk_tiles;
+    hipLaunchKernelGGL((k_rts_count<DT, VAL, CODE, TILE>), dim3(a.nchunks), dim3(256), stage, s, a);
+    hipLaunchKernelGGL(k_rts_scan, dim3(RADIX), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL((k_rts_scatter<DT, VAL, sh.w, sh.ipt, CODE>), dim3(a.nchunks), dim3(sh.w * 64), stage, s, a);
+}
+
 template <int DT, bool VAL, bool CODE, int V>
 static void launch_pass_v(hipStream_t s, uint32_t tiles, const OnesweepArgs &a, size_t stage) {
+    if (os_rts()) {
+        launch_rts_v<DT, VAL, CODE, V>(s, tiles, a, stage);
+        return;
+    }
     constexpr OsShape sh = CODE ? OS_CODE_SHAPES[key_bits(DT) == 64][V] : OS_SHAPES[key_bits(DT) == 64][VAL][V];
     // code digits: persistent grid (the staged table leaves room for one
     // workgroup per CU); key digits: one workgroup per tile, or a persistent
@@ -487,6 +730,7 @@ static ak_status launch_passes(hipStream_t stream, Workspace *ws, RunState *st, 
     a.v0 = v0;
     a.perm = perm;
     a.lookback = ws->lookback;
+    a.ccnt = (uint32_t *)ws->aux[4];
     a.st = st;
     a.n = n;
     a.model = model;
@@ -610,6 +854,7 @@ static ak_status radix_sort_t(Workspace *ws, void *keys, uint32_t *perm, int64_t
     const int TILE = tile_keys(DT, pm);
     const size_t tiles = (n + TILE - 1) / TILE;
     if ((r = ws_reserve_lookback(ws, lookback_words(tiles) * 8)) != AK_OK) return r;
+    if ((r = ws_reserve(ws, &ws->aux[4], &ws->aux_bytes[4], rts_bytes(tiles))) != AK_OK) return r;
     uint32_t epoch;
     if ((r = ws_next_epoch(ws, &epoch)) != AK_OK) return r;
     RunState *st = ws->state + slot;
@@ -673,6 +918,7 @@ static ak_status code_partition_t(Workspace *ws, void *keys, uint32_t n, const f
     const int TILE = os_code_tile(DT);
     const size_t tiles = (n + TILE - 1) / TILE;
     if ((r = ws_reserve_lookback(ws, lookback_words(tiles) * 8)) != AK_OK) return r;
+    if ((r = ws_reserve(ws, &ws->aux[4], &ws->aux_bytes[4], rts_bytes(tiles))) != AK_OK) return r;
     uint32_t epoch;
     if ((r = ws_next_epoch(ws, &epoch)) != AK_OK) return r;
     const int nplaces = (cb + RADIX_BITS - 1) / RADIX_BITS;

@@ -16,6 +16,10 @@ struct OnesweepArgs {
     int place;
     int cb;               // code bits (code digits only)
     int staged;           // code digits: model table staged in dynamic LDS
+    // reduce-then-scan passes: digit counts, then offsets, per chunk of
+    // chunk_tiles tiles, digit-major (ccnt[d * nchunks + c])
+    uint32_t *ccnt;
+    uint32_t nchunks, chunk_tiles;
 };
 
 // One-sweep tile shapes (W waves x IPT keys per lane).  A few shapes are
