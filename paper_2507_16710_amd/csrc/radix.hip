@@ -608,9 +608,12 @@ __global__ __launch_bounds__(W * 64) void k_small_sort(const typename KT<DT>::U 
 
 // ------------------------------------------------------------ driver
 // default shape per (64-bit keys, values), from the tuning sweep
-static const int OS_DEFAULT[2][2] = {{0, 0}, {0, 0}};
-// default shape of the code-digit passes per key width
-static const int OS_CODE_DEFAULT[2] = {0, 0};
+// (measured on 2^28 float32 and 2^30 int64 keys: 16 waves x 16 keys and
+// 16 waves x 8 keys per lane)
+static const int OS_DEFAULT[2][2] = {{3, 0}, {3, 0}};
+// default shape of the code-digit passes per key width (16 waves x 6 keys
+// for 64-bit keys, measured on the 2^31 mixture)
+static const int OS_CODE_DEFAULT[2] = {0, 2};
 
 static int env_variant(const char *name) {
     const char *e = getenv(name);
