@@ -83,6 +83,8 @@ ak_status ak_sortperm_f64(const double *keys, uint32_t *perm, int64_t n, ak_stre
 /* ------------------------------------------------------- segmented sort
  * Batched form of Sec. II-B's sort: for s in [0, nseg) the segment
  * keys[offsets[s] .. offsets[s+1]) is sorted ascending in place, on its own.
+ * keys must hold at least offsets[nseg] elements (the library cannot check
+ * the length of a raw pointer; the Python binding checks it).
  * offsets is a DEVICE array of nseg+1 nondecreasing int64 values >= 0; the
  * call reads offsets[0] and offsets[nseg] back to the host (one small
  * synchronous copy) to size its scratch.  Keys outside

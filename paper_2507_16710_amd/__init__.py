@@ -168,6 +168,11 @@ def segmented_sort_(keys: torch.Tensor, offsets: torch.Tensor, dtype: str | None
     if offsets.dtype != torch.int64:
         raise TypeError("offsets must be int64")
     dt = _dtype(keys, dtype)
+    if offsets.numel() >= 2:
+        # the library sees a raw pointer: the segments must lie inside keys
+        lo, hi = (int(x) for x in offsets[[0, -1]].tolist())
+        if lo < 0 or hi > keys.numel() or hi < lo:
+            raise ValueError(f"offsets span [{lo}, {hi}) but keys has {keys.numel()} elements")
     with torch.cuda.device(keys.device):
         _check(load_library().ak_segmented_sort(keys.data_ptr(), offsets.data_ptr(), offsets.numel() - 1,
                                                 DTYPE_CODE[dt], _stream(keys)), "ak_segmented_sort")

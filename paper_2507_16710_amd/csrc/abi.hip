@@ -37,16 +37,18 @@ static std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
 
 constexpr int RUN_SLOTS = 4;
 
-__global__ void k_zero_u64(uint64_t *p, size_t n) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        p[i] = 0;
+// Zeroes n 8-byte words at p, then `tail` (< 8) more bytes after them.
+__global__ void k_zero_u64(uint64_t *p, size_t n, uint32_t tail) {
+    const size_t t0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    for (size_t i = t0; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+    if (t0 < tail) reinterpret_cast<uint8_t *>(p + n)[t0] = 0;
 }
 
 ak_status zero_fill(hipStream_t s, void *p, size_t bytes) {
+    if (!bytes) return AK_OK;
     const size_t n = bytes / 8;
-    if (!n) return AK_OK;
-    const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_zero_u64, dim3(grid), dim3(256), 0, s, (uint64_t *)p, n);
+    const unsigned grid = (unsigned)std::max<size_t>(1, std::min<size_t>((n + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_zero_u64, dim3(grid), dim3(256), 0, s, (uint64_t *)p, n, (uint32_t)(bytes % 8));
     AK_LAUNCH_CHECK("k_zero_u64");
     return AK_OK;
 }

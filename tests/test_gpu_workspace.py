@@ -23,16 +23,22 @@ def _offsets(lengths) -> np.ndarray:
 @pytest.mark.parametrize("dt", ["u64", "f32"])
 def test_arena_paths_bit_exact(dt):
     rng = np.random.default_rng(zlib.crc32(f"arena{dt}".encode()))
+
+    def segments(n):
+        # segment lengths summing to n: tiny, empty, one-workgroup and huge ones
+        lens = [5, n // 4, 0, 3000, n // 2, 1]
+        return _offsets(lens + [n - sum(lens)])
+
     n = 300_001
-    lens = [5, 70_000, 0, 3000, 150_000, 1, 77_000 - 5]
-    off = _offsets(lens)
-    nseg = len(lens)
+    nseg = len(segments(n)) - 1
     need = max(ak.temp_bytes("sort", n, dt), ak.temp_bytes("sortperm", n, dt),
-               ak.temp_bytes_segmented(int(off[-1]), nseg, dt), ak.temp_bytes("learned", n, dt))
+               ak.temp_bytes_segmented(n, nseg, dt), ak.temp_bytes("learned", n, dt))
     arena = torch.empty(need, dtype=torch.uint8, device="cuda")
     ak.set_workspace(arena)
     try:
         for it in range(2):   # the second round reuses the arena's carving
+            off = segments(n)
+            assert int(off[-1]) == n
             k = random_keys(dt, n, rng, "mixed")
             print(f"arena dt={dt} round={it} sort", flush=True)
             t = to_gpu(k, dt)
@@ -43,10 +49,9 @@ def test_arena_paths_bit_exact(dt):
             p = ak.sortperm(t, dtype=dt)
             assert np.array_equal(p.cpu().numpy().view(np.uint32), oracle.sortperm(k))
             print(f"arena dt={dt} round={it} segmented", flush=True)
-            ks = k[: int(off[-1])]
-            t = to_gpu(ks, dt)
+            t = to_gpu(k, dt)
             ak.segmented_sort_(t, torch.from_numpy(off).cuda(), dtype=dt)
-            assert np.array_equal(bits(to_host(t, dt)), bits(oracle.segsort(ks, off)))
+            assert np.array_equal(bits(to_host(t, dt)), bits(oracle.segsort(k, off)))
             print(f"arena dt={dt} round={it} learned", flush=True)
             t = to_gpu(k, dt)
             ak.sort_learned_(t, dtype=dt)
@@ -72,3 +77,15 @@ def test_arena_paths_bit_exact(dt):
     t = to_gpu(k, dt)
     ak.sort_(t, dtype=dt)
     assert np.array_equal(bits(to_host(t, dt)), bits(oracle.sort(k)))
+
+
+def test_segment_offsets_beyond_keys_are_refused():
+    """Offsets that run past the key array are refused by the binding before
+    the library is called (the C call sees only a raw pointer)."""
+    t = torch.zeros(1000, dtype=torch.int64, device="cuda")
+    off = torch.tensor([0, 500, 2000], dtype=torch.int64, device="cuda")
+    with pytest.raises(ValueError):
+        ak.segmented_sort_(t, off, dtype="i64")
+    off = torch.tensor([-1, 500], dtype=torch.int64, device="cuda")
+    with pytest.raises(ValueError):
+        ak.segmented_sort_(t, off, dtype="i64")
