@@ -281,16 +281,16 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(
     const int lane = tid & 63, w = tid >> 6;
     const uint32_t tbase = tile * (uint32_t)TILE;
     const uint32_t tvalid = min((uint32_t)TILE, a.n - tbase);
-    uint32_t dg[IPT], rk[IPT];
+    uint32_t rd[IPT];  // digit, then rank | digit << 16
 #pragma unroll
     for (int jj = 0; jj < IPT; ++jj) {
         const uint32_t e = striped_elem<IPT>(w, jj, lane);
         U t = KT<DT>::image(k[jj]);
         if (CODE) t = (U)rmi_code(h, leaves, t, a.cb, scale);
-        dg[jj] = e < tvalid ? (uint32_t)(t >> shift) & (RADIX - 1) : 0u;
+        rd[jj] = e < tvalid ? (uint32_t)(t >> shift) & (RADIX - 1) : 0u;
     }
 
-    rank_match<RADIX_BITS, W, IPT, uint16_t>(dg, tvalid, rk, s_cnt, s_tot, tid);
+    rank_match_packed<RADIX_BITS, W, IPT, uint16_t>(rd, tvalid, s_cnt, s_tot, tid);
 
     // publish this tile's digit counts first, so successors can look back
     // (the first tile of a group is inclusive within its group)
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(
     if (PERS && tid == 0) s_tile = atomicAdd(&a.st->tile_ctr[a.place], 1u);
 
     block_exscan<B, RADIX>(s_tot, s_start, s_wsum, tid);
-    rank_finish<RADIX_BITS, W, IPT, uint16_t>(dg, rk, s_cnt, s_start, tid);
+    rank_finish_packed<RADIX_BITS, W, IPT, uint16_t>(rd, s_cnt, s_start, tid);
 
     uint32_t next = ntiles;
     U kn[IPT];
@@ -341,9 +341,10 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(
     for (int jj = 0; jj < IPT; ++jj) {
         const uint32_t e = striped_elem<IPT>(w, jj, lane);
         if (e < tvalid) {
-            s_keys[rk[jj]] = k[jj];
-            if (CODE) s_dig[rk[jj]] = (uint8_t)dg[jj];
-            if (VAL) s_vals[rk[jj]] = v[jj];
+            const uint32_t r = rd[jj] & 0xFFFFu;
+            s_keys[r] = k[jj];
+            if (CODE) s_dig[r] = (uint8_t)(rd[jj] >> 16);
+            if (VAL) s_vals[r] = v[jj];
         }
     }
     __syncthreads();
@@ -528,10 +529,15 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(
     const uint32_t t0 = c * a.chunk_tiles;
     const uint32_t t1 = min((a.n + TILE - 1) / TILE, t0 + a.chunk_tiles);
     for (uint32_t tile = t0; tile < t1; ++tile) {
+        // per-thread indices re-derived each tile from an opaque copy of the
+        // thread id (hoisted out of the loop they would be spilled)
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const int lane = tid & 63, w = tid >> 6;
         const uint32_t tbase = tile * (uint32_t)TILE;
         const uint32_t tvalid = min((uint32_t)TILE, a.n - tbase);
         U k[IPT];
-        uint32_t v[IPT], dg[IPT], rk[IPT];
+        uint32_t v[IPT], rd[IPT];
         const U *sp = src + tbase + w * 64 * IPT + lane;
 #pragma unroll
         for (int jj = 0; jj < IPT; ++jj) {
@@ -544,11 +550,11 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(
             const uint32_t e = striped_elem<IPT>(w, jj, lane);
             U t = KT<DT>::image(k[jj]);
             if (CODE) t = (U)rmi_code(h, leaves, t, a.cb, scale);
-            dg[jj] = e < tvalid ? (uint32_t)(t >> shift) & (RADIX - 1) : 0u;
+            rd[jj] = e < tvalid ? (uint32_t)(t >> shift) & (RADIX - 1) : 0u;
         }
-        rank_match<RADIX_BITS, W, IPT, uint16_t>(dg, tvalid, rk, s_cnt, s_tot, tid);
+        rank_match_packed<RADIX_BITS, W, IPT, uint16_t>(rd, tvalid, s_cnt, s_tot, tid);
         block_exscan<B, RADIX>(s_tot, s_start, s_wsum, tid);
-        rank_finish<RADIX_BITS, W, IPT, uint16_t>(dg, rk, s_cnt, s_start, tid);
+        rank_finish_packed<RADIX_BITS, W, IPT, uint16_t>(rd, s_cnt, s_start, tid);
         for (int d = tid; d < RADIX; d += B) {
             s_glob[d] = s_run[d] - s_start[d];
             s_run[d] += s_tot[d];
@@ -558,9 +564,10 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(
         for (int jj = 0; jj < IPT; ++jj) {
             const uint32_t e = striped_elem<IPT>(w, jj, lane);
             if (e < tvalid) {
-                s_keys[rk[jj]] = k[jj];
-                if (CODE) s_dig[rk[jj]] = (uint8_t)dg[jj];
-                if (VAL) s_vals[rk[jj]] = v[jj];
+                const uint32_t r = rd[jj] & 0xFFFFu;
+                s_keys[r] = k[jj];
+                if (CODE) s_dig[r] = (uint8_t)(rd[jj] >> 16);
+                if (VAL) s_vals[r] = v[jj];
             }
         }
         __syncthreads();
