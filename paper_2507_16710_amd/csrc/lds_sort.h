@@ -25,7 +25,7 @@ __device__ __forceinline__ void lds_sort_regs(typename KT<DT>::U (&k)[IPT], type
     using U = typename KT<DT>::U;
     constexpr int B = W * 64;
     const int lane = tid & 63, w = tid >> 6;
-    uint32_t v[IPT], dg[IPT], rk[IPT];
+    uint32_t v[IPT], rd[IPT];  // digit, then rank | digit << 16
     uint64_t vor = 0, vand = ~0ull;
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
@@ -46,17 +46,17 @@ __device__ __forceinline__ void lds_sort_regs(typename KT<DT>::U (&k)[IPT], type
 #pragma unroll
             for (int j = 0; j < IPT; ++j) {
                 const uint32_t e = striped_elem<IPT>(w, j, lane);
-                dg[j] = e < len ? (uint32_t)(KT<DT>::image(k[j]) >> shift) & (RADIX - 1) : 0u;
+                rd[j] = e < len ? (uint32_t)(KT<DT>::image(k[j]) >> shift) & (RADIX - 1) : 0u;
             }
-            rank_match<RADIX_BITS, W, IPT>(dg, len, rk, sm.cnt, sm.tot, tid);
+            rank_match_packed<RADIX_BITS, W, IPT>(rd, len, sm.cnt, sm.tot, tid);
             block_exscan<B, RADIX>(sm.tot, sm.start, sm.wsum, tid);
-            rank_finish<RADIX_BITS, W, IPT>(dg, rk, sm.cnt, sm.start, tid);
+            rank_finish_packed<RADIX_BITS, W, IPT>(rd, sm.cnt, sm.start, tid);
 #pragma unroll
             for (int j = 0; j < IPT; ++j) {
                 const uint32_t e = striped_elem<IPT>(w, j, lane);
                 if (e < len) {
-                    sm.keys[rk[j]] = k[j];
-                    if (VAL) sm.vals[rk[j]] = v[j];
+                    sm.keys[rd[j] & 0xFFFFu] = k[j];
+                    if (VAL) sm.vals[rd[j] & 0xFFFFu] = v[j];
                 }
             }
             grp_sync<W>();

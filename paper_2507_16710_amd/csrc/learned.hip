@@ -434,6 +434,11 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(WPE))) v
     const uint32_t end = sm.bound[1];
     uint32_t nchunks = 0;
     while (pos < end) {
+        // per-thread indices re-derived per chunk from an opaque copy of the
+        // thread id (hoisted out of the loop they would hold registers)
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const int lane = tid & 63, w = tid >> 6;
         const uint32_t len = std::min<uint32_t>(CAP, end - pos);
         // one read of the chunk: registers (striped) for the sort and the cut
         U k[IPT];
@@ -736,7 +741,7 @@ static ak_status leaf_grad_t(Workspace *ws, const void *sorted, uint32_t m, cons
 struct ChunkShape {
     int w, ipt, wpe;
 };
-constexpr ChunkShape CHUNK_SHAPES[3] = {{16, 4, 8}, {8, 4, 8}, {4, 8, 5}};
+constexpr ChunkShape CHUNK_SHAPES[3] = {{16, 4, 8}, {8, 4, 8}, {4, 8, 6}};
 constexpr int LEARNED_CAP_MIN = 2048;
 
 static int chunk_variant() {

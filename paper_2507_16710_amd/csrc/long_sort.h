@@ -74,7 +74,7 @@ __device__ void sort_long(typename KT<DT>::U *keys, typename KT<DT>::U *tmp, uin
         for (uint32_t tb = 0; tb < len; tb += TILE) {
             const uint32_t tvalid = min((uint32_t)TILE, len - tb);
             U k[IPT];
-            uint32_t dg[IPT], rk[IPT];
+            uint32_t rd[IPT];  // digit, then rank | digit << 16
 #pragma unroll
             for (int jj = 0; jj < IPT; ++jj) k[jj] = kn[jj];
             const uint32_t nb = tb + TILE;
@@ -88,17 +88,17 @@ __device__ void sort_long(typename KT<DT>::U *keys, typename KT<DT>::U *tmp, uin
 #pragma unroll
             for (int jj = 0; jj < IPT; ++jj) {
                 const uint32_t e = striped_elem<IPT>(w, jj, lane);
-                dg[jj] = e < tvalid ? (uint32_t)(KT<DT>::image(k[jj]) >> (8 * p)) & (RADIX - 1) : 0u;
+                rd[jj] = e < tvalid ? (uint32_t)(KT<DT>::image(k[jj]) >> (8 * p)) & (RADIX - 1) : 0u;
             }
-            rank_match<RADIX_BITS, W, IPT>(dg, tvalid, rk, sm.cnt, sm.tot, tid);
+            rank_match_packed<RADIX_BITS, W, IPT>(rd, tvalid, sm.cnt, sm.tot, tid);
             block_exscan<B, RADIX>(sm.tot, sm.start, sm.wsum, tid);
-            rank_finish<RADIX_BITS, W, IPT>(dg, rk, sm.cnt, sm.start, tid);
+            rank_finish_packed<RADIX_BITS, W, IPT>(rd, sm.cnt, sm.start, tid);
 #pragma unroll
             for (int jj = 0; jj < IPT; ++jj) {
                 const uint32_t e = striped_elem<IPT>(w, jj, lane);
                 if (e < tvalid) {
-                    sm.keys[rk[jj]] = k[jj];
-                    sm.dig[rk[jj]] = (uint8_t)dg[jj];
+                    sm.keys[rd[jj] & 0xFFFFu] = k[jj];
+                    sm.dig[rd[jj] & 0xFFFFu] = (uint8_t)(rd[jj] >> 16);
                 }
             }
             __syncthreads();

@@ -62,82 +62,11 @@ __device__ __forceinline__ uint32_t striped_elem(int w, int j, int lane) {
 // Phase 1 of the stable ranking.  For every valid item, finds the lanes of
 // its wave holding the same digit (RB ballots), and gives the item its rank
 // among equal digits of earlier items of the wave.  Per-wave digit counters
-// live in s_cnt[w*R + d].  Afterwards (and a barrier), s_cnt holds, per
+// live in s_cnt[w*R + d]; afterwards (and a barrier) s_cnt holds, per
 // digit, the exclusive prefix over waves and s_tot the tile's digit totals.
-template <int RB, int W, int IPT, typename C = uint32_t>
-__device__ __forceinline__ void rank_match(const uint32_t (&dg)[IPT], uint32_t nvalid, uint32_t (&rk)[IPT],
-                                           C *s_cnt, uint32_t *s_tot, int tid) {
-    constexpr int R = 1 << RB;
-    constexpr int B = W * 64;
-    const int lane = tid & 63, w = tid >> 6;
-    for (int i = tid; i < W * R; i += B) s_cnt[i] = 0;
-    grp_sync<W>();
-    C *cnt = s_cnt + w * R;
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-        const bool valid = striped_elem<IPT>(w, j, lane) < nvalid;
-        const uint64_t vm = ballot64(valid);
-        uint32_t plo = (uint32_t)vm, phi = (uint32_t)(vm >> 32);
-#pragma unroll
-        for (int b = 0; b < RB; ++b) {
-            // t = all ones if this lane's bit b is set; lanes agreeing on the
-            // bit keep their peer bit: peers &= ~(ballot ^ t)
-            const uint32_t t = (uint32_t)__builtin_amdgcn_sbfe((int32_t)dg[j], b, 1);
-            const uint64_t m = ballot64(t != 0u);
-            plo &= ~((uint32_t)m ^ t);
-            phi &= ~((uint32_t)(m >> 32) ^ t);
-        }
-        const uint64_t peers = ((uint64_t)phi << 32) | plo;
-        const uint32_t below = count_below(peers);
-        const uint32_t c = cnt[dg[j]];
-        rk[j] = c + below;
-        if (valid && below == 0) cnt[dg[j]] = (C)(c + (uint32_t)__popcll(peers));
-    }
-    grp_sync<W>();
-    if constexpr (B >= R && W % (B / R) == 0) {
-        // TPD adjacent threads per digit, each scanning W/TPD waves' counters
-        // (independent loads), joined by a shuffle scan inside the group
-        constexpr int TPD = B / R, WPT = W / TPD;
-        const int d = tid / TPD, g = tid % TPD;
-        uint32_t c[WPT];
-#pragma unroll
-        for (int i = 0; i < WPT; ++i) c[i] = s_cnt[(g * WPT + i) * R + d];
-        uint32_t sum = 0;
-#pragma unroll
-        for (int i = 0; i < WPT; ++i) {
-            const uint32_t t = c[i];
-            c[i] = sum;
-            sum += t;
-        }
-        uint32_t incl = sum;
-#pragma unroll
-        for (int o = 1; o < TPD; o <<= 1) {
-            const uint32_t y = (uint32_t)__shfl_up((int)incl, o, TPD);
-            if (g >= o) incl += y;
-        }
-        const uint32_t base = incl - sum;
-#pragma unroll
-        for (int i = 0; i < WPT; ++i) s_cnt[(g * WPT + i) * R + d] = (C)(base + c[i]);
-        if (g == TPD - 1) s_tot[d] = incl;
-    } else {
-        for (int d = tid; d < R; d += B) {
-            uint32_t run = 0;
-#pragma unroll
-            for (int ww = 0; ww < W; ++ww) {
-                const uint32_t c = s_cnt[ww * R + d];
-                s_cnt[ww * R + d] = (C)run;
-                run += c;
-            }
-            s_tot[d] = run;
-        }
-    }
-    grp_sync<W>();
-}
-
-// The same ranking with each item's digit and rank in one register
-// (rd[j] = rank | digit << 16; ranks stay below 2^16): the tile kernels
-// that hold many items per lane save IPT registers this way.  On input
-// rd[j] holds the digit; afterwards the wave-local rank and the digit.
+// Each item's digit and rank share one register (rd[j] = rank | digit <<
+// 16; ranks stay below 2^16), which saves IPT registers per lane: on input
+// rd[j] holds the digit, afterwards the wave-local rank and the digit.
 template <int RB, int W, int IPT, typename C = uint32_t>
 __device__ __forceinline__ void rank_match_packed(uint32_t (&rd)[IPT], uint32_t nvalid, C *s_cnt, uint32_t *s_tot,
                                                   int tid) {
@@ -205,6 +134,8 @@ __device__ __forceinline__ void rank_match_packed(uint32_t (&rd)[IPT], uint32_t 
     grp_sync<W>();
 }
 
+// Phase 2: with s_start = exclusive scan of s_tot over digits, turns the
+// wave-local ranks into tile positions.
 template <int RB, int W, int IPT, typename C = uint32_t>
 __device__ __forceinline__ void rank_finish_packed(uint32_t (&rd)[IPT], const C *s_cnt, const uint32_t *s_start,
                                                    int tid) {
@@ -215,17 +146,6 @@ __device__ __forceinline__ void rank_finish_packed(uint32_t (&rd)[IPT], const C 
         const uint32_t dg = rd[j] >> 16;
         rd[j] += s_start[dg] + (uint32_t)s_cnt[w * R + dg];
     }
-}
-
-// Phase 2: with s_start = exclusive scan of s_tot over digits, turns the
-// wave-local ranks into tile positions.
-template <int RB, int W, int IPT, typename C = uint32_t>
-__device__ __forceinline__ void rank_finish(const uint32_t (&dg)[IPT], uint32_t (&rk)[IPT], const C *s_cnt,
-                                            const uint32_t *s_start, int tid) {
-    constexpr int R = 1 << RB;
-    const int w = tid >> 6;
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) rk[j] += s_start[dg[j]] + (uint32_t)s_cnt[w * R + dg[j]];
 }
 
 // Decoupled look-back of one digit by a group of K adjacent threads (kk =

@@ -512,19 +512,19 @@ __global__ __launch_bounds__(XL_W * 64) void k_xl_pass(const SegArgs *ap, SegSta
         const int shift = 8 * place;
 
         U k[IPT];
-        uint32_t dg[IPT], rk[IPT];
+        uint32_t rd[IPT];  // digit, then rank | digit << 16
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
             const uint32_t e = striped_elem<IPT>(w, j, lane);
             k[j] = e < tvalid ? src[tbase + e] : U(0);
-            dg[j] = e < tvalid ? (uint32_t)(KT<DT>::image(k[j]) >> shift) & (RADIX - 1) : 0u;
+            rd[j] = e < tvalid ? (uint32_t)(KT<DT>::image(k[j]) >> shift) & (RADIX - 1) : 0u;
         }
-        rank_match<RADIX_BITS, W, IPT, uint16_t>(dg, tvalid, rk, s_cnt, s_tot, tid);
+        rank_match_packed<RADIX_BITS, W, IPT, uint16_t>(rd, tvalid, s_cnt, s_tot, tid);
         uint64_t *lb = a.xl_lb + (size_t)tile * RADIX;
         for (int d = tid; d < RADIX; d += B)
             lb_store(lb + d, lb_pack(epoch, lt == 0 ? LB_INC : LB_AGG, s_tot[d]));
         block_exscan<B, RADIX>(s_tot, s_start, s_wsum, tid);
-        rank_finish<RADIX_BITS, W, IPT, uint16_t>(dg, rk, s_cnt, s_start, tid);
+        rank_finish_packed<RADIX_BITS, W, IPT, uint16_t>(rd, s_cnt, s_start, tid);
         {
             constexpr int K = B / RADIX;
             const int d = tid / K, kk = tid % K;
@@ -539,7 +539,7 @@ __global__ __launch_bounds__(XL_W * 64) void k_xl_pass(const SegArgs *ap, SegSta
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
             const uint32_t e = striped_elem<IPT>(w, j, lane);
-            if (e < tvalid) s_keys[rk[j]] = k[j];
+            if (e < tvalid) s_keys[rd[j] & 0xFFFFu] = k[j];
         }
         __syncthreads();
 #pragma unroll
