@@ -528,6 +528,22 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(
     for (int d = tid; d < RADIX; d += B) s_run[d] = a.ccnt[(size_t)d * a.nchunks + c];
     const uint32_t t0 = c * a.chunk_tiles;
     const uint32_t t1 = min((a.n + TILE - 1) / TILE, t0 + a.chunk_tiles);
+    // tile t's keys (and values) in registers, striped; the next tile's are
+    // loaded before tile t is ranked, so their latency overlaps the work
+    auto load_tile = [&](uint32_t t, int w_, int lane_, U(&kk)[IPT], uint32_t(&vv)[IPT]) {
+        const uint32_t tb = t * (uint32_t)TILE;
+        const uint32_t tv = min((uint32_t)TILE, a.n - tb);
+        const U *sp = src + tb + w_ * 64 * IPT + lane_;
+#pragma unroll
+        for (int jj = 0; jj < IPT; ++jj) {
+            const uint32_t e = striped_elem<IPT>(w_, jj, lane_);
+            kk[jj] = e < tv ? __builtin_nontemporal_load(sp + jj * 64) : U(0);
+            if (VAL) vv[jj] = e >= tv ? 0u : (vsrc ? __builtin_nontemporal_load(vsrc + tb + e) : tb + e);
+        }
+    };
+    U k[IPT];
+    uint32_t v[IPT];
+    if (t0 < t1) load_tile(t0, w, lane, k, v);
     for (uint32_t tile = t0; tile < t1; ++tile) {
         // per-thread indices re-derived each tile from an opaque copy of the
         // thread id (hoisted out of the loop they would be spilled)
@@ -536,15 +552,9 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(
         const int lane = tid & 63, w = tid >> 6;
         const uint32_t tbase = tile * (uint32_t)TILE;
         const uint32_t tvalid = min((uint32_t)TILE, a.n - tbase);
-        U k[IPT];
-        uint32_t v[IPT], rd[IPT];
-        const U *sp = src + tbase + w * 64 * IPT + lane;
-#pragma unroll
-        for (int jj = 0; jj < IPT; ++jj) {
-            const uint32_t e = striped_elem<IPT>(w, jj, lane);
-            k[jj] = e < tvalid ? __builtin_nontemporal_load(sp + jj * 64) : U(0);
-            if (VAL) v[jj] = e >= tvalid ? 0u : (vsrc ? __builtin_nontemporal_load(vsrc + tbase + e) : tbase + e);
-        }
+        U kn[IPT];
+        uint32_t vn[IPT], rd[IPT];
+        if (tile + 1 < t1) load_tile(tile + 1, w, lane, kn, vn);
 #pragma unroll
         for (int jj = 0; jj < IPT; ++jj) {
             const uint32_t e = striped_elem<IPT>(w, jj, lane);
@@ -583,6 +593,11 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(
             }
         }
         __syncthreads();  // the tile's LDS is reused by the next one
+#pragma unroll
+        for (int jj = 0; jj < IPT; ++jj) {
+            k[jj] = kn[jj];
+            if (VAL) v[jj] = vn[jj];
+        }
     }
 }
 
