@@ -81,15 +81,19 @@ __device__ __forceinline__ void rank_match_packed(uint32_t (&rd)[IPT], uint32_t 
         const uint32_t dg = rd[j];
         const bool valid = striped_elem<IPT>(w, j, lane) < nvalid;
         const uint64_t vm = ballot64(valid);
-        uint32_t plo = (uint32_t)vm, phi = (uint32_t)(vm >> 32);
+        // lanes that differ from this one in some bit: per bit b, with t
+        // all ones where this lane's bit is set, mis |= ballot ^ t (one
+        // three-input op per half: 0xF6 is S0 | (S1 ^ S2))
+        uint32_t mlo = 0u, mhi = 0u;
 #pragma unroll
         for (int b = 0; b < RB; ++b) {
-            const uint32_t t = (uint32_t)__builtin_amdgcn_sbfe((int32_t)dg, b, 1);
+            uint32_t t = (uint32_t)__builtin_amdgcn_sbfe((int32_t)dg, b, 1);
+            asm("" : "+v"(t));  // the ballot tests t itself, not a second shift of dg
             const uint64_t m = ballot64(t != 0u);
-            plo &= ~((uint32_t)m ^ t);
-            phi &= ~((uint32_t)(m >> 32) ^ t);
+            mlo = __builtin_amdgcn_bitop3_b32(mlo, (uint32_t)m, t, 0xF6);
+            mhi = __builtin_amdgcn_bitop3_b32(mhi, (uint32_t)(m >> 32), t, 0xF6);
         }
-        const uint64_t peers = ((uint64_t)phi << 32) | plo;
+        const uint64_t peers = ((uint64_t)((uint32_t)(vm >> 32) & ~mhi) << 32) | ((uint32_t)vm & ~mlo);
         const uint32_t below = count_below(peers);
         const uint32_t c = cnt[dg];
         rd[j] = (c + below) | (dg << 16);
