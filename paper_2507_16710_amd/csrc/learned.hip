@@ -829,11 +829,13 @@ static ak_status learned_t(Workspace *ws, void *keys, int64_t n64, const ak_lear
     // one or two leaf records in cache: the table is not staged here, which
     // keeps the workgroup's LDS small enough for several per CU.
     const size_t stage = rmi_stage_bytes(L);
-    ProfScope ps_chunk("chunk_sort", s);
-    switch (cvar) {
-    case 0: launch_chunk_sort<DT, 0>(s, npieces, (U *)keys, n, (const float *)model, cb, piece, fb, ls); break;
-    case 1: launch_chunk_sort<DT, 1>(s, npieces, (U *)keys, n, (const float *)model, cb, piece, fb, ls); break;
-    default: launch_chunk_sort<DT, 2>(s, npieces, (U *)keys, n, (const float *)model, cb, piece, fb, ls); break;
+    {
+        ProfScope ps_chunk("chunk_sort", s);
+        switch (cvar) {
+        case 0: launch_chunk_sort<DT, 0>(s, npieces, (U *)keys, n, (const float *)model, cb, piece, fb, ls); break;
+        case 1: launch_chunk_sort<DT, 1>(s, npieces, (U *)keys, n, (const float *)model, cb, piece, fb, ls); break;
+        default: launch_chunk_sort<DT, 2>(s, npieces, (U *)keys, n, (const float *)model, cb, piece, fb, ls); break;
+        }
     }
     AK_LAUNCH_CHECK("k_chunk_sort");
     // 5. fallback runs: radix-sorted as segments (runs of one repeated key

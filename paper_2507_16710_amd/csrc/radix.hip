@@ -730,7 +730,7 @@ static void launch_pass_v(hipStream_t s, uint32_t tiles, const OnesweepArgs &a, 
     // code digits: persistent grid (the staged table leaves room for one
     // workgroup per CU); key digits: one workgroup per tile, or a persistent
     // grid of two workgroups per CU
-    if (CODE) {
+    if constexpr (CODE) {
         const uint32_t grid = std::min<uint32_t>(tiles, (uint32_t)num_cus() * (stage ? 1 : 2));
         hipLaunchKernelGGL((k_onesweep<DT, VAL, sh.w, sh.ipt, true, true>), dim3(grid), dim3(sh.w * 64), stage, s, a);
     } else if (os_persist()) {
