@@ -633,9 +633,11 @@ __global__ __launch_bounds__(W * 64) void k_small_sort(const typename KT<DT>::U 
 // (measured on 2^28 float32 and 2^30 int64 keys: 16 waves x 16 keys and
 // 16 waves x 8 keys per lane)
 static const int OS_DEFAULT[2][2] = {{3, 0}, {3, 0}};
-// default shape of the code-digit passes per key width (16 waves x 6 keys
-// for 64-bit keys, measured on the 2^31 mixture)
-static const int OS_CODE_DEFAULT[2] = {0, 2};
+// default shape of the code-digit passes per key width.  64-bit keys: 16
+// waves x 10 keys, the largest tile whose staging buffer still fits the LDS
+// beside the 64 KB model table (2^31 mixture keys, per pass: 16 x 6 keys
+// 20.7 ms, 16 x 8 keys 18.0 ms, 16 x 10 keys 16.1 ms)
+static const int OS_CODE_DEFAULT[2] = {0, 3};
 
 static int env_variant(const char *name) {
     const char *e = getenv(name);

@@ -49,11 +49,12 @@ constexpr OsShape OS_SHAPES[2][2][OS_NVAR] = {
     {{{16, 4}, {16, 3}, {16, 6}, {16, 8}}, {{16, 4}, {8, 6}, {16, 3}, {16, 6}}},
 };
 // Shapes of the code-digit passes (keys only; one persistent workgroup per
-// CU next to the staged model table, so registers are not the limit).
+// CU next to the staged model table, so registers are not the limit and
+// the tile is as large as the LDS left beside the table allows).
 // os_code_variant() picks one ($AK_OS_CODE_VARIANT overrides it).
 constexpr OsShape OS_CODE_SHAPES[2][OS_NVAR] = {
-    {{16, 8}, {16, 6}, {16, 4}, {8, 12}},
-    {{16, 4}, {16, 3}, {16, 6}, {8, 8}},
+    {{16, 8}, {16, 6}, {16, 12}, {8, 12}},
+    {{16, 4}, {16, 8}, {16, 6}, {16, 10}},
 };
 int os_variant(int dt, bool val);
 int os_code_variant(int dt);
