@@ -629,10 +629,15 @@ __global__ __launch_bounds__(W * 64) void k_small_sort(const typename KT<DT>::U 
 }
 
 // ------------------------------------------------------------ driver
-// default shape per (64-bit keys, values), from the tuning sweep
-// (measured on 2^28 float32 and 2^30 int64 keys: 16 waves x 16 keys and
-// 16 waves x 8 keys per lane)
-static const int OS_DEFAULT[2][2] = {{3, 0}, {3, 0}};
+// default shape per (64-bit keys, values), from the tuning sweep (per
+// pass, same box): 32-bit keys 16 waves x 16 keys, one tile per workgroup
+// (2^28 float32: 1.14 ms; no persistent shape was faster); 32-bit keys with
+// indices 16 x 12 persistent (1.94 -> 1.60 ms); 64-bit keys 8 x 24
+// persistent (2^30 int64: 7.43 -> 6.07 ms); 64-bit keys with indices 16 x 8
+// persistent (2^28 int64: 3.21 -> 2.50 ms).  Large tiles amortise the
+// per-tile work (digit scan, look-back, barriers) over more keys and make
+// the digit runs of the scatter longer.
+static const int OS_DEFAULT[2][2] = {{3, 3}, {3, 2}};
 // default shape of the code-digit passes per key width.  64-bit keys: 16
 // waves x 10 keys, the largest tile whose staging buffer still fits the LDS
 // beside the 64 KB model table (2^31 mixture keys, per pass: 16 x 6 keys
@@ -685,16 +690,6 @@ size_t code_partition_bytes(int dt, int64_t n) {
     return 2 * al256((size_t)n * kb) + al256(lookback_words(tiles) * 8) + al256(rts_bytes(tiles));
 }
 
-// Key-digit passes on a persistent grid ($AK_OS_PERSIST=1) or one workgroup
-// per tile (default).
-static bool os_persist() {
-    static const bool p = [] {
-        const char *e = getenv("AK_OS_PERSIST");
-        return e && *e == '1';
-    }();
-    return p;
-}
-
 // Reduce-then-scan passes ($AK_OS_RTS=1) instead of one-sweep passes.
 static bool os_rts() {
     static const bool p = [] {
@@ -730,12 +725,13 @@ static void launch_pass_v(hipStream_t s, uint32_t tiles, const OnesweepArgs &a, 
     }
     constexpr OsShape sh = CODE ? OS_CODE_SHAPES[key_bits(DT) == 64][V] : OS_SHAPES[key_bits(DT) == 64][VAL][V];
     // code digits: persistent grid (the staged table leaves room for one
-    // workgroup per CU); key digits: one workgroup per tile, or a persistent
-    // grid of two workgroups per CU
+    // workgroup per CU); key digits: a persistent grid of at most two
+    // workgroups per CU (the shapes' LDS admits one or two), or one
+    // workgroup per tile
     if constexpr (CODE) {
         const uint32_t grid = std::min<uint32_t>(tiles, (uint32_t)num_cus() * (stage ? 1 : 2));
         hipLaunchKernelGGL((k_onesweep<DT, VAL, sh.w, sh.ipt, true, true>), dim3(grid), dim3(sh.w * 64), stage, s, a);
-    } else if (os_persist()) {
+    } else if constexpr (sh.pers) {
         const uint32_t grid = std::min<uint32_t>(tiles, (uint32_t)num_cus() * 2);
         hipLaunchKernelGGL((k_onesweep<DT, VAL, sh.w, sh.ipt, false, true>), dim3(grid), dim3(sh.w * 64), 0, s, a);
     } else {

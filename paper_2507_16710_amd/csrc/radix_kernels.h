@@ -38,23 +38,29 @@ constexpr int LB_GROUP = AK_LB_GROUP;
 // look-back words of a pass over `tiles` tiles (tile words, then group words)
 inline size_t lookback_words(size_t tiles) { return (tiles + (tiles + LB_GROUP - 1) / LB_GROUP) * 256; }
 
+// A pass shape: W waves x IPT keys per lane per tile, and whether the pass
+// runs on a persistent grid (a workgroup walks tiles and loads its next
+// tile before it waits in the look-back) or one workgroup per tile.
 struct OsShape {
     int w, ipt;
+    bool pers;
 };
 constexpr int OS_NVAR = 4;
 constexpr OsShape OS_SHAPES[2][2][OS_NVAR] = {
     // 32-bit keys: keys only, with values
-    {{{16, 8}, {16, 6}, {16, 12}, {16, 16}}, {{8, 12}, {16, 8}, {16, 6}, {16, 4}}},
+    {{{16, 8, false}, {16, 6, false}, {16, 12, false}, {16, 16, false}},
+     {{8, 12, false}, {16, 8, false}, {16, 6, false}, {16, 12, true}}},
     // 64-bit keys: keys only, with values
-    {{{16, 4}, {16, 3}, {16, 6}, {16, 8}}, {{16, 4}, {8, 6}, {16, 3}, {16, 6}}},
+    {{{16, 4, false}, {16, 8, false}, {16, 12, true}, {8, 24, true}},
+     {{16, 4, false}, {8, 6, false}, {16, 8, true}, {8, 16, true}}},
 };
 // Shapes of the code-digit passes (keys only; one persistent workgroup per
 // CU next to the staged model table, so registers are not the limit and
 // the tile is as large as the LDS left beside the table allows).
 // os_code_variant() picks one ($AK_OS_CODE_VARIANT overrides it).
 constexpr OsShape OS_CODE_SHAPES[2][OS_NVAR] = {
-    {{16, 8}, {16, 6}, {16, 12}, {8, 12}},
-    {{16, 4}, {16, 8}, {16, 6}, {16, 10}},
+    {{16, 8, true}, {16, 6, true}, {16, 12, true}, {8, 12, true}},
+    {{16, 4, true}, {16, 8, true}, {16, 6, true}, {16, 10, true}},
 };
 int os_variant(int dt, bool val);
 int os_code_variant(int dt);
