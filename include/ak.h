@@ -244,6 +244,22 @@ ak_status ak_set_workspace(void *dev_ptr, size_t bytes, ak_stream_t stream);
 /* Synchronises the device and frees every workspace and cached graph. */
 ak_status ak_release_workspace(void);
 
+/* ----------------------------------------------------------- diagnostics
+ * How the last call on `stream` ordered its keys, if that call was ak_sort
+ * or ak_sortperm on more keys than one workgroup sorts on chip (all zeros
+ * otherwise).  Waits for the stream.  info is a HOST array of 5:
+ *   info[0] prefix places k: 0 if every active digit place took a pass;
+ *           2..4 if the passes covered only the top k places (a key-only
+ *           sort of more than 2^22 keys whose top places spread the keys)
+ *           and each run of equal prefix was then sorted on chip;
+ *   info[1] digit passes run;
+ *   info[2] on-chip chunk sorts of the prefix finish;
+ *   info[3] runs of equal prefix longer than a chunk, sorted by the
+ *           segmented sort instead;
+ *   info[4] keys in those runs.
+ * Errors: info NULL -> AK_ERR_INVALID_ARG. */
+ak_status ak_sort_route(int64_t *info, ak_stream_t stream);
+
 /* ------------------------------------------------------------ profiling
  * While enabled, every library kernel launch is bracketed by HIP events
  * recorded on the stream it is launched on (a few microseconds per launch).

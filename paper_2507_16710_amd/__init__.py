@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ak_rmi_codes": [vp, i64, i32, vp, i32, vp, vp],
         "ak_release_workspace": [],
         "ak_set_workspace": [vp, ctypes.c_size_t, vp],
+        "ak_sort_route": [vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -271,6 +272,15 @@ def profile_read() -> dict:
         name, cnt, ms = line.split()
         out[name] = (int(cnt), float(ms))
     return out
+
+
+def sort_route() -> dict:
+    """How the last sort_ / sortperm call on the current stream ordered its
+    keys: {"prefix_places", "passes", "chunks", "fallback_runs",
+    "fallback_keys"} (waits for the stream)."""
+    info = (ctypes.c_int64 * 5)()
+    _check(load_library().ak_sort_route(info, torch.cuda.current_stream().cuda_stream), "ak_sort_route")
+    return dict(zip(("prefix_places", "passes", "chunks", "fallback_runs", "fallback_keys"), list(info)))
 
 
 def seg_set_tuning(key_bits: int, ipt_a: int, ipt_b: int, grid_mult: int = 4, b_max: int = 0,

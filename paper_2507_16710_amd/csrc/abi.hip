@@ -183,6 +183,7 @@ static void drop_buffers(Workspace *ws) {
 // reusing the bytes is safe in stream order).  Pointers are kept so that a
 // buffer carved at the same place again keeps its cached graphs.
 void ws_begin_call(Workspace *ws) {
+    ws->last_route = 0;
     if (!ws->arena) return;
     ws->arena_used = 0;
     ws->keys0_bytes = ws->keys1_bytes = ws->vals0_bytes = ws->lookback_bytes = 0;
@@ -259,6 +260,25 @@ const char *ak_status_string(ak_status s) {
 }
 
 const char *ak_last_error(void) { return g_last_error.c_str(); }
+
+ak_status ak_sort_route(int64_t *info, ak_stream_t stream) {
+    g_last_error.clear();
+    if (!info) {
+        set_error("info is NULL");
+        return AK_ERR_INVALID_ARG;
+    }
+    for (int i = 0; i < 5; ++i) info[i] = 0;
+    Workspace *ws = get_workspace((hipStream_t)stream);
+    if (!ws) return AK_ERR_HIP;
+    AK_HIP(hipStreamSynchronize(ws->stream));
+    if (ws->last_route == 0) return AK_OK;
+    RunState st;
+    AK_HIP(hipMemcpy(&st, ws->state, sizeof(RunState), hipMemcpyDeviceToHost));
+    info[0] = st.pfx_active ? (int64_t)st.pfx_places : 0;
+    info[1] = st.q;
+    if (ws->last_route == 2 && st.pfx_active) return prefix_counts(ws, info + 2);
+    return AK_OK;
+}
 
 ak_status ak_sort(void *keys, int64_t n, ak_dtype dtype, ak_stream_t stream) {
     g_last_error.clear();

@@ -116,6 +116,13 @@ struct RunState {
     uint32_t error;                    // device-detected input error flag
     uint32_t epoch_base;               // look-back epoch of this run's first pass
     uint32_t hist_done;                // histogram workgroups finished
+    // prefix-partitioned sort (decided with the digit offsets): the passes
+    // order the keys by the `pfx_places` top active places only, and the
+    // chunk sort finishes every run of equal prefix on chip
+    uint32_t pfx_active;
+    int32_t pfx_shift;                 // bit offset of the prefix field
+    uint32_t pfx_mask;                 // prefix field mask (after the shift)
+    uint32_t pfx_places;               // digit places in the prefix field
 };
 
 // ------------------------------------------------------------- errors
@@ -165,6 +172,9 @@ struct Workspace {
     uint32_t epoch = 0;             // last epoch base handed out
     char *arena = nullptr;          // caller-owned scratch (ak_set_workspace), else null
     size_t arena_bytes = 0, arena_used = 0;
+    // route of this call's radix run on state slot 0: 0 none or on chip,
+    // 1 digit passes only, 2 passes with the prefix-partitioned finish
+    int last_route = 0;
 };
 
 Workspace *get_workspace(hipStream_t stream);
@@ -189,6 +199,22 @@ int num_cus();
 // `stream`, using run state slot `slot` of the workspace.
 ak_status radix_sort(Workspace *ws, int dtype, void *keys, uint32_t *perm, int64_t n, int slot);
 size_t radix_temp_bytes(int dtype, int64_t n, bool perm);
+
+// Prefix-partitioned finish of a key-only radix run (learned.hip): scratch
+// it needs beyond the radix passes, its reservation (before the run's
+// launches), and its launches after the passes: the on-chip chunk sorts of
+// the runs of equal prefix, then the segmented radix sort of the runs that
+// exceed a chunk.  Every launch exits at once when the run took plain
+// passes.
+size_t prefix_finish_bytes(int dtype, int64_t n);
+ak_status prefix_reserve(Workspace *ws, int dtype, int64_t n);
+ak_status prefix_finish(Workspace *ws, int dtype, void *keys, int64_t n, const RunState *st);
+// Chunk capacity of the prefix finish; a run of equal prefix up to this
+// length is sorted on chip.
+int prefix_chunk_keys();
+// Chunk sorts, fallback runs and fallback keys of the last prefix finish
+// (waits for the stream).
+ak_status prefix_counts(Workspace *ws, int64_t out[3]);
 
 // Single-workgroup on-chip sort capacity (keys) for a dtype.
 int64_t small_sort_capacity(int dtype);

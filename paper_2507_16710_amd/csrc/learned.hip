@@ -351,25 +351,42 @@ struct FbRun {
     uint32_t start, len;
 };
 
+// What a chunk sort orders by: the model code of a key (learned sort) or a
+// bit field of its order-preserving image (prefix-partitioned radix sort).
+// Both are nondecreasing in the key, so the code-ordered array is ordered
+// by code and its equal-code runs are contiguous.
 template <int DT>
-__device__ __forceinline__ uint32_t code_at(const typename KT<DT>::U *keys, uint32_t i, const RmiHead &h,
-                                            const RmiLeaf *lv, int cb, float scale) {
-    return rmi_code(h, lv, KT<DT>::image(keys[i]), cb, scale);
-}
+struct RmiCoder {
+    RmiHead h;
+    const RmiLeaf *lv;
+    int cb;
+    float scale;
+    __device__ uint32_t operator()(typename KT<DT>::U key) const {
+        return rmi_code(h, lv, KT<DT>::image(key), cb, scale);
+    }
+};
+template <int DT>
+struct PrefixCoder {
+    int shift;
+    uint32_t mask;
+    __device__ uint32_t operator()(typename KT<DT>::U key) const {
+        return (uint32_t)((uint64_t)KT<DT>::image(key) >> shift) & mask;
+    }
+};
 
 // Smallest i >= q with code(i) != c (or n); codes are nondecreasing in the
 // position.  Gallops, then bisects (single thread).
-template <int DT>
+template <int DT, typename CD>
 __device__ uint32_t next_code_change(const typename KT<DT>::U *keys, uint32_t n, uint32_t q, uint32_t c,
-                                     const RmiHead &h, const RmiLeaf *lv, int cb, float scale) {
-    if (q >= n || code_at<DT>(keys, q, h, lv, cb, scale) != c) return q;
+                                     const CD &cd) {
+    if (q >= n || cd(keys[q]) != c) return q;
     uint32_t good = q;  // code(good) == c
     uint64_t step = 1;
     uint32_t bad = n;   // first known position with a different code (or n)
     while (true) {
         const uint64_t probe = (uint64_t)good + step;
         if (probe >= n) break;
-        if (code_at<DT>(keys, (uint32_t)probe, h, lv, cb, scale) != c) {
+        if (cd(keys[probe]) != c) {
             bad = (uint32_t)probe;
             break;
         }
@@ -378,7 +395,7 @@ __device__ uint32_t next_code_change(const typename KT<DT>::U *keys, uint32_t n,
     }
     while (bad - good > 1) {
         const uint32_t mid = good + (bad - good) / 2;
-        if (code_at<DT>(keys, mid, h, lv, cb, scale) != c) bad = mid;
+        if (cd(keys[mid]) != c) bad = mid;
         else good = mid;
     }
     return bad;
@@ -386,12 +403,10 @@ __device__ uint32_t next_code_change(const typename KT<DT>::U *keys, uint32_t n,
 
 // A piece boundary: p itself if p is 0, n, or the first key of a code run;
 // otherwise the start of the next code run.
-template <int DT>
-__device__ uint32_t piece_boundary(const typename KT<DT>::U *keys, uint32_t n, uint32_t p, const RmiHead &h,
-                                   const RmiLeaf *lv, int cb, float scale) {
+template <int DT, typename CD>
+__device__ uint32_t piece_boundary(const typename KT<DT>::U *keys, uint32_t n, uint32_t p, const CD &cd) {
     if (p == 0 || p >= n) return p >= n ? n : 0;
-    const uint32_t c = code_at<DT>(keys, p - 1, h, lv, cb, scale);
-    return next_code_change<DT>(keys, n, p, c, h, lv, cb, scale);
+    return next_code_change<DT>(keys, n, p, cd(keys[p - 1]), cd);
 }
 
 template <typename U, int W, int IPT>
@@ -406,28 +421,38 @@ struct ChunkSmem {
 
 // One workgroup per piece of the code-ordered array: cuts it at code
 // changes into chunks of at most W*64*IPT keys and sorts each on chip.
-// The model's leaf table can be staged in LDS (dynamic shared memory).
+// PREFIX: the code is the key-prefix field the run state describes, and the
+// kernel exits at once if the run took plain passes instead; otherwise the
+// model code (the leaf table can be staged in LDS, dynamic shared memory).
 // Register budget: WPE waves per SIMD (8: 64 VGPRs, so two 16-wave or four
 // 8-wave workgroups per CU), so one workgroup's barriers overlap the
 // others' loads.
-template <int DT, int W, int IPT, int WPE>
+template <int DT, int W, int IPT, int WPE, bool PREFIX>
 __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void k_chunk_sort(typename KT<DT>::U *keys, uint32_t n, const float *model,
                                                        int cb, uint32_t piece, FbRun *fb, LearnedState *ls,
-                                                       int staged) {
+                                                       int staged, const RunState *st) {
     using U = typename KT<DT>::U;
+    using CD = typename std::conditional<PREFIX, PrefixCoder<DT>, RmiCoder<DT>>::type;
     constexpr int B = W * 64, CAP = B * IPT;
     __shared__ ChunkSmem<U, W, IPT> sm;
     extern __shared__ float4 s_leaves[];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const RmiHead h = rmi_head(model);
-    const RmiLeaf *glv = rmi_leaves(model);
-    const RmiLeaf *lv = rmi_stage(model, staged ? s_leaves : nullptr);
-    const float scale = (float)(1u << cb);
+    CD cd;
+    if constexpr (PREFIX) {
+        if (!st->pfx_active) return;
+        cd.shift = st->pfx_shift;
+        cd.mask = st->pfx_mask;
+    } else {
+        cd.h = rmi_head(model);
+        cd.lv = rmi_stage(model, staged ? s_leaves : nullptr);
+        cd.cb = cb;
+        cd.scale = (float)(1u << cb);
+    }
     const uint64_t p0 = (uint64_t)blockIdx.x * piece;
     const uint64_t p1 = std::min<uint64_t>(p0 + piece, n);
     if (tid == 0) {
-        sm.bound[0] = piece_boundary<DT>(keys, n, (uint32_t)p0, h, glv, cb, scale);
-        sm.bound[1] = piece_boundary<DT>(keys, n, (uint32_t)p1, h, glv, cb, scale);
+        sm.bound[0] = piece_boundary<DT>(keys, n, (uint32_t)p0, cd);
+        sm.bound[1] = piece_boundary<DT>(keys, n, (uint32_t)p1, cd);
     }
     __syncthreads();
     uint32_t pos = sm.bound[0];
@@ -457,13 +482,13 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(WPE))) v
 #pragma unroll
             for (int j = 0; j < IPT; ++j) {
                 const uint32_t e = striped_elem<IPT>(w, j, lane);
-                c[j] = e < len ? rmi_code(h, lv, KT<DT>::image(k[j]), cb, scale) : 0xFFFFFFFFu;
+                c[j] = e < len ? cd(k[j]) : 0xFFFFFFFFu;
             }
             if (lane == 63) sm.wlast[w] = c[IPT - 1];
             if (tid == 0) {
                 sm.cut = 0;
                 sm.code0 = c[0];
-                sm.code_next = rmi_code(h, lv, KT<DT>::image(knext), cb, scale);
+                sm.code_next = cd(knext);
             }
             __syncthreads();
             uint32_t best = 0;
@@ -490,7 +515,7 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(WPE))) v
             if (q == 0) {
                 // one code spans past the chunk: hand the whole run to the fallback
                 if (tid == 0) {
-                    const uint32_t run_end = next_code_change<DT>(keys, end, pos + len, sm.code0, h, glv, cb, scale);
+                    const uint32_t run_end = next_code_change<DT>(keys, end, pos + len, sm.code0, cd);
                     const uint32_t slot = atomicAdd(&ls->fb_count, 1u);
                     fb[slot] = FbRun{pos, run_end - pos};
                     sm.cut = run_end;
@@ -757,8 +782,89 @@ template <int DT, int V>
 static void launch_chunk_sort(hipStream_t s, uint32_t npieces, typename KT<DT>::U *keys, uint32_t n,
                               const float *model, int cb, uint32_t piece, FbRun *fb, LearnedState *ls) {
     constexpr ChunkShape c = CHUNK_SHAPES[V];
-    hipLaunchKernelGGL((k_chunk_sort<DT, c.w, c.ipt, c.wpe>), dim3(npieces), dim3(c.w * 64), 0, s, keys, n, model,
-                       cb, piece, fb, ls, 0);
+    hipLaunchKernelGGL((k_chunk_sort<DT, c.w, c.ipt, c.wpe, false>), dim3(npieces), dim3(c.w * 64), 0, s, keys, n,
+                       model, cb, piece, fb, ls, 0, (const RunState *)nullptr);
+}
+
+// dtype dispatch of a templated driver
+#define AK_DT_SWITCH(dt, FN, ...)                          \
+    switch (dt) {                                          \
+    case AK_I32: return FN<AK_I32>(__VA_ARGS__);           \
+    case AK_I64: return FN<AK_I64>(__VA_ARGS__);           \
+    case AK_U32: return FN<AK_U32>(__VA_ARGS__);           \
+    case AK_U64: return FN<AK_U64>(__VA_ARGS__);           \
+    case AK_F32: return FN<AK_F32>(__VA_ARGS__);           \
+    case AK_F64: return FN<AK_F64>(__VA_ARGS__);           \
+    }                                                      \
+    return AK_ERR_UNSUPPORTED_DTYPE;
+
+// ------------------------------------------- prefix-partitioned finish
+// The plain radix sort of a key-only run whose top places spread the keys
+// stops after the passes over those places; these launches finish it (they
+// exit at once when the run took all its passes).
+constexpr int PFX_CVAR = 2;  // chunk shape: 4 waves x 8 keys per lane
+
+int prefix_chunk_keys() { return CHUNK_SHAPES[PFX_CVAR].w * 64 * CHUNK_SHAPES[PFX_CVAR].ipt; }
+
+// a fallback run is longer than a chunk
+static uint32_t prefix_fb_cap(int64_t n) { return (uint32_t)(n / prefix_chunk_keys() + 2); }
+
+// aux[5]: state | fallback runs | range bounds (lo, hi)
+static size_t prefix_aux_bytes(uint32_t cap) {
+    return 256 + (((size_t)cap * sizeof(FbRun) + 255) & ~size_t(255)) + (size_t)cap * 16;
+}
+
+size_t prefix_finish_bytes(int dt, int64_t n) {
+    const uint32_t cap = prefix_fb_cap(n);
+    return ((prefix_aux_bytes(cap) + 255) & ~size_t(255)) + segmented_scratch_bytes(dt, n, cap, false);
+}
+
+ak_status prefix_reserve(Workspace *ws, int, int64_t n) {
+    return ws_reserve(ws, &ws->aux[5], &ws->aux_bytes[5], prefix_aux_bytes(prefix_fb_cap(n)));
+}
+
+template <int DT>
+static ak_status prefix_finish_t(Workspace *ws, void *keys, int64_t n64, const RunState *st) {
+    using U = typename KT<DT>::U;
+    hipStream_t s = ws->stream;
+    const uint32_t n = (uint32_t)n64;
+    const uint32_t cap = prefix_fb_cap(n64);
+    char *base = (char *)ws->aux[5];
+    LearnedState *ls = (LearnedState *)base;
+    FbRun *fb = (FbRun *)(base + 256);
+    int64_t *lo = (int64_t *)(base + 256 + (((size_t)cap * sizeof(FbRun) + 255) & ~size_t(255)));
+    int64_t *hi = lo + cap;
+    hipLaunchKernelGGL(k_learned_reset, dim3(1), dim3(256), 0, s, ls, (uint32_t *)nullptr, 0u);
+    AK_LAUNCH_CHECK("k_learned_reset");
+    constexpr ChunkShape c = CHUNK_SHAPES[PFX_CVAR];
+    constexpr uint32_t CAP = c.w * 64 * c.ipt;
+    const uint32_t pieces_target = (uint32_t)num_cus() * 16;
+    const uint32_t piece = std::max<uint32_t>(CAP * 4, (n + pieces_target - 1) / pieces_target);
+    const uint32_t npieces = (n + piece - 1) / piece;
+    {
+        ProfScope ps("prefix_chunk_sort", s);
+        hipLaunchKernelGGL((k_chunk_sort<DT, c.w, c.ipt, c.wpe, true>), dim3(npieces), dim3(c.w * 64), 0, s, (U *)keys,
+                           n, (const float *)nullptr, 0, piece, fb, ls, 0, st);
+    }
+    AK_LAUNCH_CHECK("k_chunk_sort");
+    const uint32_t fgrid = std::min<uint32_t>((cap + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fb_ranges, dim3(fgrid), dim3(256), 0, s, (const FbRun *)fb, ls, lo, hi, cap);
+    AK_LAUNCH_CHECK("k_fb_ranges");
+    ProfScope ps("prefix_fallback", s);
+    return segmented_sort_ranges(ws, DT, keys, lo, hi, cap, n64, ws->keys0);
+}
+
+ak_status prefix_counts(Workspace *ws, int64_t out[3]) {
+    LearnedState ls{};
+    AK_HIP(hipMemcpy(&ls, ws->aux[5], sizeof(ls), hipMemcpyDeviceToHost));
+    out[0] = ls.chunks;
+    out[1] = ls.fb_count;
+    out[2] = (int64_t)ls.fb_keys;
+    return AK_OK;
+}
+
+ak_status prefix_finish(Workspace *ws, int dt, void *keys, int64_t n, const RunState *st) {
+    AK_DT_SWITCH(dt, prefix_finish_t, ws, keys, n, st)
 }
 
 // aux[0] of one learned call: sample keys | model | learned state |
@@ -885,16 +991,6 @@ static ak_status learned_t(Workspace *ws, void *keys, int64_t n64, const ak_lear
     return AK_OK;
 }
 
-#define AK_DT_SWITCH(dt, FN, ...)                          \
-    switch (dt) {                                          \
-    case AK_I32: return FN<AK_I32>(__VA_ARGS__);           \
-    case AK_I64: return FN<AK_I64>(__VA_ARGS__);           \
-    case AK_U32: return FN<AK_U32>(__VA_ARGS__);           \
-    case AK_U64: return FN<AK_U64>(__VA_ARGS__);           \
-    case AK_F32: return FN<AK_F32>(__VA_ARGS__);           \
-    case AK_F64: return FN<AK_F64>(__VA_ARGS__);           \
-    }                                                      \
-    return AK_ERR_UNSUPPORTED_DTYPE;
 
 ak_status learned_sort(Workspace *ws, int dt, void *keys, int64_t n, const ak_learned_cfg *cfg,
                        ak_learned_stats *stats) {

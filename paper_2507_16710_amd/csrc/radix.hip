@@ -45,9 +45,19 @@ __global__ void k_run_init(RunState *st, uint32_t *epoch_dev) {
 // without a host round trip.  Run by one workgroup of B >= 256 threads,
 // reading counts that other workgroups accumulated with device-scope
 // atomics.
+//
+// pfx_cap > 0 (key-only runs that can finish on chip): if the top k = 2..4
+// places spread the keys so that the expected largest run of equal prefix,
+// n * prod over those places of (largest digit count / n), is at most
+// pfx_cap keys, and the run then saves at least two passes, only the active
+// places among those k keep their passes and the run is marked prefix-
+// partitioned: the keys leave the passes ordered by their top k places,
+// and the chunk sort finishes each run of equal prefix.  The estimate
+// assumes independent places; a wrong guess costs time (longer runs go to
+// the segmented fallback), never order.
 template <int B>
 __device__ void scan_places(RunState *st, uint32_t n, int nplaces, uint32_t *s_buf, uint32_t *s_wsum,
-                            int *s_active) {
+                            int *s_active, uint32_t *s_pmax, uint32_t pfx_cap) {
     const int tid = threadIdx.x;
     // every place's count in flight at once (one round trip, not one per place)
     uint32_t cnt[MAX_PLACES];
@@ -56,12 +66,17 @@ __device__ void scan_places(RunState *st, uint32_t n, int nplaces, uint32_t *s_b
         cnt[p] = (p < nplaces && tid < RADIX)
                      ? __hip_atomic_load(&st->hist[p][tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                      : 0u;
+    if (tid < MAX_PLACES) s_pmax[tid] = 0;
+    __syncthreads();
 #pragma unroll
     for (int p = 0; p < MAX_PLACES; ++p) {
         if (p >= nplaces) break;
         const uint32_t c = cnt[p];
         const int trivial = __syncthreads_or(tid < RADIX && c == n);
-        if (tid < RADIX) s_buf[tid] = c;
+        if (tid < RADIX) {
+            s_buf[tid] = c;
+            if (c) atomicMax(&s_pmax[p], c);
+        }
         __syncthreads();
         block_exscan<B, RADIX>(s_buf, s_buf, s_wsum, tid);
         if (tid < RADIX) st->base[p][tid] = s_buf[tid];
@@ -69,18 +84,43 @@ __device__ void scan_places(RunState *st, uint32_t n, int nplaces, uint32_t *s_b
         __syncthreads();
     }
     if (tid == 0) {
-        int q = 0;
-        for (int p = 0; p < nplaces; ++p) q += s_active[p];
+        int q = 0, top = -1;
+        for (int p = 0; p < nplaces; ++p) {
+            q += s_active[p];
+            if (s_active[p]) top = p;
+        }
+        int lo = 0, qk = q;  // lowest place that keeps its pass; passes kept
+        uint32_t kp = 0;
+        if (pfx_cap > 0 && top >= 1) {
+            for (int k = 2; k <= 4 && k <= top + 1; ++k) {
+                double e = (double)n;
+                for (int i = 0; i < k; ++i) e *= (double)s_pmax[top - i] / (double)n;
+                if (e <= (double)pfx_cap) {
+                    int qa = 0;
+                    for (int p = top - k + 1; p <= top; ++p) qa += s_active[p];
+                    if (qa + 2 <= q) {
+                        kp = (uint32_t)k;
+                        lo = top - k + 1;
+                        qk = qa;
+                    }
+                    break;
+                }
+            }
+        }
         int j = 0;
         for (int p = 0; p < MAX_PLACES; ++p) {
             PassDesc d;
-            d.active = p < nplaces ? s_active[p] : 0;
+            d.active = (p < nplaces && p >= lo) ? s_active[p] : 0;
             d.j = d.active ? j++ : -1;
-            d.q = q;
+            d.q = qk;
             d.shift = p * RADIX_BITS;
             st->desc[p] = d;
         }
-        st->q = q;
+        st->q = qk;
+        st->pfx_active = kp != 0;
+        st->pfx_places = kp;
+        st->pfx_shift = lo * RADIX_BITS;
+        st->pfx_mask = kp >= 4 ? 0xFFFFFFFFu : ((1u << (kp * RADIX_BITS)) - 1u);
     }
 }
 
@@ -95,7 +135,7 @@ __device__ void scan_places(RunState *st, uint32_t n, int nplaces, uint32_t *s_b
 template <int DT, bool CODE>
 __global__ __launch_bounds__(CODE ? 1024 : 256) void k_hist(const typename KT<DT>::U *__restrict__ keys, uint32_t n,
                                                             int nplaces, RunState *st, const float *model, int cb,
-                                                            int staged) {
+                                                            int staged, uint32_t pfx_cap) {
     extern __shared__ float4 s_leaves[];
     using U = typename KT<DT>::U;
     constexpr int B = CODE ? 1024 : 256, ITEMS = 8;
@@ -144,13 +184,14 @@ __global__ __launch_bounds__(CODE ? 1024 : 256) void k_hist(const typename KT<DT
     __shared__ int s_last;
     __shared__ uint32_t s_wsum[B / 64];
     __shared__ int s_active[MAX_PLACES];
+    __shared__ uint32_t s_pmax[MAX_PLACES];
     __threadfence();
     __syncthreads();
     if (tid == 0) s_last = atomicAdd(&st->hist_done, 1u) == gridDim.x - 1;
     __syncthreads();
     if (!s_last) return;
     __threadfence();
-    scan_places<B>(st, n, nplaces, s_h, s_wsum, s_active);
+    scan_places<B>(st, n, nplaces, s_h, s_wsum, s_active, s_pmax, pfx_cap);
 }
 
 // ----------------------------------------------------- one-sweep pass
@@ -672,6 +713,10 @@ static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
 // (at most one chunk per tile).
 static size_t rts_bytes(size_t tiles) { return tiles * RADIX * 4; }
 
+// Key-only runs above this size may take the prefix-partitioned finish
+// (smaller ones replay a captured graph of plain passes).
+constexpr int64_t PREFIX_MIN = int64_t(1) << 22;
+
 size_t radix_temp_bytes(int dt, int64_t n, bool perm) {
     if (n <= small_sort_capacity(dt)) return 0;
     const size_t kb = (size_t)dtype_bytes(dt);
@@ -681,6 +726,7 @@ size_t radix_temp_bytes(int dt, int64_t n, bool perm) {
     // are never written), the look-back words, and the index buffer
     size_t b = 2 * al256((size_t)n * kb) + al256(lookback_words(tiles) * 8) + al256(rts_bytes(tiles));
     if (perm) b += al256((size_t)n * 4);
+    if (!perm && n > PREFIX_MIN) b += prefix_finish_bytes(dt, n);
     return b;
 }
 
@@ -778,7 +824,7 @@ static ak_status launch_passes(hipStream_t stream, Workspace *ws, RunState *st, 
 // ones exit at once), and the device-decided copy-back / identity.
 template <int DT, bool CODE>
 static ak_status launch_run(hipStream_t s, Workspace *ws, RunState *st, void *keys, uint32_t *perm, uint32_t n,
-                            int nplaces, const float *model, int cb, size_t stage = 0) {
+                            int nplaces, const float *model, int cb, size_t stage = 0, uint32_t pfx_cap = 0) {
     using U = typename KT<DT>::U;
     const bool pm = perm != nullptr;
     hipLaunchKernelGGL(k_run_init, dim3(1), dim3(256), 0, s, st, ws->epoch_dev);
@@ -789,7 +835,7 @@ static ak_status launch_run(hipStream_t s, Workspace *ws, RunState *st, void *ke
     {
         ProfScope ps(CODE ? "code_hist" : "digit_hist", s);
         hipLaunchKernelGGL((k_hist<DT, CODE>), dim3(hgrid), dim3(HB), stage, s, (const U *)keys, n, nplaces, st,
-                           model, cb, (int)(stage > 0));
+                           model, cb, (int)(stage > 0), pfx_cap);
     }
     AK_LAUNCH_CHECK("k_hist");
     ak_status r;
@@ -878,10 +924,22 @@ static ak_status radix_sort_t(Workspace *ws, void *keys, uint32_t *perm, int64_t
     const size_t tiles = (n + TILE - 1) / TILE;
     if ((r = ws_reserve_lookback(ws, lookback_words(tiles) * 8)) != AK_OK) return r;
     if ((r = ws_reserve(ws, &ws->aux[4], &ws->aux_bytes[4], rts_bytes(tiles))) != AK_OK) return r;
+    // key-only runs too large for a captured graph may finish on chip once
+    // their top places are placed (decided on the device from the digit
+    // counts; plain passes otherwise)
+    const bool pfx = !pm && n64 > PREFIX_MIN && !stream_capturing(s);
+    if (pfx && (r = prefix_reserve(ws, DT, n64)) != AK_OK) return r;
+    if (slot == 0) ws->last_route = pfx ? 2 : 1;
     uint32_t epoch;
     if ((r = ws_next_epoch(ws, &epoch)) != AK_OK) return r;
     RunState *st = ws->state + slot;
     const int nplaces = (int)(sizeof(U) * 8 / RADIX_BITS);
+    if (pfx) {
+        if ((r = launch_run<DT, false>(s, ws, st, keys, perm, n, nplaces, nullptr, 0, 0,
+                                       (uint32_t)(prefix_chunk_keys() / 4))) != AK_OK)
+            return r;
+        return prefix_finish(ws, DT, keys, n64, st);
+    }
     if (n64 > GRAPH_MAX || stream_capturing(s)) return launch_run<DT, false>(s, ws, st, keys, perm, n, nplaces, nullptr, 0);
 
     std::lock_guard<std::mutex> lk(g_graph_mu);

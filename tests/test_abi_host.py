@@ -81,3 +81,8 @@ def test_temp_bytes_predictable():
         assert lib.ak_temp_bytes_segmented(n, 10, dt) < lib.ak_temp_bytes_segmented(n, 2 * n, dt)
         assert lib.ak_temp_bytes_segmented(n, 0, dt) == 0
     assert lib.ak_rmi_model_floats(4096) == 8 + 4 * (4096 + 1)
+
+
+def test_sort_route_argument_error():
+    lib = _lib()
+    assert lib.ak_sort_route(None, None) == 1  # info NULL, checked before any device call

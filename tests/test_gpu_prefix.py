@@ -1,0 +1,114 @@
+"""GPU parity of the prefix-partitioned radix sort (bit-exact vs the oracle).
+
+A key-only sort of more than 2**22 keys whose top digit places spread the
+keys takes passes over those places only; each run of equal prefix is then
+sorted on chip, and runs longer than a chunk by the segmented sort.  The
+route is read back with ak_sort_route, so every case checks both the order
+and the route it expects.
+"""
+import zlib
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2507_16710_amd as ak
+from gpucheck import to_gpu, to_host
+from pools import bits, random_keys
+
+pytestmark = pytest.mark.gpu
+
+N0 = (1 << 22) + 777  # just above the size that replays a captured graph
+CHUNK = 2048          # keys one on-chip chunk sort holds
+
+
+def _sort_route(k: np.ndarray, dt: str):
+    t = to_gpu(k, dt)
+    ak.sort_(t, dtype=dt)
+    route = ak.sort_route()
+    return to_host(t, dt), route
+
+
+def _check(k, dt, tag):
+    print(f"prefix {tag} dt={dt} n={k.size}", flush=True)
+    got, route = _sort_route(k, dt)
+    assert np.array_equal(bits(got), bits(oracle.sort(k))), (tag, dt, k.size)
+    return route
+
+
+@pytest.mark.parametrize("dt", ["u64", "i64", "f64", "u32", "i32", "f32"])
+def test_uniform_keys_take_prefix_route(dt):
+    """Random bits in every place: two prefix places leave runs of about
+    n / 2**16 keys, so two passes and the chunk sorts finish the sort."""
+    rng = np.random.default_rng(zlib.crc32(f"pfx{dt}".encode()))
+    for n in (N0, (1 << 23) + 12345):
+        k = random_keys(dt, n, rng, "uniform")
+        route = _check(k, dt, "uniform")
+        assert route["prefix_places"] == 2 and route["passes"] == 2, route
+        assert route["chunks"] > 0, route
+
+
+def test_heavy_prefix_goes_to_fallback():
+    """0.1% of the keys share one 16-bit prefix: the per-place counts look
+    uniform (prefix chosen), but that run exceeds a chunk and is sorted by
+    the segmented sort."""
+    rng = np.random.default_rng(11)
+    n = (1 << 22) + 4321
+    k = rng.integers(0, 1 << 64, size=n, dtype=np.uint64)
+    heavy = rng.random(n) < 0.001
+    k[heavy] = (np.uint64(0xA5C3) << np.uint64(48)) | (k[heavy] & np.uint64((1 << 48) - 1))
+    route = _check(k, "u64", "heavy")
+    assert route["prefix_places"] == 2, route
+    assert route["fallback_runs"] >= 1 and route["fallback_keys"] > CHUNK, route
+
+
+def test_constant_place_inside_prefix():
+    """Byte 6 is constant: the prefix spans bytes 6..7 (two places, one of
+    them inactive), so one pass plus the chunk sorts."""
+    rng = np.random.default_rng(12)
+    n = N0
+    k = rng.integers(0, 1 << 64, size=n, dtype=np.uint64)
+    k = (k & ~np.uint64(0xFF << 48)) | np.uint64(0x5A << 48)
+    route = _check(k, "u64", "inactive")
+    assert route["prefix_places"] >= 2 and route["passes"] == route["prefix_places"] - 1, route
+
+
+def test_skewed_and_small_keys_take_plain_passes():
+    """Keys whose top places are mostly zero (80% below 2**20, the rest
+    random bits) and keys with few distinct values keep every active pass."""
+    rng = np.random.default_rng(13)
+    k = rng.integers(0, 1 << 64, size=N0, dtype=np.uint64).view(np.int64)
+    small = rng.random(N0) < 0.8
+    k[small] = rng.integers(0, 1 << 20, size=int(small.sum()), dtype=np.int64)
+    route = _check(k, "i64", "skewed")
+    assert route["prefix_places"] == 0 and route["passes"] == 8, route
+    k = random_keys("f64", N0, rng, "mixed")
+    route = _check(k, "f64", "mixed")
+    assert route["prefix_places"] == 0, route
+    k = np.full(N0, 77, dtype=np.uint64)
+    route = _check(k, "u64", "constant")
+    assert route == {"prefix_places": 0, "passes": 0, "chunks": 0, "fallback_runs": 0, "fallback_keys": 0}, route
+
+
+def test_sortperm_never_takes_prefix_route():
+    rng = np.random.default_rng(14)
+    k = random_keys("u64", N0, rng, "uniform")
+    t = to_gpu(k, "u64")
+    p = ak.sortperm(t, dtype="u64")
+    route = ak.sort_route()
+    assert route["prefix_places"] == 0 and route["passes"] == 8, route
+    assert np.array_equal(p.cpu().numpy().view(np.uint32), oracle.sortperm(k))
+
+
+def test_prefix_route_repeats():
+    """Back-to-back sorts of different inputs on one workspace (the prefix
+    scratch and the fallback's cached launch sequence are reused)."""
+    rng = np.random.default_rng(15)
+    for i in range(3):
+        k = rng.integers(0, 1 << 64, size=N0 + 1000 * i, dtype=np.uint64)
+        if i == 1:
+            heavy = rng.random(k.size) < 0.002
+            k[heavy] = np.uint64(0x1234) << np.uint64(48) | (k[heavy] & np.uint64(0xFFFF))
+        _check(k, "u64", f"repeat{i}")
+    torch.cuda.synchronize()
