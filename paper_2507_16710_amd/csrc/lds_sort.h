@@ -81,6 +81,102 @@ __device__ __forceinline__ void lds_sort_regs(typename KT<DT>::U (&k)[IPT], type
     }
 }
 
+// Keys-only on-chip sort of a chunk of a code-ordered array (the chunk sorts
+// of the prefix-partitioned radix sort), stable, same result as
+// lds_sort_regs.  When more than MB bits vary, one stable pass orders the
+// chunk by its top MB varying bits (most significant digit first; 16-bit
+// counters in the counter space, 2^MB-entry bucket totals and starts in
+// mtot / mstart); if every bucket then holds at most BMAX keys, each key's
+// final place is its bucket's start plus the number of keys of its bucket
+// that precede it in the total order: a smaller image, or an equal image at
+// an earlier place (the pass kept input order).  They are counted by
+// comparing against the bucket's keys in LDS, and the key is stored at its
+// place in `out`, which must not overlap keys other threads still read (the
+// whole chunk is on chip by then).  A chunk of nearly uniform keys has
+// about len / 2^MB keys per bucket, so this costs one ranking pass plus a
+// few comparisons per key instead of one ranking pass per varying digit.
+// Chunks with a larger bucket take the LSD passes of lds_sort_regs over
+// the keys in their bucket order.
+template <int DT, int W, int IPT, int MB, int BMAX = 64>
+__device__ __forceinline__ void lds_sort_chunk(typename KT<DT>::U (&k)[IPT], typename KT<DT>::U *out, uint32_t len,
+                                               SmallSmem<typename KT<DT>::U, false, W, IPT> &sm, uint32_t *mtot,
+                                               uint32_t *mstart, int tid) {
+    using U = typename KT<DT>::U;
+    using I = decltype(KT<DT>::image(k[0]));
+    constexpr int B = W * 64, MR = 1 << MB;
+    static_assert((size_t)W * MR * 2 <= sizeof(sm.cnt), "16-bit digit counters fit the counter space");
+    const int lane = tid & 63, w = tid >> 6;
+    uint64_t vor = 0, vand = ~0ull;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const uint32_t e = striped_elem<IPT>(w, j, lane);
+        if (e < len) {
+            const uint64_t t = (uint64_t)KT<DT>::image(k[j]);
+            vor |= t;
+            vand &= t;
+        }
+    }
+    uint64_t ror, rand_;
+    block_or_and<W>(vor, vand, sm.red, ror, rand_, tid);
+    const uint64_t diff = ror ^ rand_;
+    int lo = 0, hi = -1;
+    if (diff != 0) {
+        lo = __builtin_ctzll(diff);
+        hi = 63 - __builtin_clzll(diff);
+    }
+    if (hi - lo >= MB) {
+        const int shift = hi - (MB - 1);
+        uint16_t *cnt16 = reinterpret_cast<uint16_t *>(sm.cnt);
+        uint32_t rd[IPT];
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const uint32_t e = striped_elem<IPT>(w, j, lane);
+            rd[j] = e < len ? (uint32_t)((uint64_t)KT<DT>::image(k[j]) >> shift) & (MR - 1) : 0u;
+        }
+        rank_match_packed<MB, W, IPT, uint16_t>(rd, len, cnt16, mtot, tid);
+        block_exscan<B, MR>(mtot, mstart, sm.wsum, tid);
+        rank_finish_packed<MB, W, IPT, uint16_t>(rd, cnt16, mstart, tid);
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const uint32_t e = striped_elem<IPT>(w, j, lane);
+            if (e < len) sm.keys[rd[j] & 0xFFFFu] = k[j];
+        }
+        bool big = false;
+        for (int d = tid; d < MR; d += B) big |= mtot[d] > (uint32_t)BMAX;
+        grp_sync<W>();
+        if (!__syncthreads_or(big)) {
+#pragma unroll
+            for (int j = 0; j < IPT; ++j) {
+                const uint32_t e = striped_elem<IPT>(w, j, lane);
+                if (e < len) {
+                    const U key = sm.keys[e];
+                    const I ti = KT<DT>::image(key);
+                    const uint32_t d = (uint32_t)((uint64_t)ti >> shift) & (MR - 1);
+                    const uint32_t b0 = mstart[d], b1 = b0 + mtot[d];
+                    // one loop over the bucket (a wave runs as long as its
+                    // largest bucket; two loops would each run that long)
+                    uint32_t r = 0;
+                    for (uint32_t q = b0; q < b1; ++q) {
+                        const I tq = KT<DT>::image(sm.keys[q]);
+                        r += (tq < ti || (tq == ti && q < e)) ? 1u : 0u;
+                    }
+                    out[b0 + r] = key;
+                }
+            }
+            return;
+        }
+        // a large bucket: LSD passes over the chunk in its new order (the
+        // pass was stable, so equal keys are still in input order)
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const uint32_t e = striped_elem<IPT>(w, j, lane);
+            k[j] = e < len ? sm.keys[e] : U(0);
+        }
+        grp_sync<W>();
+    }
+    lds_sort_regs<DT, false, W, IPT>(k, out, nullptr, len, sm, tid);
+}
+
 // Loads up to W*64*IPT keys from `in` and sorts them on chip (`in` may
 // equal `out`: every key is read before any is written).
 template <int DT, bool VAL, int W, int IPT>

@@ -409,9 +409,10 @@ __device__ uint32_t piece_boundary(const typename KT<DT>::U *keys, uint32_t n, u
     return next_code_change<DT>(keys, n, p, cd(keys[p - 1]), cd);
 }
 
-template <typename U, int W, int IPT>
+template <typename U, int W, int IPT, int MR>
 struct ChunkSmem {
     SmallSmem<U, false, W, IPT> sort;
+    uint32_t mtot[MR], mstart[MR];  // top-digit buckets of the prefix finish
     uint32_t wlast[W];  // code of every wave's last element
     uint32_t cut;
     uint32_t bound[2];
@@ -427,14 +428,14 @@ struct ChunkSmem {
 // Register budget: WPE waves per SIMD (8: 64 VGPRs, so two 16-wave or four
 // 8-wave workgroups per CU), so one workgroup's barriers overlap the
 // others' loads.
-template <int DT, int W, int IPT, int WPE, bool PREFIX>
+template <int DT, int W, int IPT, int WPE, bool PREFIX, int MB = RADIX_BITS>
 __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void k_chunk_sort(typename KT<DT>::U *keys, uint32_t n, const float *model,
                                                        int cb, uint32_t piece, FbRun *fb, LearnedState *ls,
                                                        int staged, const RunState *st) {
     using U = typename KT<DT>::U;
     using CD = typename std::conditional<PREFIX, PrefixCoder<DT>, RmiCoder<DT>>::type;
     constexpr int B = W * 64, CAP = B * IPT;
-    __shared__ ChunkSmem<U, W, IPT> sm;
+    __shared__ ChunkSmem<U, W, IPT, PREFIX ? (1 << MB) : 1> sm;
     extern __shared__ float4 s_leaves[];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     CD cd;
@@ -528,7 +529,11 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(WPE))) v
             cut = pos + q;
             __syncthreads();
         }
-        lds_sort_regs<DT, false, W, IPT>(k, keys + pos, nullptr, cut - pos, sm.sort, tid);
+        // prefix runs of nearly uniform keys: one top-digit pass and
+        // comparisons; model-code chunks (often with many repeated keys):
+        // LSD passes
+        if constexpr (PREFIX) lds_sort_chunk<DT, W, IPT, MB>(k, keys + pos, cut - pos, sm.sort, sm.mtot, sm.mstart, tid);
+        else lds_sort_regs<DT, false, W, IPT>(k, keys + pos, nullptr, cut - pos, sm.sort, tid);
         ++nchunks;
         pos = cut;
         __syncthreads();
@@ -802,9 +807,27 @@ static void launch_chunk_sort(hipStream_t s, uint32_t npieces, typename KT<DT>::
 // The plain radix sort of a key-only run whose top places spread the keys
 // stops after the passes over those places; these launches finish it (they
 // exit at once when the run took all its passes).
-constexpr int PFX_CVAR = 2;  // chunk shape: 4 waves x 8 keys per lane
+// Chunk shapes of the prefix finish (2048 keys each: waves, keys per lane,
+// register budget, bits of the top digit; $AK_PFX_CHUNK_VARIANT picks one).
+struct PfxShape {
+    int w, ipt, wpe, mb;
+};
+constexpr PfxShape PFX_SHAPES[3] = {{8, 4, 8, 9}, {4, 8, 6, 9}, {4, 8, 6, 8}};
+constexpr int PFX_CAP = 2048;
+static_assert(PFX_SHAPES[0].w * 64 * PFX_SHAPES[0].ipt == PFX_CAP && PFX_SHAPES[1].w * 64 * PFX_SHAPES[1].ipt == PFX_CAP &&
+                  PFX_SHAPES[2].w * 64 * PFX_SHAPES[2].ipt == PFX_CAP,
+              "prefix chunk shapes hold PFX_CAP keys");
 
-int prefix_chunk_keys() { return CHUNK_SHAPES[PFX_CVAR].w * 64 * CHUNK_SHAPES[PFX_CVAR].ipt; }
+static int pfx_variant() {
+    static const int v = [] {
+        const char *e = getenv("AK_PFX_CHUNK_VARIANT");
+        const int x = (e && *e) ? atoi(e) : 0;
+        return x >= 0 && x < 3 ? x : 0;
+    }();
+    return v;
+}
+
+int prefix_chunk_keys() { return PFX_CAP; }
 
 // a fallback run is longer than a chunk
 static uint32_t prefix_fb_cap(int64_t n) { return (uint32_t)(n / prefix_chunk_keys() + 2); }
@@ -836,15 +859,21 @@ static ak_status prefix_finish_t(Workspace *ws, void *keys, int64_t n64, const R
     int64_t *hi = lo + cap;
     hipLaunchKernelGGL(k_learned_reset, dim3(1), dim3(256), 0, s, ls, (uint32_t *)nullptr, 0u);
     AK_LAUNCH_CHECK("k_learned_reset");
-    constexpr ChunkShape c = CHUNK_SHAPES[PFX_CVAR];
-    constexpr uint32_t CAP = c.w * 64 * c.ipt;
     const uint32_t pieces_target = (uint32_t)num_cus() * 16;
-    const uint32_t piece = std::max<uint32_t>(CAP * 4, (n + pieces_target - 1) / pieces_target);
+    const uint32_t piece = std::max<uint32_t>(PFX_CAP * 4, (n + pieces_target - 1) / pieces_target);
     const uint32_t npieces = (n + piece - 1) / piece;
     {
         ProfScope ps("prefix_chunk_sort", s);
-        hipLaunchKernelGGL((k_chunk_sort<DT, c.w, c.ipt, c.wpe, true>), dim3(npieces), dim3(c.w * 64), 0, s, (U *)keys,
-                           n, (const float *)nullptr, 0, piece, fb, ls, 0, st);
+        auto launch = [&](auto shape) {
+            constexpr PfxShape c = PFX_SHAPES[decltype(shape)::value];
+            hipLaunchKernelGGL((k_chunk_sort<DT, c.w, c.ipt, c.wpe, true, c.mb>), dim3(npieces), dim3(c.w * 64), 0, s,
+                               (U *)keys, n, (const float *)nullptr, 0, piece, fb, ls, 0, st);
+        };
+        switch (pfx_variant()) {
+        case 0: launch(std::integral_constant<int, 0>{}); break;
+        case 1: launch(std::integral_constant<int, 1>{}); break;
+        default: launch(std::integral_constant<int, 2>{}); break;
+        }
     }
     AK_LAUNCH_CHECK("k_chunk_sort");
     const uint32_t fgrid = std::min<uint32_t>((cap + 255) / 256, 4096);

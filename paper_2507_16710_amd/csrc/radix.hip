@@ -166,7 +166,11 @@ __global__ __launch_bounds__(CODE ? 1024 : 256) void k_hist(const typename KT<DT
             U t = KT<DT>::image(v[it]);
             if (CODE) t = (U)rmi_code(h, leaves, t, cb, scale);
             const uint64_t act = ballot64(true);
-            for (int p = 0; p < nplaces; ++p) {
+            // key digits: every place of the key, unrolled (constant shifts)
+            constexpr int KP = (int)sizeof(U);
+#pragma unroll
+            for (int p = 0; p < (CODE ? MAX_PLACES : KP); ++p) {
+                if (CODE && p >= nplaces) break;
                 const uint32_t d = (uint32_t)(t >> (p * RADIX_BITS)) & (RADIX - 1);
                 const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
                 if (ballot64(d == d0) == act) {

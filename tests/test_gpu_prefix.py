@@ -112,3 +112,22 @@ def test_prefix_route_repeats():
             k[heavy] = np.uint64(0x1234) << np.uint64(48) | (k[heavy] & np.uint64(0xFFFF))
         _check(k, "u64", f"repeat{i}")
     torch.cuda.synchronize()
+
+
+def test_repeated_keys_take_in_chunk_fallback():
+    """Every value repeated 100 times: the per-place counts still look
+    uniform (prefix route), but each chunk's top-digit buckets hold about
+    100 keys, more than the comparison finish takes, so those chunks run the
+    LSD passes on chip; ties keep their order (identical keys)."""
+    rng = np.random.default_rng(16)
+    vals = rng.integers(0, 1 << 64, size=N0 // 100 + 1, dtype=np.uint64)
+    k = np.repeat(vals, 100)[:N0]
+    rng.shuffle(k)
+    route = _check(k, "u64", "repeated")
+    assert route["prefix_places"] >= 2 and route["chunks"] > 0, route
+    # float keys with repeated values and both zeros
+    f = np.repeat(rng.standard_normal(N0 // 50 + 1), 50)[:N0]
+    f[rng.random(N0) < 0.01] = -0.0
+    f[rng.random(N0) < 0.01] = 0.0
+    rng.shuffle(f)
+    _check(f.astype(np.float64), "f64", "repeated-float")
