@@ -83,7 +83,7 @@ __device__ __forceinline__ void lds_sort_regs(typename KT<DT>::U (&k)[IPT], type
 
 // Keys-only on-chip sort of a chunk of a code-ordered array (the chunk sorts
 // of the prefix-partitioned radix sort), stable, same result as
-// lds_sort_regs.  When more than MB bits vary, one stable pass orders the
+// lds_sort_regs.  When more than 24 bits vary, one stable pass orders the
 // chunk by its top MB varying bits (most significant digit first; 16-bit
 // counters in the counter space, 2^MB-entry bucket totals and starts in
 // mtot / mstart); if every bucket then holds at most BMAX keys, each key's
@@ -124,7 +124,10 @@ __device__ __forceinline__ void lds_sort_chunk(typename KT<DT>::U (&k)[IPT], typ
         lo = __builtin_ctzll(diff);
         hi = 63 - __builtin_clzll(diff);
     }
-    if (hi - lo >= MB) {
+    // more than three digits vary: one pass and comparisons beat the LSD
+    // passes (fewer varying bits: the LSD passes, which also suit chunks of
+    // a few repeated values)
+    if (hi - lo + 1 > 3 * RADIX_BITS) {
         const int shift = hi - (MB - 1);
         uint16_t *cnt16 = reinterpret_cast<uint16_t *>(sm.cnt);
         uint32_t rd[IPT];

@@ -428,7 +428,7 @@ struct ChunkSmem {
 // Register budget: WPE waves per SIMD (8: 64 VGPRs, so two 16-wave or four
 // 8-wave workgroups per CU), so one workgroup's barriers overlap the
 // others' loads.
-template <int DT, int W, int IPT, int WPE, bool PREFIX, int MB = RADIX_BITS>
+template <int DT, int W, int IPT, int WPE, bool PREFIX, int MB = 9>
 __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void k_chunk_sort(typename KT<DT>::U *keys, uint32_t n, const float *model,
                                                        int cb, uint32_t piece, FbRun *fb, LearnedState *ls,
                                                        int staged, const RunState *st) {
@@ -529,9 +529,9 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(WPE))) v
             cut = pos + q;
             __syncthreads();
         }
-        // prefix runs of nearly uniform keys: one top-digit pass and
-        // comparisons; model-code chunks (often with many repeated keys):
-        // LSD passes
+        // prefix runs (keys spread over many bits): one top-digit pass and
+        // comparisons; model-code chunks (measured: no gain, many repeated
+        // keys): LSD passes
         if constexpr (PREFIX) lds_sort_chunk<DT, W, IPT, MB>(k, keys + pos, cut - pos, sm.sort, sm.mtot, sm.mstart, tid);
         else lds_sort_regs<DT, false, W, IPT>(k, keys + pos, nullptr, cut - pos, sm.sort, tid);
         ++nchunks;

@@ -126,10 +126,10 @@ __device__ void scan_places(RunState *st, uint32_t n, int nplaces, uint32_t *s_b
 
 // ---------------------------------------------------------- histogram
 // One read of the keys; counts the digit of every place.  LDS counters per
-// workgroup, then one global atomic per nonzero bin.  A wave whose lanes all
-// hold the same digit adds its lane count once instead of 64 conflicting
-// LDS atomics (long runs of equal digits are the common case for the
-// high places of small keys).
+// workgroup, then one global atomic per nonzero bin.  The lanes of a wave
+// that hold the first lane's digit add their count once instead of as
+// conflicting LDS atomics on one address (all 64 for a constant high place
+// of small keys, the frequent digit of a skewed place).
 // Code digits use 1024-thread workgroups: the staged model table (64 KB at
 // 4096 leaves) leaves room for two workgroups per CU.
 template <int DT, bool CODE>
@@ -172,9 +172,15 @@ __global__ __launch_bounds__(CODE ? 1024 : 256) void k_hist(const typename KT<DT
             for (int p = 0; p < (CODE ? MAX_PLACES : KP); ++p) {
                 if (CODE && p >= nplaces) break;
                 const uint32_t d = (uint32_t)(t >> (p * RADIX_BITS)) & (RADIX - 1);
+                // the lanes that share the first lane's digit add once when
+                // there are many of them (all lanes of a constant place, the
+                // frequent digit of a skewed one); otherwise every lane adds
+                // one (a single atomic instruction)
                 const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-                if (ballot64(d == d0) == act) {
-                    if (count_below(act) == 0) atomicAdd(&s_h[p * RADIX + d0], (uint32_t)__popcll(act));
+                const uint64_t m0 = ballot64(d == d0);
+                if (__popcll(m0) > 8) {
+                    if (count_below(act) == 0) atomicAdd(&s_h[p * RADIX + d0], (uint32_t)__popcll(m0));
+                    if (d != d0) atomicAdd(&s_h[p * RADIX + d], 1u);
                 } else {
                     atomicAdd(&s_h[p * RADIX + d], 1u);
                 }
