@@ -404,17 +404,33 @@ __global__ __launch_bounds__(256) void k_xl_hist(const SegArgs *ap, SegState *st
             const int64_t lo = a.off[s], len = a.hi[s] - lo;
             const uint32_t tb = (g - a.xl_pre[i]) * (uint32_t)XL_TILE;
             const uint32_t tv = (uint32_t)min((int64_t)XL_TILE, len - (int64_t)tb);
-            for (uint32_t e = tid; e < tv; e += 256) {
-                const U t = KT<DT>::image(keys[lo + tb + e]);
-                const uint64_t act = ballot64(true);
+            // XI keys per thread in flight before they are counted
+            constexpr int XI = 4;
+            for (uint32_t e0 = 0; e0 < tv; e0 += 256 * XI) {
+                U v[XI];
 #pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    const uint32_t d = (uint32_t)(t >> (8 * p)) & (RADIX - 1);
-                    const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-                    if (ballot64(d == d0) == act) {
-                        if (count_below(act) == 0) atomicAdd(&s_h[p * RADIX + d0], (uint32_t)__popcll(act));
-                    } else {
-                        atomicAdd(&s_h[p * RADIX + d], 1u);
+                for (int it = 0; it < XI; ++it) {
+                    const uint32_t e = e0 + it * 256 + tid;
+                    v[it] = e < tv ? keys[lo + tb + e] : U(0);
+                }
+#pragma unroll
+                for (int it = 0; it < XI; ++it) {
+                    if (e0 + it * 256 + tid >= tv) break;
+                    const U t = KT<DT>::image(v[it]);
+                    const uint64_t act = ballot64(true);
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        const uint32_t d = (uint32_t)(t >> (8 * p)) & (RADIX - 1);
+                        // lanes sharing the first lane's digit add once when
+                        // there are many (constant or skewed places)
+                        const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+                        const uint64_t m0 = ballot64(d == d0);
+                        if (__popcll(m0) > 8) {
+                            if (count_below(act) == 0) atomicAdd(&s_h[p * RADIX + d0], (uint32_t)__popcll(m0));
+                            if (d != d0) atomicAdd(&s_h[p * RADIX + d], 1u);
+                        } else {
+                            atomicAdd(&s_h[p * RADIX + d], 1u);
+                        }
                     }
                 }
             }
