@@ -689,11 +689,12 @@ __global__ __launch_bounds__(W * 64) void k_small_sort(const typename KT<DT>::U 
 // per-tile work (digit scan, look-back, barriers) over more keys and make
 // the digit runs of the scatter longer.
 static const int OS_DEFAULT[2][2] = {{3, 3}, {3, 2}};
-// default shape of the code-digit passes per key width.  64-bit keys: 16
-// waves x 10 keys, the largest tile whose staging buffer still fits the LDS
-// beside the 64 KB model table (2^31 mixture keys, per pass: 16 x 6 keys
-// 20.7 ms, 16 x 8 keys 18.0 ms, 16 x 10 keys 16.1 ms)
-static const int OS_CODE_DEFAULT[2] = {0, 3};
+// default shape of the code-digit passes per key width.  64-bit keys: a
+// 10240-key tile, the largest whose staging buffer still fits the LDS beside
+// the 64 KB model table, held by 8 waves x 20 keys (2^31 mixture keys, per
+// pass: 16 x 6 keys 20.7 ms, 16 x 8 keys 18.0 ms, 16 x 10 keys 16.1 ms,
+// 8 x 20 keys 15.6 ms)
+static const int OS_CODE_DEFAULT[2] = {0, 0};
 
 static int env_variant(const char *name) {
     const char *e = getenv(name);

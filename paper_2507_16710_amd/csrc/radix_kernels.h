@@ -60,7 +60,7 @@ constexpr OsShape OS_SHAPES[2][2][OS_NVAR] = {
 // os_code_variant() picks one ($AK_OS_CODE_VARIANT overrides it).
 constexpr OsShape OS_CODE_SHAPES[2][OS_NVAR] = {
     {{16, 8, true}, {16, 6, true}, {16, 12, true}, {8, 12, true}},
-    {{16, 4, true}, {16, 8, true}, {16, 6, true}, {16, 10, true}},
+    {{8, 20, true}, {16, 8, true}, {8, 16, true}, {16, 10, true}},
 };
 int os_variant(int dt, bool val);
 int os_code_variant(int dt);
