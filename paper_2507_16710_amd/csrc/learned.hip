@@ -424,19 +424,18 @@ struct ChunkSmem {
 // changes into chunks of at most W*64*IPT keys and sorts each on chip.
 // PREFIX: the code is the key-prefix field the run state describes, and the
 // kernel exits at once if the run took plain passes instead; otherwise the
-// model code (the leaf table can be staged in LDS, dynamic shared memory).
+// model code.
 // Register budget: WPE waves per SIMD (8: 64 VGPRs, so two 16-wave or four
 // 8-wave workgroups per CU), so one workgroup's barriers overlap the
 // others' loads.
 template <int DT, int W, int IPT, int WPE, bool PREFIX, int MB = 9>
 __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void k_chunk_sort(typename KT<DT>::U *keys, uint32_t n, const float *model,
                                                        int cb, uint32_t piece, FbRun *fb, LearnedState *ls,
-                                                       int staged, const RunState *st) {
+                                                       const RunState *st) {
     using U = typename KT<DT>::U;
     using CD = typename std::conditional<PREFIX, PrefixCoder<DT>, RmiCoder<DT>>::type;
     constexpr int B = W * 64, CAP = B * IPT;
     __shared__ ChunkSmem<U, W, IPT, PREFIX ? (1 << MB) : 1> sm;
-    extern __shared__ float4 s_leaves[];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     CD cd;
     if constexpr (PREFIX) {
@@ -444,8 +443,10 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(WPE))) v
         cd.shift = st->pfx_shift;
         cd.mask = st->pfx_mask;
     } else {
+        // the keys of a chunk lie in a narrow code range, so their leaf
+        // records stay in cache: the table is read from global memory
         cd.h = rmi_head(model);
-        cd.lv = rmi_stage(model, staged ? s_leaves : nullptr);
+        cd.lv = rmi_leaves(model);
         cd.cb = cb;
         cd.scale = (float)(1u << cb);
     }
@@ -788,7 +789,7 @@ static void launch_chunk_sort(hipStream_t s, uint32_t npieces, typename KT<DT>::
                               const float *model, int cb, uint32_t piece, FbRun *fb, LearnedState *ls) {
     constexpr ChunkShape c = CHUNK_SHAPES[V];
     hipLaunchKernelGGL((k_chunk_sort<DT, c.w, c.ipt, c.wpe, false>), dim3(npieces), dim3(c.w * 64), 0, s, keys, n,
-                       model, cb, piece, fb, ls, 0, (const RunState *)nullptr);
+                       model, cb, piece, fb, ls, (const RunState *)nullptr);
 }
 
 // dtype dispatch of a templated driver
@@ -867,7 +868,7 @@ static ak_status prefix_finish_t(Workspace *ws, void *keys, int64_t n64, const R
         auto launch = [&](auto shape) {
             constexpr PfxShape c = PFX_SHAPES[decltype(shape)::value];
             hipLaunchKernelGGL((k_chunk_sort<DT, c.w, c.ipt, c.wpe, true, c.mb>), dim3(npieces), dim3(c.w * 64), 0, s,
-                               (U *)keys, n, (const float *)nullptr, 0, piece, fb, ls, 0, st);
+                               (U *)keys, n, (const float *)nullptr, 0, piece, fb, ls, st);
         };
         switch (pfx_variant()) {
         case 0: launch(std::integral_constant<int, 0>{}); break;

@@ -159,12 +159,23 @@ __global__ __launch_bounds__(CODE ? 1024 : 256) void k_hist(const typename KT<DT
             const uint32_t i = base + it * B + tid;
             v[it] = i < n ? __builtin_nontemporal_load(keys + i) : U(0);
         }
+        // model codes: one uniform branch per batch, so the staged table is
+        // read with LDS instructions (not flat loads through a pointer that
+        // may be LDS or global)
+        U cv[ITEMS];
+        if constexpr (CODE) {
+            auto codes = [&](const RmiLeaf *lv) {
+#pragma unroll
+                for (int it = 0; it < ITEMS; ++it) cv[it] = (U)rmi_code(h, lv, KT<DT>::image(v[it]), cb, scale);
+            };
+            if (staged) codes(reinterpret_cast<const RmiLeaf *>(s_leaves));
+            else codes(rmi_leaves(model));
+        }
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
             const uint32_t i = base + it * B + tid;
             if (i >= n) break;
-            U t = KT<DT>::image(v[it]);
-            if (CODE) t = (U)rmi_code(h, leaves, t, cb, scale);
+            const U t = CODE ? cv[it] : KT<DT>::image(v[it]);
             const uint64_t act = ballot64(true);
             // key digits: every place of the key, unrolled (constant shifts)
             constexpr int KP = (int)sizeof(U);
@@ -333,12 +344,27 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(
     const uint32_t tbase = tile * (uint32_t)TILE;
     const uint32_t tvalid = min((uint32_t)TILE, a.n - tbase);
     uint32_t rd[IPT];  // digit, then rank | digit << 16
+    if constexpr (CODE) {
+        // one uniform branch: the staged table is read with LDS
+        // instructions (a pointer that may be LDS or global would be read
+        // with slower flat loads)
+        auto code_digits = [&](const RmiLeaf *lv) {
 #pragma unroll
-    for (int jj = 0; jj < IPT; ++jj) {
-        const uint32_t e = striped_elem<IPT>(w, jj, lane);
-        U t = KT<DT>::image(k[jj]);
-        if (CODE) t = (U)rmi_code(h, leaves, t, a.cb, scale);
-        rd[jj] = e < tvalid ? (uint32_t)(t >> shift) & (RADIX - 1) : 0u;
+            for (int jj = 0; jj < IPT; ++jj) {
+                const uint32_t e = striped_elem<IPT>(w, jj, lane);
+                const uint32_t c = rmi_code(h, lv, KT<DT>::image(k[jj]), a.cb, scale);
+                rd[jj] = e < tvalid ? (c >> shift) & (RADIX - 1) : 0u;
+            }
+        };
+        if (a.staged) code_digits(reinterpret_cast<const RmiLeaf *>(s_leaves));
+        else code_digits(rmi_leaves(a.model));
+    } else {
+#pragma unroll
+        for (int jj = 0; jj < IPT; ++jj) {
+            const uint32_t e = striped_elem<IPT>(w, jj, lane);
+            const U t = KT<DT>::image(k[jj]);
+            rd[jj] = e < tvalid ? (uint32_t)(t >> shift) & (RADIX - 1) : 0u;
+        }
     }
 
     rank_match_packed<RADIX_BITS, W, IPT, uint16_t>(rd, tvalid, s_cnt, s_tot, tid);
