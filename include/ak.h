@@ -60,7 +60,12 @@ typedef enum {
 /* ------------------------------------------------------------------ sort
  * Sec. II-B (merge_sort): sorts keys[0..n) ascending, in place.  Output keys
  * keep their original bit patterns (NaN payloads and signs included); NaNs
- * end up last, in input order.  Scratch: n keys + per-tile look-back words.
+ * end up last, in input order.  LSD radix passes over the active digit
+ * places; above 2^22 keys, when the digit counts show that the top places
+ * spread the keys, only those places take passes and each run of equal
+ * prefix is finished on chip (same result; ak_sort_route tells which).
+ * Scratch: two key buffers, per-tile look-back words, and above 2^22 keys
+ * the prefix finish's run lists (ak_temp_bytes gives the total).
  * Errors: AK_ERR_INVALID_ARG for n < 0, n >= 2^32 or keys == NULL with
  * n > 0; AK_ERR_UNSUPPORTED_DTYPE for an unknown dtype. */
 ak_status ak_sort(void *keys, int64_t n, ak_dtype dtype, ak_stream_t stream);

@@ -728,9 +728,17 @@ static int env_variant(const char *name) {
     return v >= 0 && v < OS_NVAR ? v : -1;
 }
 
-int os_variant(int dt, bool val) {
+// Key-only sorts of at most 2^21 keys are bound by launch latency: the
+// first shape of the table (16 x 8 keys for 32-bit keys, 16 x 4 for 64-bit
+// keys) gives more tiles per pass and was faster there (1M int64 keys: 233
+// -> 205 us; 2^20 float32: 140 -> 128 us).  Sortperm keeps its shapes.
+constexpr int64_t SMALL_SHAPE_MAX = int64_t(1) << 21;
+
+int os_variant(int dt, bool val, int64_t n) {
     static const int forced = env_variant("AK_OS_VARIANT");
-    return forced >= 0 ? forced : OS_DEFAULT[key_bits(dt) == 64][val];
+    if (forced >= 0) return forced;
+    if (!val && n <= SMALL_SHAPE_MAX) return 0;
+    return OS_DEFAULT[key_bits(dt) == 64][val];
 }
 
 int os_code_variant(int dt) {
@@ -742,7 +750,7 @@ constexpr int SMALL_W = 4, SMALL_IPT = 16;
 
 int64_t small_sort_capacity(int) { return SMALL_W * 64 * SMALL_IPT; }
 
-static inline int tile_keys(int dt, bool val) { return os_tile(dt, val); }
+static inline int tile_keys(int dt, bool val, int64_t n) { return os_tile(dt, val, n); }
 
 static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -757,7 +765,7 @@ constexpr int64_t PREFIX_MIN = int64_t(1) << 22;
 size_t radix_temp_bytes(int dt, int64_t n, bool perm) {
     if (n <= small_sort_capacity(dt)) return 0;
     const size_t kb = (size_t)dtype_bytes(dt);
-    const size_t tiles = (size_t)((n + tile_keys(dt, perm) - 1) / tile_keys(dt, perm));
+    const size_t tiles = (size_t)((n + tile_keys(dt, perm, n) - 1) / tile_keys(dt, perm, n));
     // two key-sized ping-pong buffers (sort: the second one lets an odd
     // number of passes end in the caller's buffer; sortperm: the const keys
     // are never written), the look-back words, and the index buffer
@@ -826,8 +834,8 @@ template <int DT, bool VAL, bool CODE>
 static ak_status launch_passes(hipStream_t stream, Workspace *ws, RunState *st, const void *keys_in, void *t0, void *t1,
                                uint32_t *v0, uint32_t *perm, uint32_t n, int nplaces, const float *model, int cb,
                                size_t stage) {
-    const int var = CODE ? os_code_variant(DT) : os_variant(DT, VAL);
-    const int TILE = CODE ? os_code_tile(DT) : os_tile(DT, VAL);
+    const int var = CODE ? os_code_variant(DT) : os_variant(DT, VAL, n);
+    const int TILE = CODE ? os_code_tile(DT) : os_tile(DT, VAL, n);
     const uint32_t tiles = (n + TILE - 1) / TILE;
     OnesweepArgs a{};
     a.keys = const_cast<void *>(keys_in);
@@ -957,7 +965,7 @@ static ak_status radix_sort_t(Workspace *ws, void *keys, uint32_t *perm, int64_t
     if ((r = ws_reserve(ws, &ws->keys0, &ws->keys0_bytes, (size_t)n * kb)) != AK_OK) return r;
     if ((r = ws_reserve(ws, &ws->keys1, &ws->keys1_bytes, (size_t)n * kb)) != AK_OK) return r;
     if (pm && (r = ws_reserve(ws, &ws->vals0, &ws->vals0_bytes, (size_t)n * 4)) != AK_OK) return r;
-    const int TILE = tile_keys(DT, pm);
+    const int TILE = tile_keys(DT, pm, n64);
     const size_t tiles = (n + TILE - 1) / TILE;
     if ((r = ws_reserve_lookback(ws, lookback_words(tiles) * 8)) != AK_OK) return r;
     if ((r = ws_reserve(ws, &ws->aux[4], &ws->aux_bytes[4], rts_bytes(tiles))) != AK_OK) return r;

@@ -62,10 +62,10 @@ constexpr OsShape OS_CODE_SHAPES[2][OS_NVAR] = {
     {{16, 8, true}, {16, 6, true}, {16, 12, true}, {8, 12, true}},
     {{8, 20, true}, {16, 8, true}, {8, 16, true}, {16, 10, true}},
 };
-int os_variant(int dt, bool val);
+int os_variant(int dt, bool val, int64_t n);
 int os_code_variant(int dt);
-inline int os_tile(int dt, bool val) {
-    const OsShape s = OS_SHAPES[key_bits(dt) == 64][val][os_variant(dt, val)];
+inline int os_tile(int dt, bool val, int64_t n) {
+    const OsShape s = OS_SHAPES[key_bits(dt) == 64][val][os_variant(dt, val, n)];
     return s.w * 64 * s.ipt;
 }
 inline int os_code_tile(int dt) {
