@@ -11,7 +11,8 @@ outputs are checked bit for bit against each other after the timed steps.
 value = input bytes sorted per second (GB/s) of the learned sort.
 roofline: the kernel with the largest share of the learned sort's time,
   algorithmic bytes per launch / its mean launch time (HIP events recorded
-  by the library on the launch stream during the timed steps).
+  by the library on the launch stream during the timed steps), against the
+  nominal 8 TB/s and against this GPU's measured streaming-copy bandwidth.
 cpu_baseline: the oracle's threaded merge sort on a bounded sample of the
   same keys, on this host's cores.
 extras: the other workloads (1M int64 latency, 2**28 float32 sort and
@@ -189,6 +190,21 @@ def main():
     log(f"generated {n} keys in {time.time() - t0:.1f} s")
     work = torch.empty_like(keys)
 
+    # streaming-copy bandwidth of this GPU (a device copy of the keys: one
+    # read and one write of n*8 bytes), the practical ceiling beside the
+    # nominal 8 TB/s
+    copy_ms = []
+    for r in range(4):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        work.copy_(keys)
+        b.record()
+        torch.cuda.synchronize()
+        if r:
+            copy_ms.append(a.elapsed_time(b))
+    copy_gbps = 2 * n * 8 / (min(copy_ms) / 1e3) / 1e9
+
     # plain radix sort of the same keys (reference path)
     plain_ms = timed_steps(torch, lambda t: ak.sort_(t, dtype="u64"), keys, work, args.steps, args.warmup)
     plain_out = work.clone()
@@ -216,6 +232,8 @@ def main():
     rl = roofline(learned_launches, n, 8, None)
     if rl is not None:
         rl["traffic"] = load_traffic(rl["kernel"])
+        rl["copy_GBps"] = round(copy_gbps, 1)
+        rl["frac_of_copy"] = round(rl["achieved"] / copy_gbps, 4)
     # learned-path algorithmic bytes: histogram read + 2 per code pass + chunk sort
     passes = (stats["code_bits"] + 7) // 8
     alg_bytes = n * 8 * (1 + 2 * passes + 2)
