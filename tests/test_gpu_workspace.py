@@ -89,3 +89,30 @@ def test_segment_offsets_beyond_keys_are_refused():
     off = torch.tensor([-1, 500], dtype=torch.int64, device="cuda")
     with pytest.raises(ValueError):
         ak.segmented_sort_(t, off, dtype="i64")
+
+
+def test_arena_prefix_route_exact_size():
+    """Key-only sorts above 2**22 keys take the prefix route, whose run lists
+    and fallback scratch come from the arena too: an arena of exactly
+    ak_temp_bytes("sort", n) suffices, with and without fallback runs."""
+    rng = np.random.default_rng(41)
+    n = (1 << 22) + 777
+    need = ak.temp_bytes("sort", n, "u64")
+    arena = torch.empty(need, dtype=torch.uint8, device="cuda")
+    ak.set_workspace(arena)
+    try:
+        for heavy_frac in (0.0, 0.002):
+            k = rng.integers(0, 1 << 64, size=n, dtype=np.uint64)
+            if heavy_frac:
+                h = rng.random(n) < heavy_frac
+                k[h] = (np.uint64(0x7777) << np.uint64(48)) | (k[h] & np.uint64((1 << 48) - 1))
+            print(f"arena prefix heavy={heavy_frac}", flush=True)
+            t = to_gpu(k, "u64")
+            ak.sort_(t, dtype="u64")
+            route = ak.sort_route()
+            assert route["prefix_places"] >= 2, route
+            if heavy_frac:
+                assert route["fallback_runs"] >= 1, route
+            assert np.array_equal(to_host(t, "u64"), oracle.sort(k))
+    finally:
+        ak.set_workspace(None)
