@@ -131,3 +131,24 @@ def test_repeated_keys_take_in_chunk_fallback():
     f[rng.random(N0) < 0.01] = 0.0
     rng.shuffle(f)
     _check(f.astype(np.float64), "f64", "repeated-float")
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_prefix_route_with_nan_payloads_and_zeros(dt):
+    """Raw random bits: NaNs with every payload and sign (all tie, so they
+    keep input order), both zeros and infinities.  The NaN run exceeds a
+    chunk and goes to the segmented fallback, which must keep it stable."""
+    rng = np.random.default_rng(zlib.crc32(f"pfxnan{dt}".encode()))
+    n = N0
+    w = 32 if dt == "f32" else 64
+    raw = rng.integers(0, 1 << w, size=n, dtype=np.uint64).astype(np.uint32 if w == 32 else np.uint64)
+    k = raw.view(np.float32 if w == 32 else np.float64).copy()
+    pos = rng.choice(n, size=3000, replace=False)
+    k[pos[:1000]] = -0.0
+    k[pos[1000:2000]] = 0.0
+    k[pos[2000:2500]] = np.inf
+    k[pos[2500:]] = -np.inf
+    route = _check(k, dt, "nan-payloads")
+    assert route["prefix_places"] >= 2, route
+    if dt == "f32":
+        assert route["fallback_runs"] >= 1, route   # about n/256 NaNs in one run
