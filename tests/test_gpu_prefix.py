@@ -14,7 +14,7 @@ import torch
 
 import oracle
 import paper_2507_16710_amd as ak
-from gpucheck import to_gpu, to_host
+from gpucheck import fingerprint, is_sorted, rank_checks, to_gpu, to_host
 from pools import bits, random_keys
 
 pytestmark = pytest.mark.gpu
@@ -152,3 +152,26 @@ def test_prefix_route_with_nan_payloads_and_zeros(dt):
     assert route["prefix_places"] >= 2, route
     if dt == "f32":
         assert route["fallback_runs"] >= 1, route   # about n/256 NaNs in one run
+
+
+def test_prefix_route_full_size_2p31():
+    """2**31 uniform uint64 keys (17 GiB, about a million chunks): the prefix
+    route at the largest size; sorted, same multiset, sampled ranks, and the
+    oracle's sort of a strided sample equals the sorted sample."""
+    g = torch.Generator(device="cuda").manual_seed(2031)
+    keys = torch.randint(-(1 << 63), (1 << 63) - 1, (1 << 31,), generator=g, device="cuda", dtype=torch.int64)
+    fp = fingerprint(keys)
+    t = keys.clone()
+    ak.sort_(t, dtype="u64")
+    route = ak.sort_route()
+    print(route, flush=True)
+    assert route["prefix_places"] == 3 and route["passes"] == 3, route
+    assert is_sorted(t, "u64") and fingerprint(t) == fp
+    rank_checks(keys, t, "u64", samples=8)
+    idx = torch.arange(0, keys.numel(), 65537, device="cuda")
+    sub = to_host(keys[idx], "u64")
+    del keys, t
+    torch.cuda.empty_cache()
+    t2 = to_gpu(sub, "u64")
+    ak.sort_(t2, dtype="u64")
+    assert np.array_equal(to_host(t2, "u64"), oracle.sort(sub))
