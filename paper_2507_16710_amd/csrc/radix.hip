@@ -225,6 +225,14 @@ __global__ __launch_bounds__(CODE ? 1024 : 256) void k_hist(const typename KT<DT
 // one writes the caller's keys.
 __device__ __forceinline__ bool odd_route(int q, const void *t1) { return t1 != nullptr && (q & 1) && q >= 3; }
 
+// Keys whose model codes a code pass forms together (their table reads in
+// flight at once; the persistent code passes run two waves per SIMD, too
+// few to hide one read's latency behind another wave).
+#ifndef AK_CODE_GROUP
+#define AK_CODE_GROUP 2
+#endif
+constexpr int CODE_GROUP = AK_CODE_GROUP;
+
 template <typename U, bool VAL, bool CODE, int W, int IPT>
 struct OsSmem {
     static constexpr int TILE = W * 64 * IPT;
@@ -347,13 +355,22 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(
     if constexpr (CODE) {
         // one uniform branch: the staged table is read with LDS
         // instructions (a pointer that may be LDS or global would be read
-        // with slower flat loads)
+        // with slower flat loads).  No per-key bounds test: the ranking
+        // ignores the digits past the tile's end (keys there are zero, and
+        // the clamped leaf index keeps their table reads in bounds), and a
+        // test would become a branch around each key's table reads that
+        // serialises their latency.
         auto code_digits = [&](const RmiLeaf *lv) {
+            constexpr int G = IPT % CODE_GROUP == 0 ? CODE_GROUP : (IPT % 2 == 0 ? 2 : 1);
 #pragma unroll
-            for (int jj = 0; jj < IPT; ++jj) {
-                const uint32_t e = striped_elem<IPT>(w, jj, lane);
-                const uint32_t c = rmi_code(h, lv, KT<DT>::image(k[jj]), a.cb, scale);
-                rd[jj] = e < tvalid ? (c >> shift) & (RADIX - 1) : 0u;
+            for (int j0 = 0; j0 < IPT; j0 += G) {
+                U t[G];
+                uint32_t c[G];
+#pragma unroll
+                for (int g = 0; g < G; ++g) t[g] = KT<DT>::image(k[j0 + g]);
+                rmi_code_group<G>(h, lv, t, a.cb, scale, c);
+#pragma unroll
+                for (int g = 0; g < G; ++g) rd[j0 + g] = (c[g] >> shift) & (RADIX - 1);
             }
         };
         if (a.staged) code_digits(reinterpret_cast<const RmiLeaf *>(s_leaves));

@@ -46,22 +46,51 @@ __device__ __forceinline__ int rmi_leaf(const RmiHead &h, U t, float &x) {
     return (int)p;
 }
 
-template <typename U>
-__device__ __forceinline__ float rmi_cdf(const RmiHead &h, const RmiLeaf *leaves, U t) {
-    float x;
-    const int leaf = rmi_leaf(h, t, x);
-    const RmiLeaf p = leaves[leaf];
-    const float hi = leaves[leaf + 1].w;
+// F of a key whose leaf record p and upper clamp hi are already read
+__device__ __forceinline__ float rmi_cdf_at(const RmiLeaf &p, float hi, float x) {
     const float F = __fadd_rn(__fmul_rn(p.x, __fsub_rn(x, p.z)), p.y);
     return fminf(fmaxf(F, p.w), hi);
 }
 
-template <typename U>
-__device__ __forceinline__ uint32_t rmi_code(const RmiHead &h, const RmiLeaf *leaves, U t, int cb, float scale) {
-    const float F = rmi_cdf(h, leaves, t);
-    const uint32_t c = (uint32_t)__fmul_rn(F, scale);
+__device__ __forceinline__ uint32_t rmi_code_at(const RmiLeaf &p, float hi, float x, int cb, float scale) {
+    const uint32_t c = (uint32_t)__fmul_rn(rmi_cdf_at(p, hi, x), scale);
     const uint32_t top = (1u << cb) - 1u;
     return c < top ? c : top;
+}
+
+template <typename U>
+__device__ __forceinline__ float rmi_cdf(const RmiHead &h, const RmiLeaf *leaves, U t) {
+    float x;
+    const int leaf = rmi_leaf(h, t, x);
+    return rmi_cdf_at(leaves[leaf], leaves[leaf + 1].w, x);
+}
+
+template <typename U>
+__device__ __forceinline__ uint32_t rmi_code(const RmiHead &h, const RmiLeaf *leaves, U t, int cb, float scale) {
+    float x;
+    const int leaf = rmi_leaf(h, t, x);
+    return rmi_code_at(leaves[leaf], leaves[leaf + 1].w, x, cb, scale);
+}
+
+// Codes of G keys: every leaf is located and its records requested before
+// any code is formed, so the table reads of the G keys are in flight
+// together.
+template <int G, typename U>
+__device__ __forceinline__ void rmi_code_group(const RmiHead &h, const RmiLeaf *leaves, const U (&t)[G], int cb,
+                                               float scale, uint32_t (&c)[G]) {
+    float x[G];
+    int leaf[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) leaf[g] = rmi_leaf(h, t[g], x[g]);
+    RmiLeaf p[G];
+    float hi[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        p[g] = leaves[leaf[g]];
+        hi[g] = leaves[leaf[g] + 1].w;
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) c[g] = rmi_code_at(p[g], hi[g], x[g], cb, scale);
 }
 
 // Copies the L+1 leaf records into LDS (`dst`, room for L+1 float4) with
