@@ -413,7 +413,7 @@ template <typename U, int W, int IPT, int MR>
 struct ChunkSmem {
     SmallSmem<U, false, W, IPT> sort;
     uint32_t mtot[MR], mstart[MR];  // top-digit buckets of the prefix finish
-    uint32_t wlast[W];  // code of every wave's last element
+    uint32_t clast;  // code of the chunk's last element
     uint32_t cut;
     uint32_t bound[2];
     uint32_t code0;
@@ -474,46 +474,38 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(WPE))) v
             const uint32_t e = striped_elem<IPT>(w, j, lane);
             k[j] = e < len ? keys[pos + e] : U(0);
         }
-        // the key after the chunk, loaded beside the chunk (not after it)
-        const U knext = (tid == 0 && pos + len < end) ? keys[pos + len] : U(0);
         uint32_t cut = end;
         if (pos + len < end) {
-            // code of every element; the element before lane 0 of item j is
-            // lane 63 of item j-1 (or the previous wave's last element)
-            uint32_t c[IPT];
-#pragma unroll
-            for (int j = 0; j < IPT; ++j) {
-                const uint32_t e = striped_elem<IPT>(w, j, lane);
-                c[j] = e < len ? cd(k[j]) : 0xFFFFFFFFu;
-            }
-            if (lane == 63) sm.wlast[w] = c[IPT - 1];
-            if (tid == 0) {
-                sm.cut = 0;
-                sm.code0 = c[0];
-                sm.code_next = cd(knext);
-            }
-            __syncthreads();
-            uint32_t best = 0;
-#pragma unroll
-            for (int j = 0; j < IPT; ++j) {
-                const uint32_t e = striped_elem<IPT>(w, j, lane);
-                uint32_t prev = __shfl_up(c[j], 1, 64);
-                if (j > 0) {
-                    const uint32_t prevj = __shfl(c[j > 0 ? j - 1 : 0], 63, 64);
-                    if (lane == 0) prev = prevj;
-                } else if (lane == 0) {
-                    prev = w > 0 ? sm.wlast[w - 1] : c[0];
+            // Here len == CAP.  Codes do not decrease along the chunk, so its
+            // last code change is where the run of its last code starts.
+            // Wave 0 forms the code of every SPAN-th element, then of each
+            // element of the SPAN-wide gap in which that run starts (two
+            // model rounds in one wave instead of one per key); wave 1
+            // forms the codes of the chunk's first key and of the key after
+            // the chunk.  The keys come from the cache (just loaded).
+            constexpr uint32_t SPAN = CAP / 64;
+            static_assert(CAP % 64 == 0 && SPAN <= 64 && W >= 2, "one wave covers the samples and a gap");
+            if (w == 0) {
+                const uint32_t c = cd(keys[pos + (uint32_t)(lane + 1) * SPAN - 1]);
+                const uint32_t clast = __shfl(c, 63, 64);
+                const uint32_t g = (uint32_t)__builtin_ctzll(ballot64(c == clast));  // lane 63 matches
+                // the run starts in [g*SPAN, (g+1)*SPAN): its last element
+                // is sample g, which has the last code
+                const uint32_t c2 = (uint32_t)lane < SPAN ? cd(keys[pos + g * SPAN + (uint32_t)lane]) : clast;
+                const uint64_t m2 = ballot64((uint32_t)lane < SPAN && c2 == clast);
+                if (lane == 0) {
+                    sm.clast = clast;
+                    sm.cut = g * SPAN + (uint32_t)__builtin_ctzll(m2);
                 }
-                if (e > 0 && e < len && c[j] != prev) best = e;
+            } else if (w == 1 && lane < 2) {
+                const uint32_t c = cd(keys[pos + (lane == 0 ? len : 0u)]);
+                if (lane == 0) sm.code_next = c;
+                else sm.code0 = c;
             }
-            // the chunk ends at a code change if its last element's code
-            // differs from the next key's
-#pragma unroll
-            for (int j = 0; j < IPT; ++j)
-                if (striped_elem<IPT>(w, j, lane) == len - 1 && c[j] != sm.code_next) best = len;
-            if (best) atomicMax(&sm.cut, best);
             __syncthreads();
-            const uint32_t q = sm.cut;
+            // the chunk ends at its own end if its last code differs from
+            // the next key's
+            const uint32_t q = sm.clast != sm.code_next ? len : sm.cut;
             if (q == 0) {
                 // one code spans past the chunk: hand the whole run to the fallback
                 if (tid == 0) {
