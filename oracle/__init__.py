@@ -9,6 +9,8 @@ Contents
   * ``sort`` / ``sortperm`` / ``segsort`` / ``sort_mt`` -- ctypes wrappers of
     the C merge sort in ``sort_oracle.c`` (paper Sec. II-B: ``merge_sort``,
     ``sortperm``; Julia Base order, Sec. II).
+  * ``searchsorted`` -- the C bisection of Sec. II-B (searchsortedfirst /
+    searchsortedlast) under the same order.
   * ``rmi`` -- the learned-CDF model (sampling, fitting, loss, gradients,
     bucket codes) in float64 / IEEE float32 numpy.
   * ``brute`` -- independent brute-force checkers (insertion sort with a
@@ -54,7 +56,9 @@ def _load():
         lib.oracle_sortperm.argtypes = [i32, vp, vp, i64]
         lib.oracle_segsort.argtypes = [i32, vp, vp, i64]
         lib.oracle_sort_mt.argtypes = [i32, vp, i64, i32]
-        for f in (lib.oracle_sort, lib.oracle_sortperm, lib.oracle_segsort, lib.oracle_sort_mt):
+        lib.oracle_searchsorted.argtypes = [i32, vp, i64, vp, i64, i32, vp]
+        for f in (lib.oracle_sort, lib.oracle_sortperm, lib.oracle_segsort, lib.oracle_sort_mt,
+                  lib.oracle_searchsorted):
             f.restype = i32
         _lib = lib
     return _lib
@@ -90,6 +94,20 @@ def sortperm(keys: np.ndarray) -> np.ndarray:
     if _load().oracle_sortperm(_code(k), k.ctypes.data, perm.ctypes.data, k.size) != 0:
         raise RuntimeError("oracle_sortperm failed")
     return perm
+
+
+def searchsorted(v: np.ndarray, x: np.ndarray, last: bool) -> np.ndarray:
+    """Sec. II-B binary search over ``v`` (sorted under the total order),
+    0-based, int64: ``last=False`` gives searchsortedfirst (index of the
+    first element not below x; len(v) if none), ``last=True``
+    searchsortedlast (index of the last element not above x; -1 if none)."""
+    vv = np.ascontiguousarray(v)
+    xx = np.ascontiguousarray(x, dtype=vv.dtype)
+    out = np.empty(xx.size, dtype=np.int64)
+    if _load().oracle_searchsorted(_code(vv), vv.ctypes.data, vv.size, xx.ctypes.data, xx.size,
+                                   1 if last else 0, out.ctypes.data) != 0:
+        raise RuntimeError("oracle_searchsorted failed")
+    return out
 
 
 def segsort(keys: np.ndarray, offsets: np.ndarray) -> np.ndarray:

@@ -95,3 +95,13 @@ def perm_is_stable_sort(keys: np.ndarray, perm: np.ndarray) -> bool:
         if not isless(a, b) and p[i + 1] < p[i]:   # tie: index must rise
             return False
     return True
+
+
+def count_search(v: np.ndarray, x: np.ndarray, last: bool) -> np.ndarray:
+    """searchsortedfirst / searchsortedlast (0-based) by counting, without
+    using that ``v`` is sorted: first = number of elements below x; last =
+    number of elements not above x, minus one."""
+    vs, xs = _py(v), _py(x)
+    if last:
+        return np.asarray([sum(1 for a in vs if not isless(b, a)) - 1 for b in xs], dtype=np.int64)
+    return np.asarray([sum(1 for a in vs if isless(a, b)) for b in xs], dtype=np.int64)

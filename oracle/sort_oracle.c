@@ -195,6 +195,53 @@ int oracle_segsort(int dt, void *keys, const int64_t *off, int64_t nseg) {
     return 0;
 }
 
+/* ---------------------------------------------------------------------
+ * Binary search (Sec. II-B: searchsortedfirst / searchsortedlast, the
+ * lower and upper bound of std::).  v[0..n) is sorted under the order above.
+ * For every x[i]:
+ *   last == 0: out[i] = smallest j in [0, n] with j == n or !less(v[j], x[i])
+ *              (0-based index of the first element not below x[i]; n if none);
+ *   last != 0: out[i] = largest j in [-1, n-1] with j == -1 or
+ *              !less(x[i], v[j]) (0-based index of the last element not above
+ *              x[i]; -1 if none).
+ * "v[j] comes before the answer" holds for a prefix of v, so plain bisection
+ * on that predicate finds the length of the prefix. */
+#define DEFINE_SEARCH(SUF, T, LESS)                                                   \
+    static void search_##SUF(const T *v, int64_t n, const T *x, int64_t m, int last, \
+                             int64_t *out) {                                          \
+        for (int64_t i = 0; i < m; ++i) {                                             \
+            int64_t lo = 0, hi = n; /* prefix length lies in [lo, hi] */              \
+            while (lo < hi) {                                                         \
+                const int64_t mid = lo + (hi - lo) / 2;                               \
+                const int before = last ? !LESS(x[i], v[mid]) : LESS(v[mid], x[i]);   \
+                if (before) lo = mid + 1;                                             \
+                else hi = mid;                                                        \
+            }                                                                         \
+            out[i] = last ? lo - 1 : lo;                                              \
+        }                                                                             \
+    }
+DEFINE_SEARCH(i32, int32_t, LESS_INT)
+DEFINE_SEARCH(i64, int64_t, LESS_INT)
+DEFINE_SEARCH(u32, uint32_t, LESS_INT)
+DEFINE_SEARCH(u64, uint64_t, LESS_INT)
+DEFINE_SEARCH(f32, float, LESS_FLT)
+DEFINE_SEARCH(f64, double, LESS_FLT)
+
+int oracle_searchsorted(int dt, const void *v, int64_t n, const void *x, int64_t m, int last,
+                        int64_t *out) {
+    if (n < 0 || m < 0) return 1;
+    switch (dt) {
+    case OR_I32: search_i32((const int32_t *)v, n, (const int32_t *)x, m, last, out); break;
+    case OR_I64: search_i64((const int64_t *)v, n, (const int64_t *)x, m, last, out); break;
+    case OR_U32: search_u32((const uint32_t *)v, n, (const uint32_t *)x, m, last, out); break;
+    case OR_U64: search_u64((const uint64_t *)v, n, (const uint64_t *)x, m, last, out); break;
+    case OR_F32: search_f32((const float *)v, n, (const float *)x, m, last, out); break;
+    case OR_F64: search_f64((const double *)v, n, (const double *)x, m, last, out); break;
+    default: return 1;
+    }
+    return 0;
+}
+
 /* ---- threaded variant: T chunks sorted in parallel, then pairwise merges ---- */
 typedef struct {
     int dt;

@@ -159,3 +159,46 @@ def test_segsort():
     assert np.array_equal(bits(out2[2500:]), bits(k[2500:]))
     # one segment == sort
     assert np.array_equal(bits(oracle.segsort(k, np.array([0, 3000]))), bits(oracle.sort(k)))
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+def test_searchsorted_matches_counting(dt):
+    """Sec. II-B searchsortedfirst / searchsortedlast: the oracle's bisection
+    against counting with the separately written comparator, on sorted
+    haystacks with repeats and (floats) NaNs, signed zeros and infinities;
+    needles are haystack members, specials and random keys."""
+    rng = np.random.default_rng(zlib.crc32(f"search{dt}".encode()))
+    for n in [0, 1, 2, 9, 64, 301]:
+        v = oracle.sort(random_keys(dt, n, rng, "ties" if n % 2 else "mixed"))
+        x = np.concatenate([v[rng.integers(0, max(n, 1), size=min(n, 40))] if n else v,
+                            special_bits(dt).view(NP[dt]), random_keys(dt, 40, rng, "mixed")])
+        for last in (False, True):
+            got = oracle.searchsorted(v, x, last)
+            assert np.array_equal(got, brute.count_search(v, x, last)), (dt, n, last)
+
+
+def test_searchsorted_closed_forms():
+    """Worked cases: repeats give the ends of their run; below every element
+    gives 0 / -1; above every element gives n / n-1; -0.0 sits before +0.0
+    and NaN after +inf (all NaNs tie)."""
+    v = np.array([1, 3, 3, 3, 7, 9], dtype=np.int64)
+    x = np.array([0, 1, 2, 3, 4, 9, 10], dtype=np.int64)
+    assert oracle.searchsorted(v, x, False).tolist() == [0, 0, 1, 1, 4, 5, 6]
+    assert oracle.searchsorted(v, x, True).tolist() == [-1, 0, 0, 3, 3, 5, 5]
+    f = np.array([-np.inf, -0.0, 0.0, 0.0, np.inf, np.nan, np.nan], dtype=np.float64)
+    q = np.array([-0.0, 0.0, np.nan, np.inf, 5.0], dtype=np.float64)
+    assert oracle.searchsorted(f, q, False).tolist() == [1, 2, 5, 4, 4]
+    assert oracle.searchsorted(f, q, True).tolist() == [1, 3, 6, 4, 3]
+    # the empty haystack
+    e = np.array([], dtype=np.float32)
+    assert oracle.searchsorted(e, np.array([1.0], np.float32), False).tolist() == [0]
+    assert oracle.searchsorted(e, np.array([1.0], np.float32), True).tolist() == [-1]
+
+
+def test_searchsorted_planted_mistake_is_caught():
+    """An off-by-one in the bisection (using <= for the first-index search)
+    differs from counting on a haystack with repeats."""
+    v = np.array([2, 2, 5], dtype=np.int32)
+    x = np.array([2], dtype=np.int32)
+    wrong_first = oracle.searchsorted(v, x, True) + 1   # upper bound instead of lower bound
+    assert not np.array_equal(wrong_first, brute.count_search(v, x, False))
