@@ -11,6 +11,7 @@ Contents
     ``sortperm``; Julia Base order, Sec. II).
   * ``searchsorted`` -- the C bisection of Sec. II-B (searchsortedfirst /
     searchsortedlast) under the same order.
+  * ``accumulate`` -- the C left-to-right prefix sum of Sec. II-B.
   * ``rmi`` -- the learned-CDF model (sampling, fitting, loss, gradients,
     bucket codes) in float64 / IEEE float32 numpy.
   * ``brute`` -- independent brute-force checkers (insertion sort with a
@@ -57,8 +58,9 @@ def _load():
         lib.oracle_segsort.argtypes = [i32, vp, vp, i64]
         lib.oracle_sort_mt.argtypes = [i32, vp, i64, i32]
         lib.oracle_searchsorted.argtypes = [i32, vp, i64, vp, i64, i32, vp]
+        lib.oracle_accumulate.argtypes = [i32, vp, i64, i32, vp]
         for f in (lib.oracle_sort, lib.oracle_sortperm, lib.oracle_segsort, lib.oracle_sort_mt,
-                  lib.oracle_searchsorted):
+                  lib.oracle_searchsorted, lib.oracle_accumulate):
             f.restype = i32
         _lib = lib
     return _lib
@@ -107,6 +109,19 @@ def searchsorted(v: np.ndarray, x: np.ndarray, last: bool) -> np.ndarray:
     if _load().oracle_searchsorted(_code(vv), vv.ctypes.data, vv.size, xx.ctypes.data, xx.size,
                                    1 if last else 0, out.ctypes.data) != 0:
         raise RuntimeError("oracle_searchsorted failed")
+    return out
+
+
+def accumulate(x: np.ndarray, inclusive: bool = True) -> np.ndarray:
+    """Sec. II-B accumulate with +, left to right.  Integer input: same
+    dtype, sums wrap around in its width.  Float input: float64 prefixes of
+    a running sum carried wider than the input (its error is far below one
+    unit in the last place of the input type)."""
+    xx = np.ascontiguousarray(x)
+    out = np.empty(xx.size, dtype=np.float64 if xx.dtype.kind == "f" else xx.dtype)
+    if _load().oracle_accumulate(_code(xx), xx.ctypes.data, xx.size, 1 if inclusive else 0,
+                                 out.ctypes.data) != 0:
+        raise RuntimeError("oracle_accumulate failed")
     return out
 
 

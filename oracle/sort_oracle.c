@@ -242,6 +242,55 @@ int oracle_searchsorted(int dt, const void *v, int64_t n, const void *x, int64_t
     return 0;
 }
 
+/* ---------------------------------------------------------------------
+ * accumulate with + (Sec. II-B prefix scan), left to right:
+ *   inclusive: out[i] = x[0] + ... + x[i];  exclusive: out[0] = 0,
+ *   out[i] = x[0] + ... + x[i-1].
+ * Integer keys: sums wrap around in the key's width (done in the unsigned
+ * type of that width).  Float keys: the running sum is carried in a wider
+ * type (double for float32, long double for float64) and each prefix is
+ * returned as a double, so its error is far below one unit in the last
+ * place of the key type: out is int32/int64/uint32/uint64 or double. */
+#define DEFINE_ACC_INT(SUF, T, UT)                                                  \
+    static void acc_##SUF(const T *x, int64_t n, int inclusive, T *out) {          \
+        UT run = 0;                                                                 \
+        for (int64_t i = 0; i < n; ++i) {                                           \
+            const UT xi = (UT)x[i];                                                 \
+            if (inclusive) run += xi;                                               \
+            out[i] = (T)run;                                                        \
+            if (!inclusive) run += xi;                                              \
+        }                                                                           \
+    }
+DEFINE_ACC_INT(i32, int32_t, uint32_t)
+DEFINE_ACC_INT(i64, int64_t, uint64_t)
+DEFINE_ACC_INT(u32, uint32_t, uint32_t)
+DEFINE_ACC_INT(u64, uint64_t, uint64_t)
+#define DEFINE_ACC_FLT(SUF, T, W)                                                   \
+    static void acc_##SUF(const T *x, int64_t n, int inclusive, double *out) {     \
+        W run = 0;                                                                  \
+        for (int64_t i = 0; i < n; ++i) {                                           \
+            if (inclusive) run += (W)x[i];                                          \
+            out[i] = (double)run;                                                   \
+            if (!inclusive) run += (W)x[i];                                         \
+        }                                                                           \
+    }
+DEFINE_ACC_FLT(f32, float, double)
+DEFINE_ACC_FLT(f64, double, long double)
+
+int oracle_accumulate(int dt, const void *x, int64_t n, int inclusive, void *out) {
+    if (n < 0) return 1;
+    switch (dt) {
+    case OR_I32: acc_i32((const int32_t *)x, n, inclusive, (int32_t *)out); break;
+    case OR_I64: acc_i64((const int64_t *)x, n, inclusive, (int64_t *)out); break;
+    case OR_U32: acc_u32((const uint32_t *)x, n, inclusive, (uint32_t *)out); break;
+    case OR_U64: acc_u64((const uint64_t *)x, n, inclusive, (uint64_t *)out); break;
+    case OR_F32: acc_f32((const float *)x, n, inclusive, (double *)out); break;
+    case OR_F64: acc_f64((const double *)x, n, inclusive, (double *)out); break;
+    default: return 1;
+    }
+    return 0;
+}
+
 /* ---- threaded variant: T chunks sorted in parallel, then pairwise merges ---- */
 typedef struct {
     int dt;

@@ -202,3 +202,59 @@ def test_searchsorted_planted_mistake_is_caught():
     x = np.array([2], dtype=np.int32)
     wrong_first = oracle.searchsorted(v, x, True) + 1   # upper bound instead of lower bound
     assert not np.array_equal(wrong_first, brute.count_search(v, x, False))
+
+
+@pytest.mark.parametrize("dt", ["i32", "i64", "u32", "u64"])
+def test_accumulate_integers_match_big_int_sums(dt):
+    """Sec. II-B accumulate with +: the oracle against Python's unbounded
+    integers reduced modulo 2^width (wrap-around), inclusive and exclusive."""
+    rng = np.random.default_rng(zlib.crc32(f"acc{dt}".encode()))
+    w = 32 if dt.endswith("32") else 64
+    for n in [0, 1, 2, 17, 1000]:
+        x = random_keys(dt, n, rng, "uniform")
+        run, inc, exc = 0, [], []
+        for v in x.tolist():
+            exc.append(run)
+            run += int(v)
+            inc.append(run)
+        for inclusive, ref in ((True, inc), (False, exc)):
+            want = np.array([r % (1 << w) for r in ref], dtype=np.uint64 if w == 64 else np.uint32)
+            got = oracle.accumulate(x, inclusive)
+            assert np.array_equal(got.view(want.dtype), want), (dt, n, inclusive)
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_accumulate_floats_match_exactly_rounded_sums(dt):
+    """Float prefixes against math.fsum (the correctly rounded sum) of each
+    prefix: equal to within a few units of float64 rounding."""
+    import math
+    rng = np.random.default_rng(zlib.crc32(f"accf{dt}".encode()))
+    x = (rng.standard_normal(600) * np.exp(rng.uniform(-20, 20, 600))).astype(NP[dt])
+    inc = oracle.accumulate(x, True)
+    exc = oracle.accumulate(x, False)
+    xs = [float(v) for v in x]
+    for i in range(x.size):
+        s_inc = math.fsum(xs[: i + 1])
+        s_exc = math.fsum(xs[:i])
+        scale = math.fsum(abs(v) for v in xs[: i + 1])
+        assert abs(inc[i] - s_inc) <= 4e-16 * scale + 1e-300
+        assert abs(exc[i] - s_exc) <= 4e-16 * scale + 1e-300
+
+
+def test_accumulate_closed_forms():
+    """All ones: i + 1 inclusive, i exclusive; 0..n-1: the Gauss sums; a
+    planted shift (exclusive read as inclusive) is caught."""
+    n = 5000
+    ones = np.ones(n, dtype=np.int64)
+    assert np.array_equal(oracle.accumulate(ones, True), np.arange(1, n + 1))
+    assert np.array_equal(oracle.accumulate(ones, False), np.arange(n))
+    r = np.arange(n, dtype=np.uint64)
+    i = np.arange(n, dtype=np.uint64)
+    assert np.array_equal(oracle.accumulate(r, True), i * (i + np.uint64(1)) // np.uint64(2))
+    assert np.array_equal(oracle.accumulate(r, False), i * (i - np.uint64(1)) // np.uint64(2) * (i > 0))
+    f = np.full(n, 0.5, dtype=np.float32)
+    assert np.array_equal(oracle.accumulate(f, True), 0.5 * np.arange(1, n + 1))
+    assert not np.array_equal(oracle.accumulate(ones, False), oracle.accumulate(ones, True))
+    # wrap-around: int32 max + 1 wraps to int32 min
+    w = np.array([2**31 - 1, 1], dtype=np.int32)
+    assert oracle.accumulate(w, True).tolist() == [2**31 - 1, -(2**31)]
