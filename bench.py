@@ -16,7 +16,8 @@ roofline: the kernel with the largest share of the learned sort's time,
 cpu_baseline: the oracle's threaded merge sort on a bounded sample of the
   same keys, on this host's cores.
 extras: the other workloads (1M int64 latency, 2**28 float32 sort and
-  sortperm, 2**30 int64 in three distributions, 100,000 segments).
+  sortperm, 2**30 int64 in three distributions, binary search of 2**24
+  int64 keys in 2**28 sorted ones, 100,000 segments).
 """
 from __future__ import annotations
 
@@ -142,6 +143,37 @@ def extras(torch, ak, synth, reps=3):
         out[f"w3_{v}_i64_2^30"] = {"sort_ms": round(ms, 3), "sort_GBps": round(n * 8 / ms / 1e6, 1)}
         del k
         torch.cuda.empty_cache()
+    # binary search (Sec. II-B): 2^24 int64 needles (half haystack members,
+    # half random) in 2^28 sorted uniform int64 keys
+    k = synth.workload3("uniform", n=1 << 28, device="cuda")
+    ak.sort_(k, dtype="i64")
+    g = torch.Generator(device="cuda").manual_seed(28)
+    m = 1 << 24
+    idx = torch.randint(0, k.numel(), (m // 2,), generator=g, device="cuda")
+    q = torch.cat([k[idx], torch.randint(-(1 << 62), 1 << 62, (m - m // 2,), generator=g, device="cuda")])
+    res = torch.empty(m, dtype=torch.int64, device="cuda")
+
+    def t_search(fn):
+        ts = []
+        for r in range(reps + 1):
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            if r:
+                ts.append(a.elapsed_time(b))
+        return min(ts)
+
+    msf = t_search(lambda: ak.searchsortedfirst(k, q, dtype="i64", out=res))
+    msl = t_search(lambda: ak.searchsortedlast(k, q, dtype="i64", out=res))
+    out["search_i64_2^24_in_2^28"] = {"first_ms": round(msf, 3), "last_ms": round(msl, 3),
+                                      "first_Gkeys_s": round(m / msf / 1e6, 2),
+                                      "last_Gkeys_s": round(m / msl / 1e6, 2)}
+    del k, q, res, idx
+    torch.cuda.empty_cache()
     keys, off = synth.workload4(device="cuda")
     work = torch.empty_like(keys)
     ts = []

@@ -215,7 +215,8 @@ ak_status ak_rmi_codes(const void *keys, int64_t n, ak_dtype dtype, const float 
                        int32_t code_bits, uint32_t *codes, ak_stream_t stream);
 
 /* --------------------------------------------------------------- scratch */
-typedef enum { AK_OP_SORT = 0, AK_OP_SORTPERM = 1, AK_OP_SEGMENTED = 2, AK_OP_LEARNED = 3 } ak_op;
+typedef enum { AK_OP_SORT = 0, AK_OP_SORTPERM = 1, AK_OP_SEGMENTED = 2, AK_OP_LEARNED = 3,
+               AK_OP_ACCUMULATE = 4 } ak_op;
 
 /* Bytes of device scratch one call of `op` on n keys needs (Sec. II-B: the
  * temporaries are known ahead of the call from the input size).  The value
@@ -248,6 +249,49 @@ ak_status ak_set_workspace(void *dev_ptr, size_t bytes, ak_stream_t stream);
 
 /* Synchronises the device and frees every workspace and cached graph. */
 ak_status ak_release_workspace(void);
+
+/* ------------------------------------------------------------- prefix sums
+ * Sec. II-B (accumulate with +, inclusive and exclusive; in place or not).
+ * in and out hold n keys of `dtype` (DEVICE pointers); out may equal in
+ * (in place) but must not overlap it otherwise.
+ *   inclusive != 0: out[i] = in[0] + ... + in[i];
+ *   inclusive == 0: out[0] = 0, out[i] = in[0] + ... + in[i-1].
+ * Integer keys: sums wrap around in the key's width (two's complement for
+ * signed keys), so results are exact.  Float keys: sums in the key's own
+ * precision, associated as chunk totals of 4096 keys (16 consecutive keys
+ * per thread, then wave and workgroup trees) plus a scan of those totals:
+ * each result is within d x u x (sum of |in[j]| for j <= i) of the exact
+ * sum, u the unit roundoff and d = 88 + 2 ceil(n / 2^22) the most roundings
+ * a term passes through (first order).  Asynchronous on
+ * `stream`; scratch: one value per 4096 keys (ak_temp_bytes with
+ * AK_OP_ACCUMULATE).  Errors: n < 0, n >= 2^32, NULL pointers with n > 0,
+ * partial overlap -> AK_ERR_INVALID_ARG; unknown dtype ->
+ * AK_ERR_UNSUPPORTED_DTYPE; a bound arena too small -> AK_ERR_NO_MEMORY. */
+ak_status ak_accumulate(const void *in, void *out, int64_t n, ak_dtype dtype, int32_t inclusive,
+                        ak_stream_t stream);
+
+/* ------------------------------------------------------------ binary search
+ * Sec. II-B (searchsortedfirst / searchsortedlast, the lower and upper
+ * bound of a sorted collection).  `sorted` holds n keys (DEVICE pointer)
+ * in ascending order of this library's total order (the order ak_sort
+ * produces: for floats -0.0 before +0.0 and every NaN last, all NaNs
+ * equal); `keys` holds m query keys and `out` m int64 results (DEVICE
+ * pointers; `out` must not overlap either input).  Indices are 0-based:
+ *   ak_searchsortedfirst: out[i] = index of the first element that is not
+ *       below keys[i] (n if none), i.e. keys[i] inserted there keeps the
+ *       order and lands before its equals;
+ *   ak_searchsortedlast:  out[i] = index of the last element that is not
+ *       above keys[i] (-1 if none).
+ * (The paper's 1-based results are out[i] + 1.)  If `sorted` is not in
+ * that order the results are unspecified but in [0, n] / [-1, n-1].
+ * Asynchronous on `stream`; no scratch memory.  Errors: n or m < 0, n >=
+ * 2^40, a NULL pointer with m > 0 (or `sorted` NULL with n > 0), or `out`
+ * overlapping an input -> AK_ERR_INVALID_ARG; unknown dtype ->
+ * AK_ERR_UNSUPPORTED_DTYPE. */
+ak_status ak_searchsortedfirst(const void *sorted, int64_t n, const void *keys, int64_t m, ak_dtype dtype,
+                               int64_t *out, ak_stream_t stream);
+ak_status ak_searchsortedlast(const void *sorted, int64_t n, const void *keys, int64_t m, ak_dtype dtype,
+                              int64_t *out, ak_stream_t stream);
 
 /* ----------------------------------------------------------- diagnostics
  * How the last call on `stream` ordered its keys, if that call was ak_sort

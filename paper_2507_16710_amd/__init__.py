@@ -84,6 +84,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ak_release_workspace": [],
         "ak_set_workspace": [vp, ctypes.c_size_t, vp],
         "ak_sort_route": [vp, vp],
+        "ak_accumulate": [vp, vp, i64, i32, i32, vp],
+        "ak_searchsortedfirst": [vp, i64, vp, i64, i32, vp, vp],
+        "ak_searchsortedlast": [vp, i64, vp, i64, i32, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -272,6 +275,60 @@ def profile_read() -> dict:
         name, cnt, ms = line.split()
         out[name] = (int(cnt), float(ms))
     return out
+
+
+def _search(fn: str, sorted_keys: torch.Tensor, keys: torch.Tensor, dtype: str | None,
+            out: torch.Tensor | None) -> torch.Tensor:
+    _gpu(sorted_keys, "sorted_keys")
+    _gpu(keys, "keys")
+    dt = _dtype(sorted_keys, dtype)
+    if _dtype(keys, dt) != dt or keys.dtype != sorted_keys.dtype:
+        raise TypeError("keys and sorted_keys must have the same dtype")
+    if out is None:
+        out = torch.empty(keys.numel(), dtype=torch.int64, device=keys.device)
+    _gpu(out, "out")
+    if out.dtype != torch.int64 or out.numel() != keys.numel():
+        raise ValueError("out must be an int64 tensor with one element per key")
+    with torch.cuda.device(keys.device):
+        _check(getattr(load_library(), fn)(sorted_keys.data_ptr(), sorted_keys.numel(), keys.data_ptr(),
+                                           keys.numel(), DTYPE_CODE[dt], out.data_ptr(), _stream(keys)), fn)
+    return out
+
+
+def accumulate(x: torch.Tensor, inclusive: bool = True, dtype: str | None = None,
+               out: torch.Tensor | None = None) -> torch.Tensor:
+    """Prefix sums of ``x`` (ak_accumulate): a new tensor, or ``out`` (which
+    may be ``x`` itself for the in-place form)."""
+    _gpu(x, "x")
+    dt = _dtype(x, dtype)
+    if out is None:
+        out = torch.empty_like(x)
+    _gpu(out, "out")
+    if out.dtype != x.dtype or out.numel() != x.numel():
+        raise ValueError("out must match x in dtype and size")
+    with torch.cuda.device(x.device):
+        _check(load_library().ak_accumulate(x.data_ptr(), out.data_ptr(), x.numel(), DTYPE_CODE[dt],
+                                            1 if inclusive else 0, _stream(x)), "ak_accumulate")
+    return out
+
+
+def accumulate_(x: torch.Tensor, inclusive: bool = True, dtype: str | None = None) -> torch.Tensor:
+    """In-place prefix sums of ``x``."""
+    return accumulate(x, inclusive, dtype, out=x)
+
+
+def searchsortedfirst(sorted_keys: torch.Tensor, keys: torch.Tensor, dtype: str | None = None,
+                      out: torch.Tensor | None = None) -> torch.Tensor:
+    """0-based index of the first element of ``sorted_keys`` not below each
+    key (len if none), as int64 (ak_searchsortedfirst)."""
+    return _search("ak_searchsortedfirst", sorted_keys, keys, dtype, out)
+
+
+def searchsortedlast(sorted_keys: torch.Tensor, keys: torch.Tensor, dtype: str | None = None,
+                     out: torch.Tensor | None = None) -> torch.Tensor:
+    """0-based index of the last element of ``sorted_keys`` not above each
+    key (-1 if none), as int64 (ak_searchsortedlast)."""
+    return _search("ak_searchsortedlast", sorted_keys, keys, dtype, out)
 
 
 def sort_route() -> dict:

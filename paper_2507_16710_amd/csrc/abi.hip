@@ -320,6 +320,64 @@ AK_PERM_T(u64, uint64_t, AK_U64)
 AK_PERM_T(f32, float, AK_F32)
 AK_PERM_T(f64, double, AK_F64)
 
+static ak_status search_entry(const void *v, int64_t n, const void *x, int64_t m, ak_dtype dtype, int64_t *out,
+                              ak_stream_t stream, bool last) {
+    g_last_error.clear();
+    if (!dtype_ok(dtype)) {
+        set_error("unknown dtype " + std::to_string(dtype));
+        return AK_ERR_UNSUPPORTED_DTYPE;
+    }
+    if (n < 0 || m < 0) {
+        set_error("n < 0 or m < 0");
+        return AK_ERR_INVALID_ARG;
+    }
+    if (n >= (int64_t(1) << 40)) {
+        set_error("n >= 2^40 is not supported");
+        return AK_ERR_INVALID_ARG;
+    }
+    if (m == 0) return AK_OK;
+    if (!x || !out || (n > 0 && !v)) {
+        set_error("sorted, keys or out is NULL");
+        return AK_ERR_INVALID_ARG;
+    }
+    const size_t kb = (size_t)dtype_bytes(dtype);
+    if (overlaps(out, (size_t)m * 8, x, (size_t)m * kb) || (n > 0 && overlaps(out, (size_t)m * 8, v, (size_t)n * kb))) {
+        set_error("out overlaps sorted or keys");
+        return AK_ERR_INVALID_ARG;
+    }
+    return search_sorted((hipStream_t)stream, dtype, v, n, x, m, last, out);
+}
+
+ak_status ak_accumulate(const void *in, void *out, int64_t n, ak_dtype dtype, int32_t inclusive,
+                        ak_stream_t stream) {
+    g_last_error.clear();
+    ak_status r = check_keys(in, n, dtype);
+    if (r != AK_OK || n == 0) return r;
+    if (!out) {
+        set_error("out is NULL");
+        return AK_ERR_INVALID_ARG;
+    }
+    const size_t bytes = (size_t)n * dtype_bytes(dtype);
+    if (out != in && overlaps(in, bytes, out, bytes)) {
+        set_error("out overlaps in without being equal to it");
+        return AK_ERR_INVALID_ARG;
+    }
+    Workspace *ws = ws_or_error(stream, &r);
+    if (!ws) return r;
+    if ((r = ws_arena_fits(ws, accumulate_temp_bytes(n))) != AK_OK) return r;
+    return accumulate(ws, dtype, in, out, n, inclusive != 0);
+}
+
+ak_status ak_searchsortedfirst(const void *sorted, int64_t n, const void *keys, int64_t m, ak_dtype dtype,
+                               int64_t *out, ak_stream_t stream) {
+    return search_entry(sorted, n, keys, m, dtype, out, stream, false);
+}
+
+ak_status ak_searchsortedlast(const void *sorted, int64_t n, const void *keys, int64_t m, ak_dtype dtype,
+                              int64_t *out, ak_stream_t stream) {
+    return search_entry(sorted, n, keys, m, dtype, out, stream, true);
+}
+
 ak_status ak_segmented_sort(void *keys, const int64_t *offsets, int64_t nseg, ak_dtype dtype, ak_stream_t stream) {
     g_last_error.clear();
     if (!dtype_ok(dtype)) {
@@ -471,6 +529,7 @@ size_t ak_temp_bytes(ak_op op, int64_t n, ak_dtype dtype) {
         ak_learned_cfg c = resolve_cfg(nullptr);
         return learned_temp_bytes(dtype, n, &c);
     }
+    case AK_OP_ACCUMULATE: return accumulate_temp_bytes(n);
     }
     return 0;
 }

@@ -198,6 +198,15 @@ int num_cus();
 // Sorts keys (sort mode, in place) or writes perm (sortperm mode) on
 // `stream`, using run state slot `slot` of the workspace.
 ak_status radix_sort(Workspace *ws, int dtype, void *keys, uint32_t *perm, int64_t n, int slot);
+// Binary search of keys x[0..m) in the sorted v[0..n) on stream s: out[i] =
+// first index not below x[i] (n if none), or with `last` the last index not
+// above x[i] (-1 if none).
+ak_status search_sorted(hipStream_t s, int dtype, const void *v, int64_t n, const void *x, int64_t m, bool last,
+                        int64_t *out);
+// Prefix sums of in[0..n) into out (which may be in), inclusive or
+// exclusive, on the workspace's stream; scratch: accumulate_temp_bytes(n).
+ak_status accumulate(Workspace *ws, int dtype, const void *in, void *out, int64_t n, bool inclusive);
+size_t accumulate_temp_bytes(int64_t n);
 size_t radix_temp_bytes(int dtype, int64_t n, bool perm);
 
 // Prefix-partitioned finish of a key-only radix run (learned.hip): scratch

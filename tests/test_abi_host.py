@@ -89,3 +89,40 @@ def test_temp_bytes_predictable():
 def test_sort_route_argument_error():
     lib = _lib()
     assert lib.ak_sort_route(None, None) == 1  # info NULL, checked before any device call
+
+
+def test_searchsorted_argument_errors():
+    """Bad arguments of ak_searchsortedfirst / ak_searchsortedlast are
+    rejected before any launch; m == 0 launches nothing."""
+    lib = _lib()
+    vp, i64 = ctypes.c_void_p, ctypes.c_int64
+    for name in ("ak_searchsortedfirst", "ak_searchsortedlast"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, i64, vp, i64, ctypes.c_int32, vp, vp]
+        v, x, out = vp(0x1000), vp(0x100000), vp(0x200000)
+        assert f(v, -1, x, 4, 2, out, None) == 1               # n < 0
+        assert f(v, 4, x, -1, 2, out, None) == 1               # m < 0
+        assert f(v, 1 << 40, x, 4, 2, out, None) == 1          # n too large
+        assert f(v, 4, x, 4, 9, out, None) == 2                # unknown dtype
+        assert f(v, 4, None, 4, 2, out, None) == 1             # keys NULL
+        assert f(v, 4, x, 4, 2, None, None) == 1               # out NULL
+        assert f(None, 4, x, 4, 2, out, None) == 1             # sorted NULL with n > 0
+        assert f(v, 4, x, 4, 2, vp(0x100010), None) == 1       # out overlaps keys
+        assert f(v, 4, x, 0, 2, out, None) == 0                # m == 0: nothing to do
+
+
+def test_accumulate_argument_errors():
+    lib = _lib()
+    vp, i64 = ctypes.c_void_p, ctypes.c_int64
+    f = lib.ak_accumulate
+    f.argtypes = [vp, vp, i64, ctypes.c_int32, ctypes.c_int32, vp]
+    a = vp(0x1000)
+    assert f(a, vp(0x100000), -1, 2, 1, None) == 1          # n < 0
+    assert f(a, vp(0x100000), 1 << 32, 2, 1, None) == 1     # too many keys
+    assert f(a, None, 8, 2, 1, None) == 1                   # out NULL
+    assert f(None, vp(0x100000), 8, 2, 1, None) == 1        # in NULL
+    assert f(a, vp(0x1008), 8, 2, 1, None) == 1             # partial overlap
+    assert f(a, vp(0x100000), 8, 9, 1, None) == 2           # unknown dtype
+    assert f(a, a, 0, 2, 1, None) == 0                      # n == 0
+    assert lib.ak_temp_bytes(4, 4096, 2) == 0               # one chunk: no scratch
+    assert lib.ak_temp_bytes(4, 4097, 2) == 256
