@@ -148,6 +148,8 @@ static ak_status accumulate_t(Workspace *ws, const void *in, void *out, int64_t 
     ProfScope ps("accumulate", s);
     if (nchunks > 1) {
         ak_status r;
+        // the chunk totals live in the sortperm index scratch, which no
+        // other call holds across calls (work on the stream runs in order)
         if ((r = ws_reserve(ws, &ws->vals0, &ws->vals0_bytes, (size_t)nchunks * sizeof(T))) != AK_OK) return r;
         part = (T *)ws->vals0;
         hipLaunchKernelGGL((k_scan_reduce<T>), dim3(nchunks), dim3(SCAN_B), 0, s, (const T *)in, (uint64_t)n, part);

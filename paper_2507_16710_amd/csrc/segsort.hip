@@ -418,6 +418,19 @@ __global__ __launch_bounds__(256) void k_xl_hist(const SegArgs *ap, SegState *st
                     if (e0 + it * 256 + tid >= tv) break;
                     const U t = KT<DT>::image(v[it]);
                     const uint64_t act = ballot64(true);
+                    // a wave whose keys are all equal (runs of one repeated
+                    // key) adds its count once per place
+                    const uint64_t t64 = (uint64_t)t;
+                    const uint32_t tl = __builtin_amdgcn_readfirstlane((uint32_t)t64);
+                    const uint32_t th = __builtin_amdgcn_readfirstlane((uint32_t)(t64 >> 32));
+                    if (ballot64((uint32_t)t64 == tl && (uint32_t)(t64 >> 32) == th) == act) {
+                        if (count_below(act) == 0) {
+                            const uint32_t c = (uint32_t)__popcll(act);
+#pragma unroll
+                            for (int p = 0; p < P; ++p) atomicAdd(&s_h[p * RADIX + ((uint32_t)(t64 >> (8 * p)) & (RADIX - 1))], c);
+                        }
+                        continue;
+                    }
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
                         const uint32_t d = (uint32_t)(t >> (8 * p)) & (RADIX - 1);
