@@ -73,3 +73,24 @@ def test_search_large_haystack_sorted_on_gpu(dt):
     last = ak.searchsortedlast(t, tx, dtype=dt).cpu().numpy()
     assert np.array_equal(first, oracle.searchsorted(v, x, False))
     assert np.array_equal(last, oracle.searchsorted(v, x, True))
+
+
+def test_search_bench_configuration_sampled():
+    """The timed configuration: 2^24 int64 keys (half haystack members, half
+    random) in 2^28 sorted uniform int64 keys; a strided sample of 2^16
+    results of each search against the oracle's bisection."""
+    import synth
+    k = synth.workload3("uniform", n=1 << 28, device="cuda")
+    ak.sort_(k, dtype="i64")
+    g = torch.Generator(device="cuda").manual_seed(28)
+    m = 1 << 24
+    idx = torch.randint(0, k.numel(), (m // 2,), generator=g, device="cuda")
+    q = torch.cat([k[idx], torch.randint(-(1 << 62), 1 << 62, (m - m // 2,), generator=g, device="cuda")])
+    print(f"search bench configuration n={k.numel()} m={m}", flush=True)
+    first = ak.searchsortedfirst(k, q, dtype="i64")
+    last = ak.searchsortedlast(k, q, dtype="i64")
+    pick = torch.arange(0, m, m >> 16, device="cuda")
+    v = to_host(k, "i64")
+    x = to_host(q[pick].contiguous(), "i64")
+    assert np.array_equal(first[pick].cpu().numpy(), oracle.searchsorted(v, x, False))
+    assert np.array_equal(last[pick].cpu().numpy(), oracle.searchsorted(v, x, True))
