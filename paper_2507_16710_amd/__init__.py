@@ -29,7 +29,7 @@ for _name, _dt in (("uint32", "u32"), ("uint64", "u64")):
     if hasattr(torch, _name):
         _TORCH_DEFAULT[getattr(torch, _name)] = _dt
 _WIDTH = {"i32": 4, "u32": 4, "f32": 4, "i64": 8, "u64": 8, "f64": 8}
-OPS = {"sort": 0, "sortperm": 1, "segmented": 2, "learned": 3}
+OPS = {"sort": 0, "sortperm": 1, "segmented": 2, "learned": 3, "accumulate": 4}
 
 
 class AKError(RuntimeError):

@@ -116,3 +116,29 @@ def test_arena_prefix_route_exact_size():
             assert np.array_equal(to_host(t, "u64"), oracle.sort(k))
     finally:
         ak.set_workspace(None)
+
+
+def test_arena_accumulate_exact_size():
+    """Prefix sums take their chunk totals from the arena: exactly
+    ak_temp_bytes("accumulate", n) suffices, and one byte less than a
+    256-byte block is refused before any launch."""
+    rng = np.random.default_rng(43)
+    n = 3 * 4096 * 1000 + 11
+    need = ak.temp_bytes("accumulate", n, "i64")
+    assert need >= ((n + 4095) // 4096) * 8
+    x = rng.integers(-(1 << 40), 1 << 40, size=n, dtype=np.int64)
+    arena = torch.empty(need, dtype=torch.uint8, device="cuda")
+    ak.set_workspace(arena)
+    try:
+        print(f"arena accumulate n={n} bytes={need}", flush=True)
+        got = ak.accumulate(to_gpu(x, "i64"), True, dtype="i64")
+        assert np.array_equal(to_host(got, "i64"), oracle.accumulate(x, True))
+    finally:
+        ak.set_workspace(None)
+    small = torch.empty(max(4096, need - 256), dtype=torch.uint8, device="cuda")
+    ak.set_workspace(small)
+    try:
+        with pytest.raises(ak.AKError):
+            ak.accumulate(to_gpu(x, "i64"), True, dtype="i64")
+    finally:
+        ak.set_workspace(None)
