@@ -17,7 +17,8 @@ cpu_baseline: the oracle's threaded merge sort on a bounded sample of the
   same keys, on this host's cores.
 extras: the other workloads (1M int64 latency, 2**28 float32 sort and
   sortperm, 2**30 int64 in three distributions, binary search of 2**24
-  int64 keys in 2**28 sorted ones, 100,000 segments).
+  int64 keys in 2**28 sorted ones, prefix sums of 2**28 int64 keys,
+  100,000 segments).
 """
 from __future__ import annotations
 
@@ -172,7 +173,12 @@ def extras(torch, ak, synth, reps=3):
     out["search_i64_2^24_in_2^28"] = {"first_ms": round(msf, 3), "last_ms": round(msl, 3),
                                       "first_Gkeys_s": round(m / msf / 1e6, 2),
                                       "last_Gkeys_s": round(m / msl / 1e6, 2)}
-    del k, q, res, idx
+    del q, res, idx
+    # prefix sums (Sec. II-B accumulate): 2^28 int64 keys, inclusive
+    acc = torch.empty_like(k)
+    msa = t_search(lambda: ak.accumulate(k, True, dtype="i64", out=acc))
+    out["accumulate_i64_2^28"] = {"ms": round(msa, 3), "GBps_alg": round(2 * k.numel() * 8 / msa / 1e6, 1)}
+    del k, acc
     torch.cuda.empty_cache()
     keys, off = synth.workload4(device="cuda")
     work = torch.empty_like(keys)
