@@ -80,10 +80,13 @@ __global__ __launch_bounds__(SCAN_PART_B) void k_scan_part(T *part, uint32_t nch
     __shared__ T s_w[SCAN_PART_B / 64];
     const uint32_t per = (nchunks + SCAN_PART_B - 1) / SCAN_PART_B;
     const uint32_t lo = min(nchunks, threadIdx.x * per), hi = min(nchunks, lo + per);
+    // unrolled so that several loads of the run are in flight at once
     T s = T(0);
+#pragma unroll 8
     for (uint32_t i = lo; i < hi; ++i) s = s + part[i];
     T total;
     T run = block_excl_scan<SCAN_PART_B>(s, s_w, &total);
+#pragma unroll 8
     for (uint32_t i = lo; i < hi; ++i) {
         const T v = part[i];
         part[i] = run;
