@@ -11,7 +11,11 @@
 namespace ak {
 
 constexpr int SEARCH_B = 256;
-constexpr uint32_t SEARCH_SPLIT = 2048;  // staged elements (16 KB of 64-bit images)
+// staged images per workgroup: 64 KB (8192 64-bit or 16384 32-bit keys).
+// 2^24 int64 keys in 2^28: 2048 staged elements 4.32 ms, 4096 3.91 ms, 8192
+// 3.38 ms, 16384 3.35 ms; two such workgroups fit a CU.
+constexpr size_t SEARCH_STAGE_BYTES = 65536;
+constexpr int SEARCH_WG_PER_CU = 2;
 
 // LAST = false: out[i] = number of elements whose image is below t(x[i])
 // (the first index not below x[i]); LAST: that count for "not above", minus
@@ -23,6 +27,7 @@ __global__ __launch_bounds__(SEARCH_B) void k_search(const typename KT<DT>::U *_
                                                      const typename KT<DT>::U *__restrict__ x, uint64_t m,
                                                      int64_t *__restrict__ out) {
     using U = typename KT<DT>::U;
+    constexpr uint32_t SEARCH_SPLIT = (uint32_t)(SEARCH_STAGE_BYTES / sizeof(U));
     __shared__ U s_sp[SEARCH_SPLIT];
     // staged element j is v[q_j] with q_j = j*n/S (S = min(SPLIT, n)): q_0 = 0
     // and the q_j strictly increase (n/S >= 1)
@@ -59,7 +64,7 @@ static ak_status search_t(hipStream_t s, const void *v, int64_t n, const void *x
                           int64_t *out) {
     using U = typename KT<DT>::U;
     const uint64_t want = ((uint64_t)m + SEARCH_B - 1) / SEARCH_B;
-    const uint32_t grid = (uint32_t)std::min<uint64_t>(want, (uint64_t)num_cus() * 8);
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(want, (uint64_t)num_cus() * SEARCH_WG_PER_CU);
     ProfScope ps("searchsorted", s);
     if (last)
         hipLaunchKernelGGL((k_search<DT, true>), dim3(grid), dim3(SEARCH_B), 0, s, (const U *)v, (uint64_t)n,

@@ -22,7 +22,8 @@ from pools import random_keys, special_bits
 pytestmark = pytest.mark.gpu
 
 DTYPES = ["i32", "i64", "u32", "u64", "f32", "f64"]
-SPLIT = 2048  # haystack elements staged per workgroup
+# haystack elements staged per workgroup: 64 KB of key images
+SPLIT = {"i32": 16384, "u32": 16384, "f32": 16384, "i64": 8192, "u64": 8192, "f64": 8192}
 
 
 def _search_both(v: np.ndarray, x: np.ndarray, dt: str):
@@ -35,7 +36,8 @@ def _search_both(v: np.ndarray, x: np.ndarray, dt: str):
 @pytest.mark.parametrize("dt", DTYPES)
 def test_search_matches_oracle(dt):
     rng = np.random.default_rng(zlib.crc32(f"gpusearch{dt}".encode()))
-    for n in [0, 1, 7, SPLIT - 1, SPLIT, SPLIT + 1, 3 * SPLIT + 5, 100003]:
+    sp = SPLIT[dt]
+    for n in [0, 1, 7, 2049, sp - 1, sp, sp + 1, 3 * sp + 5, 100003]:
         for kind in ("ties", "mixed"):
             v = oracle.sort(random_keys(dt, n, rng, kind))
             members = v[rng.integers(0, n, size=min(n, 5000))] if n else v
