@@ -8,7 +8,11 @@ the HIP library ``paper_2507_16710_amd`` and never imports it.
 Contents
   * ``sort`` / ``sortperm`` / ``segsort`` / ``sort_mt`` -- ctypes wrappers of
     the C merge sort in ``sort_oracle.c`` (paper Sec. II-B: ``merge_sort``,
-    ``sortperm``; Julia Base order, Sec. II).
+    ``sortperm``; Julia Base order, Sec. II), for 16- to 128-bit integer
+    and 32- / 64-bit float keys.
+  * ``sort_by_key`` -- Sec. II-B ``merge_sort_by_key``: keys and payloads
+    gathered through the stable sortperm (``sortperm`` is also the result of
+    ``sortperm_lowmem``).
   * ``searchsorted`` -- the C bisection of Sec. II-B (searchsortedfirst /
     searchsortedlast) under the same order.
   * ``accumulate`` -- the C left-to-right prefix sum of Sec. II-B.
@@ -31,7 +35,12 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 # dtype codes of the oracle's C API (its own numbering)
 _DT = {np.dtype(np.int32): 1, np.dtype(np.int64): 2, np.dtype(np.uint32): 3,
-       np.dtype(np.uint64): 4, np.dtype(np.float32): 5, np.dtype(np.float64): 6}
+       np.dtype(np.uint64): 4, np.dtype(np.float32): 5, np.dtype(np.float64): 6,
+       np.dtype(np.int16): 7, np.dtype(np.uint16): 8}
+# 128-bit integer keys (numpy has no such dtype): (n, 2) uint64 arrays, the
+# low word in column 0, the high word in column 1 (the little-endian layout
+# of one 16-byte integer per row), named by an explicit dtype
+WIDE = {"i128": 9, "u128": 10}
 
 
 def build(force: bool = False) -> str:
@@ -66,17 +75,28 @@ def _load():
     return _lib
 
 
-def _code(a: np.ndarray) -> int:
+def _code(a: np.ndarray, dtype: str | None = None) -> int:
+    if dtype is not None:
+        if dtype not in WIDE:
+            raise TypeError(f"oracle: unknown explicit dtype {dtype}")
+        if a.dtype != np.uint64 or a.ndim != 2 or a.shape[1] != 2:
+            raise TypeError("oracle: 128-bit keys are (n, 2) uint64 arrays (low word first)")
+        return WIDE[dtype]
     try:
         return _DT[a.dtype]
     except KeyError:
         raise TypeError(f"oracle: unsupported dtype {a.dtype}") from None
 
 
-def sort(keys: np.ndarray) -> np.ndarray:
-    """Stable ascending sort under the total order; returns a new array."""
+def _count(a: np.ndarray, dtype: str | None) -> int:
+    return a.shape[0] if dtype in WIDE else a.size
+
+
+def sort(keys: np.ndarray, dtype: str | None = None) -> np.ndarray:
+    """Stable ascending sort under the total order; returns a new array.
+    ``dtype`` names 128-bit keys ("i128" / "u128", (n, 2) uint64 rows)."""
     out = np.ascontiguousarray(keys).copy()
-    if _load().oracle_sort(_code(out), out.ctypes.data, out.size) != 0:
+    if _load().oracle_sort(_code(out, dtype), out.ctypes.data, _count(out, dtype)) != 0:
         raise RuntimeError("oracle_sort failed")
     return out
 
@@ -89,13 +109,28 @@ def sort_mt(keys: np.ndarray, threads: int) -> np.ndarray:
     return out
 
 
-def sortperm(keys: np.ndarray) -> np.ndarray:
-    """0-based stable index permutation (uint32) that sorts ``keys``."""
+def sortperm(keys: np.ndarray, dtype: str | None = None) -> np.ndarray:
+    """0-based stable index permutation (uint32) that sorts ``keys``.  This
+    is also the result of the paper's sortperm_lowmem (Sec. II-B), which
+    computes the same permutation with less temporary memory."""
     k = np.ascontiguousarray(keys)
-    perm = np.empty(k.size, dtype=np.uint32)
-    if _load().oracle_sortperm(_code(k), k.ctypes.data, perm.ctypes.data, k.size) != 0:
+    n = _count(k, dtype)
+    perm = np.empty(n, dtype=np.uint32)
+    if _load().oracle_sortperm(_code(k, dtype), k.ctypes.data, perm.ctypes.data, n) != 0:
         raise RuntimeError("oracle_sortperm failed")
     return perm
+
+
+def sort_by_key(keys: np.ndarray, vals: np.ndarray, dtype: str | None = None):
+    """Sec. II-B merge_sort_by_key: keys and their payloads (a separate
+    array, one row per key) reordered together by the stable sort of the
+    keys, i.e. both gathered through the stable sortperm of the keys.
+    Returns (sorted keys, payloads in the same order)."""
+    perm = sortperm(keys, dtype).astype(np.int64)
+    v = np.ascontiguousarray(vals)
+    if v.shape[0] != perm.size:
+        raise ValueError("one payload row per key")
+    return np.ascontiguousarray(keys)[perm].copy(), v[perm].copy()
 
 
 def searchsorted(v: np.ndarray, x: np.ndarray, last: bool) -> np.ndarray:

@@ -28,16 +28,30 @@ def isless(a, b) -> bool:
     return a < b
 
 
-def _py(keys: np.ndarray) -> list:
+def wide_ints(rows: np.ndarray, signed: bool) -> list:
+    """(n, 2) uint64 rows (low word, high word) -> Python ints: the value
+    lo + hi * 2**64, minus 2**128 when signed and the top bit is set."""
+    out = []
+    for lo, hi in rows.tolist():
+        v = int(lo) + (int(hi) << 64)
+        if signed and v >= 1 << 127:
+            v -= 1 << 128
+        out.append(v)
+    return out
+
+
+def _py(keys: np.ndarray, dtype: str | None = None) -> list:
+    if dtype in ("i128", "u128"):
+        return wide_ints(keys, dtype == "i128")
     if keys.dtype.kind == "f":
         return [float(v) for v in keys.tolist()]
     return [int(v) for v in keys.tolist()]
 
 
-def insertion_sortperm(keys: np.ndarray) -> np.ndarray:
+def insertion_sortperm(keys: np.ndarray, dtype: str | None = None) -> np.ndarray:
     """Stable insertion sort of indices: an element moves left only past
     strictly greater keys, so equal keys keep their input order."""
-    vals = _py(keys)
+    vals = _py(keys, dtype)
     idx = list(range(len(vals)))
     for i in range(1, len(idx)):
         cur = idx[i]
@@ -49,8 +63,8 @@ def insertion_sortperm(keys: np.ndarray) -> np.ndarray:
     return np.asarray(idx, dtype=np.uint32)
 
 
-def insertion_sort(keys: np.ndarray) -> np.ndarray:
-    return keys[insertion_sortperm(keys)]
+def insertion_sort(keys: np.ndarray, dtype: str | None = None) -> np.ndarray:
+    return keys[insertion_sortperm(keys, dtype)]
 
 
 # ---------------------------------------------------------------- invariants

@@ -336,6 +336,26 @@ def leaf_grad_scaled(model: Model, sorted_keys: np.ndarray) -> np.ndarray:
     return out
 
 
+def fallback_stats(keys: np.ndarray, code: np.ndarray, cap: int):
+    """Runs of one code longer than ``cap`` keys: once the keys are ordered
+    by code, all keys of one code form one run, and a run that does not fit
+    one on-chip chunk of ``cap`` keys goes to the radix fallback.  Returns
+    (number of such runs, keys in them, keys in those of them that hold one
+    repeated bit pattern)."""
+    code = np.asarray(code, np.int64)
+    vals, counts = np.unique(code, return_counts=True)
+    long_codes = vals[counts > cap]
+    runs = int(long_codes.size)
+    fkeys = int(counts[counts > cap].sum())
+    kb = np.ascontiguousarray(keys).view(np.uint32 if keys.dtype.itemsize == 4 else np.uint64)
+    ckeys = 0
+    for c in long_codes.tolist():
+        sel = kb[code == c]
+        if np.all(sel == sel[0]):
+            ckeys += int(sel.size)
+    return runs, fkeys, ckeys
+
+
 def bucket_stats(code: np.ndarray, cb: int, buckets: int = 4096):
     """Histogram of the top log2(buckets) bits of every code, and
     max bucket / ideal bucket."""

@@ -12,6 +12,10 @@
  *   - sortperm:  the index permutation that would sort the collection;
  *                ties (keys equal under the order) keep increasing index;
  *   - segmented: every segment [off[s], off[s+1]) sorted on its own.
+ * Key types: 16-, 32-, 64- and 128-bit signed and unsigned integers (the
+ * paper's benchmarks sort Int16 up to Int128, Sec. IV-C) and 32- and
+ * 64-bit floats.  (sort_by_key, sortperm_lowmem: in oracle/__init__.py,
+ * from sortperm.)
  * The order follows the Julia Base conventions the library adopts
  * (Sec. II, multiple dispatch onto the Base function names): integers by
  * value; floats by `isless`: -Inf < ... < -0.0 < +0.0 < ... < +Inf < NaN,
@@ -31,7 +35,13 @@
 #include <string.h>
 
 /* dtype codes used by the oracle's own API (plain ints, not shared) */
-enum { OR_I32 = 1, OR_I64 = 2, OR_U32 = 3, OR_U64 = 4, OR_F32 = 5, OR_F64 = 6 };
+enum { OR_I32 = 1, OR_I64 = 2, OR_U32 = 3, OR_U64 = 4, OR_F32 = 5, OR_F64 = 6,
+       OR_I16 = 7, OR_U16 = 8, OR_I128 = 9, OR_U128 = 10 };
+
+/* Julia's Int128 / UInt128 (Sec. IV: the sorting benchmarks run Int16 to
+ * Int128 keys): the compiler's 128-bit integers, compared by value. */
+typedef __int128 i128_t;
+typedef unsigned __int128 u128_t;
 
 /* ---- semantic "less than" for every supported key type ---- */
 #define LESS_INT(a, b) ((a) < (b))
@@ -71,6 +81,10 @@ DEFINE_SORT(u32, uint32_t, LESS_INT)
 DEFINE_SORT(u64, uint64_t, LESS_INT)
 DEFINE_SORT(f32, float, LESS_FLT)
 DEFINE_SORT(f64, double, LESS_FLT)
+DEFINE_SORT(i16, int16_t, LESS_INT)
+DEFINE_SORT(u16, uint16_t, LESS_INT)
+DEFINE_SORT(i128, i128_t, LESS_INT)
+DEFINE_SORT(u128, u128_t, LESS_INT)
 
 /* ---- pairs (key, index) for sortperm: compare keys only ---- */
 #define DEFINE_PAIR(SUF, T, LESS)                                           \
@@ -111,11 +125,17 @@ DEFINE_PAIR(u32, uint32_t, LESS_INT)
 DEFINE_PAIR(u64, uint64_t, LESS_INT)
 DEFINE_PAIR(f32, float, LESS_FLT)
 DEFINE_PAIR(f64, double, LESS_FLT)
+DEFINE_PAIR(i16, int16_t, LESS_INT)
+DEFINE_PAIR(u16, uint16_t, LESS_INT)
+DEFINE_PAIR(i128, i128_t, LESS_INT)
+DEFINE_PAIR(u128, u128_t, LESS_INT)
 
 static size_t dtype_size(int dt) {
     switch (dt) {
     case OR_I32: case OR_U32: case OR_F32: return 4;
     case OR_I64: case OR_U64: case OR_F64: return 8;
+    case OR_I16: case OR_U16: return 2;
+    case OR_I128: case OR_U128: return 16;
     default: return 0;
     }
 }
@@ -129,6 +149,10 @@ static void sort_run(int dt, void *a, void *tmp, int64_t n) {
     case OR_U64: msort_u64((uint64_t *)a, (uint64_t *)tmp, n); break;
     case OR_F32: msort_f32((float *)a, (float *)tmp, n); break;
     case OR_F64: msort_f64((double *)a, (double *)tmp, n); break;
+    case OR_I16: msort_i16((int16_t *)a, (int16_t *)tmp, n); break;
+    case OR_U16: msort_u16((uint16_t *)a, (uint16_t *)tmp, n); break;
+    case OR_I128: msort_i128((i128_t *)a, (i128_t *)tmp, n); break;
+    case OR_U128: msort_u128((u128_t *)a, (u128_t *)tmp, n); break;
     }
 }
 
@@ -141,6 +165,10 @@ static void merge_runs(int dt, const void *src, int64_t mid, int64_t n, void *ds
     case OR_U64: merge_u64((const uint64_t *)src, mid, n, (uint64_t *)dst); break;
     case OR_F32: merge_f32((const float *)src, mid, n, (float *)dst); break;
     case OR_F64: merge_f64((const double *)src, mid, n, (double *)dst); break;
+    case OR_I16: merge_i16((const int16_t *)src, mid, n, (int16_t *)dst); break;
+    case OR_U16: merge_u16((const uint16_t *)src, mid, n, (uint16_t *)dst); break;
+    case OR_I128: merge_i128((const i128_t *)src, mid, n, (i128_t *)dst); break;
+    case OR_U128: merge_u128((const u128_t *)src, mid, n, (u128_t *)dst); break;
     }
 }
 
@@ -172,6 +200,10 @@ int oracle_sortperm(int dt, const void *keys, uint32_t *perm, int64_t n) {
     case OR_U64: return sortperm_u64((const uint64_t *)keys, perm, n);
     case OR_F32: return sortperm_f32((const float *)keys, perm, n);
     case OR_F64: return sortperm_f64((const double *)keys, perm, n);
+    case OR_I16: return sortperm_i16((const int16_t *)keys, perm, n);
+    case OR_U16: return sortperm_u16((const uint16_t *)keys, perm, n);
+    case OR_I128: return sortperm_i128((const i128_t *)keys, perm, n);
+    case OR_U128: return sortperm_u128((const u128_t *)keys, perm, n);
     }
     return -1;
 }

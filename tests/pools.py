@@ -54,3 +54,60 @@ def random_keys(dt: str, n: int, rng: np.random.Generator, kind: str = "mixed") 
 
 def bits(a: np.ndarray) -> np.ndarray:
     return a.view(np.uint32 if a.itemsize == 4 else np.uint64)
+
+
+# 16-bit and 128-bit integer keys (the paper's benchmarks sort Int16 up to
+# Int128).  128-bit keys are (n, 2) uint64 rows, low word first.
+WIDE_DTYPES = ["i16", "u16", "i128", "u128"]
+NP16 = {"i16": np.int16, "u16": np.uint16}
+M64 = (1 << 64) - 1
+
+
+def rows128(vals) -> np.ndarray:
+    """Python ints (two's complement for negatives) -> (n, 2) uint64 rows."""
+    out = np.empty((len(vals), 2), dtype=np.uint64)
+    for i, v in enumerate(vals):
+        v &= (1 << 128) - 1
+        out[i, 0], out[i, 1] = v & M64, v >> 64
+    return out
+
+
+def special128(signed: bool) -> np.ndarray:
+    top = 1 << 127
+    vals = [0, 1, 2, M64, 1 << 64, (1 << 64) + 1, (5 << 64) | (1 << 63), (5 << 64) | ((1 << 63) - 1),
+            (1 << 127) - 1, (1 << 127) - 2]
+    if signed:
+        vals += [-1, -2, -top, -top + 1, -(1 << 64), -(1 << 64) - 1, -(5 << 64)]
+    else:
+        vals += [(1 << 128) - 1, (1 << 128) - 2, top, top + 1, top | M64]
+    return rows128(vals)
+
+
+def wide_keys(dt: str, n: int, rng: np.random.Generator, kind: str = "mixed") -> np.ndarray:
+    """n keys of a 16- or 128-bit dtype: 'uniform' random bits, 'ties' (few
+    distinct values) or 'mixed' (random bits, specials, repeats)."""
+    if dt in NP16:
+        T = NP16[dt]
+        rand = rng.integers(0, 1 << 16, size=n, dtype=np.uint32).astype(np.uint16).view(T)
+        info = np.iinfo(T)
+        sp = np.array([v for v in [info.min, info.min + 1, -1, 0, 1, 255, 256, info.max - 1, info.max]
+                       if info.min <= v <= info.max], dtype=T)
+    else:
+        rand = rng.integers(0, 1 << 64, size=(n, 2), dtype=np.uint64)
+        sp = special128(dt == "i128")
+    if kind == "uniform":
+        return rand
+    few = rand[: max(1, min(n, 5))]
+    pool = np.concatenate([sp, few])
+    if kind == "ties":
+        return pool[rng.integers(0, pool.shape[0], size=n)]
+    pick = rng.integers(0, 3, size=n)
+    out = rand.copy()
+    out[pick == 1] = sp[rng.integers(0, sp.shape[0], size=int((pick == 1).sum()))]
+    out[pick == 2] = few[rng.integers(0, few.shape[0], size=int((pick == 2).sum()))]
+    return out
+
+
+def wide_arg(dt: str):
+    """The oracle's explicit dtype argument (128-bit keys only)."""
+    return dt if dt in ("i128", "u128") else None

@@ -258,3 +258,96 @@ def test_accumulate_closed_forms():
     # wrap-around: int32 max + 1 wraps to int32 min
     w = np.array([2**31 - 1, 1], dtype=np.int32)
     assert oracle.accumulate(w, True).tolist() == [2**31 - 1, -(2**31)]
+
+
+# ------------------------------------------- 16- and 128-bit integer keys
+from pools import WIDE_DTYPES, rows128, special128, wide_arg, wide_keys  # noqa: E402
+
+
+@pytest.mark.parametrize("dt", WIDE_DTYPES)
+@pytest.mark.parametrize("kind", ["mixed", "ties", "uniform"])
+def test_wide_sortperm_matches_insertion_sort(dt, kind):
+    rng = np.random.default_rng(zlib.crc32(f"{dt}{kind}".encode()))
+    wd = wide_arg(dt)
+    for n in [0, 1, 2, 3, 7, 64, 301]:
+        k = wide_keys(dt, n, rng, kind)
+        perm = oracle.sortperm(k, wd)
+        assert np.array_equal(perm, brute.insertion_sortperm(k, wd)), (dt, kind, n)
+        assert np.array_equal(oracle.sort(k, wd), k[perm.astype(np.int64)]), (dt, kind, n)
+
+
+@pytest.mark.parametrize("dt", ["i16", "i128", "u128"])
+def test_wide_exhaustive_permutations_small(dt):
+    rng = np.random.default_rng(13)
+    wd = wide_arg(dt)
+    sp = wide_keys(dt, 40, rng, "ties")
+    base = sp[rng.choice(sp.shape[0], size=6, replace=True)]
+    expect = None
+    for p in itertools.permutations(range(6)):
+        k = base[list(p)]
+        perm = oracle.sortperm(k, wd)
+        assert np.array_equal(perm, brute.insertion_sortperm(k, wd))
+        out = oracle.sort(k, wd)
+        expect = out if expect is None else expect
+        assert np.array_equal(out, expect)
+
+
+def test_int128_closed_forms():
+    """Distinct values in a known order sort back to it; sortperm of a
+    permutation is its inverse; the high word decides before the low word
+    and the sign bit makes negatives smallest (signed) or largest
+    (unsigned)."""
+    rng = np.random.default_rng(17)
+    ordered = [-(1 << 127), -(1 << 64) - 1, -(1 << 64), -2, -1, 0, 1, M := (1 << 64) - 1, M + 1,
+               (5 << 64) | ((1 << 63) - 1), (5 << 64) | (1 << 63), (1 << 127) - 1]
+    rows = rows128(ordered)
+    for _ in range(10):
+        p = rng.permutation(len(ordered))
+        assert np.array_equal(oracle.sort(rows[p], "i128"), rows)
+        assert np.array_equal(oracle.sortperm(rows[p], "i128"), np.argsort(p).astype(np.uint32))
+    # unsigned: the same bit patterns, negatives now above every positive
+    uo = sorted(v & ((1 << 128) - 1) for v in ordered)
+    assert np.array_equal(oracle.sort(rows[rng.permutation(len(ordered))], "u128"), rows128(uo))
+    # a larger closed form: a shuffled progression with a step above 2**64
+    vals = [i * ((1 << 64) + 3) - (1 << 100) for i in range(3000)]
+    r = rows128(vals)
+    p = rng.permutation(len(vals))
+    assert np.array_equal(oracle.sort(r[p], "i128"), r)
+
+
+def test_int16_closed_forms():
+    rng = np.random.default_rng(19)
+    a = np.arange(-32768, 32768, dtype=np.int64).astype(np.int16)
+    p = rng.permutation(a.size)
+    assert np.array_equal(oracle.sort(a[p]), a)
+    assert np.array_equal(oracle.sortperm(a[p]), np.argsort(p).astype(np.uint32))
+    u = a.view(np.uint16)                        # every 16-bit pattern once
+    assert np.array_equal(oracle.sort(u[p]), np.arange(65536).astype(np.uint16))
+
+
+def test_int128_planted_mistake_is_caught():
+    """Sorting 128-bit keys by their low word only (a plausible slip) or as
+    unsigned when they are signed differs from the oracle on the pools."""
+    rng = np.random.default_rng(23)
+    k = wide_keys("i128", 200, rng, "mixed")
+    ref = oracle.sort(k, "i128")
+    assert not np.array_equal(k[np.argsort(k[:, 0], kind="stable")], ref)
+    assert not np.array_equal(oracle.sort(k, "u128"), ref)
+
+
+def test_sort_by_key_definition():
+    """Payloads travel with their keys: an index payload reproduces the
+    stable sortperm; equal keys keep their payloads in input order; keys and
+    payloads match the brute-force permutation for every key dtype."""
+    rng = np.random.default_rng(29)
+    for dt in DTYPES + WIDE_DTYPES:
+        wd = wide_arg(dt)
+        k = wide_keys(dt, 500, rng, "ties") if dt in WIDE_DTYPES else random_keys(dt, 500, rng, "ties")
+        idx = np.arange(500, dtype=np.uint32)
+        ks, vs = oracle.sort_by_key(k, idx, wd)
+        bp = brute.insertion_sortperm(k, wd)
+        assert np.array_equal(vs, bp), dt
+        assert np.array_equal(ks.view(np.uint8), k[bp.astype(np.int64)].view(np.uint8)), dt
+        pay = rng.integers(0, 1 << 64, size=500, dtype=np.uint64)
+        _, vs2 = oracle.sort_by_key(k, pay, wd)
+        assert np.array_equal(vs2, pay[bp.astype(np.int64)]), dt

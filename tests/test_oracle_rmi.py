@@ -199,3 +199,141 @@ def test_codes_monotone_and_balanced(dist):
         un = rmi.untrained(srt[0], srt[-1], 256)
         _, imb_u = rmi.bucket_stats(rmi.codes(un, srt, cb), cb, 256)
         assert imb_u > 10 * imb
+
+
+def test_code_bits_closed_forms():
+    """cb = clamp(ceil(log2 n) - 7, 12, 24): about 128 keys per code, at
+    least 2**12 codes (the 4096 buckets) and at most 2**24 (three 8-bit
+    passes)."""
+    cases = {1: 12, 2: 12, 1 << 12: 12, 1 << 19: 12, (1 << 19) + 1: 13, 1 << 20: 13,
+             (1 << 20) + 1: 14, 10 ** 6: 13, 1 << 30: 23, (1 << 30) + 1: 24, 1 << 31: 24, 1 << 40: 24}
+    for n, cb in cases.items():
+        assert rmi.code_bits(n) == cb, n
+    # between the clamps, n / 2**cb lies in (64, 128]
+    for n in [(1 << 19) + 1, 3 << 20, 10 ** 7, 2_147_000_000, 1 << 31]:
+        cb = rmi.code_bits(n)
+        assert 64 < n / 2 ** cb <= 128, n
+
+
+def test_sample_count_closed_forms():
+    """m = floor(frac * n), at least min(n, 4096); the library takes frac as
+    a float32, so the pins use that value too."""
+    f = float(np.float32(0.01))
+    assert f == 10737418 / 2 ** 30                       # float32(0.01), exactly
+    # floor(n * 10737418 / 2**30): just below n/100 when n/100 is whole
+    assert rmi.sample_count(10 ** 6, f) == 9_999
+    assert rmi.sample_count(10 ** 6, 0.01) == 10_000
+    assert rmi.sample_count(100_000, f) == 4096          # the 4096 floor
+    assert rmi.sample_count(1000, f) == 1000             # never more than n
+    assert rmi.sample_count(4096 * 300, f) == 12_287
+    for n in [5000, 409_601, 10 ** 7 + 3, 123_456_789]:
+        assert rmi.sample_count(n, f) == min(n, max(n * 10737418 // 2 ** 30, 4096)), n
+    # float32(0.01) = 10737418 * 2**-30, so at n = 2**31 the product is the
+    # integer 2 * 10737418 exactly
+    assert rmi.sample_count(1 << 31, f) == 21_474_836
+    assert rmi.sample_count(1 << 31, 0.01) == 21_474_836
+    assert rmi.sample_count(1 << 20, 1.0) == 1 << 20
+
+
+def _round_f32(q):
+    """Fraction -> nearest float32 (ties to even), written from the IEEE
+    definition with exact rational arithmetic (subnormals included)."""
+    from fractions import Fraction
+    if q == 0:
+        return 0.0
+    a = abs(q)
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    if Fraction(2) ** e > a:
+        e -= 1
+    e = max(e, -126)
+    quantum = Fraction(2) ** (e - 23)
+    mq = a / quantum
+    fl = mq.numerator // mq.denominator
+    rem = mq - fl
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and fl % 2 == 1):
+        fl += 1
+    return float((1 if q > 0 else -1) * fl * quantum)
+
+
+def _code_exact(model, key: int, cb: int):
+    """The model code of one uint64 key, every float32 operation rounded once
+    from its exact rational value, in the order the definition states."""
+    import struct
+    from fractions import Fraction as Fr
+
+    def rnd(q):  # exact result of one operation -> float32, as a Fraction
+        return Fr(_round_f32(q))
+
+    def f(v):
+        return Fr(float(v))
+    x = rnd(Fr(key))                                          # float(t), t = key
+    rbits = struct.unpack("<I", struct.pack("<f", float(x)))[0]
+    r = rnd(Fr(rbits))
+    u = rnd(r - f(model.rc))
+    p = rnd(rnd(f(model.ra) * u) + f(model.rb))
+    p = min(max(p, Fr(0)), Fr(model.L - 1))
+    leaf = int(p)
+    dx = rnd(x - f(model.x0[leaf]))
+    F = rnd(rnd(f(model.a[leaf]) * dx) + f(model.b[leaf]))
+    hi = f(model.lo[leaf + 1]) if leaf + 1 < model.L else Fr(1)
+    F = min(max(F, f(model.lo[leaf])), hi)
+    c = rnd(F * Fr(2 ** cb))
+    return leaf, float(F), min(int(c), (1 << cb) - 1)
+
+
+def test_codes_match_exact_rational_evaluation():
+    """route / cdf / codes use float32 arithmetic with one rounding per
+    operation and no fused multiply-add: each key's leaf, CDF value and code
+    equal an exact-rational evaluation rounded after every operation (a
+    float64 evaluation rounded once at the end, or a fused product, would
+    differ on some of these keys)."""
+    rng = np.random.default_rng(21)
+    sample = np.sort(np.concatenate([
+        np.floor(rng.lognormal(30, 3, size=3000)).clip(0, 2.0 ** 63).astype(np.uint64),
+        rng.integers(0, 1 << 64, size=1000, dtype=np.uint64),
+        rng.integers(1, 10_000_000, size=1000).astype(np.uint64)]))
+    mdl = rmi.fit(sample, 64)
+    keys = np.concatenate([
+        rng.choice(sample, 600),
+        np.floor(rng.lognormal(30, 3, size=600)).clip(0, 2.0 ** 63).astype(np.uint64),
+        rng.integers(0, 1 << 64, size=300, dtype=np.uint64),
+        np.array([0, 1, (1 << 24) + 1, (1 << 63) + (1 << 39), (1 << 64) - 1], dtype=np.uint64)])
+    # keys whose leaf a float64 evaluation of the route would change (within
+    # one float32 rounding of a leaf boundary), found by scanning keys spread
+    # evenly over the log-like feature
+    scan = np.exp2(rng.uniform(0, 63.9, size=1 << 21)).astype(np.uint64)
+    _, rs = rmi.features(scan)
+    p64 = np.float64(mdl.ra) * (rs.astype(np.float64) - np.float64(mdl.rc)) + np.float64(mdl.rb)
+    near = scan[np.minimum(np.maximum(p64, 0), mdl.L - 1).astype(np.int64) != rmi.route(mdl, rs)]
+    assert near.size > 0
+    keys = np.concatenate([keys, near[:200]])
+    _, r = rmi.features(keys)
+    leaf = rmi.route(mdl, r)
+    F = rmi.cdf(mdl, keys)
+    for cb in (12, 24):
+        c = rmi.codes(mdl, keys, cb)
+        for i, kv in enumerate(keys.tolist()):
+            lx, fx, cx = _code_exact(mdl, kv, cb)
+            assert (leaf[i], float(F[i]), int(c[i])) == (lx, fx, cx), (kv, cb)
+
+
+def test_bucket_and_fallback_stats_closed_forms():
+    cb = 14
+    # every code once: each of the 4096 buckets holds 2**(cb-12) codes
+    code = np.arange(1 << cb, dtype=np.uint32)
+    h, imb = rmi.bucket_stats(code, cb, 4096)
+    assert np.all(h == 4) and imb == 1.0
+    # all keys in code 0: one bucket holds everything
+    h, imb = rmi.bucket_stats(np.zeros(1000, np.uint32), cb, 4096)
+    assert h[0] == 1000 and h[1:].sum() == 0 and imb == 4096.0
+    # runs: code 3 x5 (one repeated key), code 7 x4 (two keys), code 9 x2
+    code = np.array([3, 3, 3, 3, 3, 7, 7, 7, 7, 9, 9], np.uint32)
+    keys = np.array([5, 5, 5, 5, 5, 8, 8, 8, 9, 10, 11], np.uint64)
+    assert rmi.fallback_stats(keys, code, 2) == (2, 9, 5)
+    assert rmi.fallback_stats(keys, code, 4) == (1, 5, 5)
+    assert rmi.fallback_stats(keys, code, 5) == (0, 0, 0)
+    # the runs are found by code, not by position
+    p = np.random.default_rng(0).permutation(code.size)
+    assert rmi.fallback_stats(keys[p], code[p], 2) == (2, 9, 5)
+    f = np.array([-0.0, 0.0, -0.0], np.float32)     # distinct bit patterns: not constant
+    assert rmi.fallback_stats(f, np.zeros(3, np.uint32), 2) == (1, 3, 0)
