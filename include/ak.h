@@ -30,7 +30,10 @@
  *     to the stream with ak_set_workspace().  Calls issued concurrently on
  *     DIFFERENT streams use different workspaces; calls on one stream are
  *     serialised by it.
- *   - Key counts are limited to n < 2^32 (indices and counters are 32-bit).
+ *   - Key counts are limited to n <= AK_MAX_KEYS = 2^31: indices, counters
+ *     and grid-stride loops are 32-bit, and 2^31 keeps every index plus one
+ *     stride below 2^32.  Larger n is rejected with AK_ERR_INVALID_ARG
+ *     before anything is launched.
  */
 #ifndef AK_H
 #define AK_H
@@ -43,6 +46,9 @@ extern "C" {
 #endif
 
 typedef void *ak_stream_t;
+
+/* Largest key count any call accepts (see the conventions above). */
+#define AK_MAX_KEYS ((int64_t)1 << 31)
 
 typedef enum {
     AK_OK = 0,
@@ -66,8 +72,8 @@ typedef enum {
  * prefix is finished on chip (same result; ak_sort_route tells which).
  * Scratch: two key buffers, per-tile look-back words, and above 2^22 keys
  * the prefix finish's run lists (ak_temp_bytes gives the total).
- * Errors: AK_ERR_INVALID_ARG for n < 0, n >= 2^32 or keys == NULL with
- * n > 0; AK_ERR_UNSUPPORTED_DTYPE for an unknown dtype. */
+ * Errors: AK_ERR_INVALID_ARG for n < 0, n > AK_MAX_KEYS or keys == NULL
+ * with n > 0; AK_ERR_UNSUPPORTED_DTYPE for an unknown dtype. */
 ak_status ak_sort(void *keys, int64_t n, ak_dtype dtype, ak_stream_t stream);
 
 /* -------------------------------------------------------------- sortperm
@@ -98,7 +104,7 @@ ak_status ak_sortperm_f64(const double *keys, uint32_t *perm, int64_t n, ak_stre
  * The launch sequence is captured once per (dtype, nseg, total) into a HIP
  * graph and replayed; pointers travel through a device-side argument block.
  * Errors: nseg < 0, NULL pointers, offsets[nseg] < offsets[0] or a total of
- * 2^32 keys or more -> AK_ERR_INVALID_ARG.  Offsets that decrease inside
+ * more than AK_MAX_KEYS keys -> AK_ERR_INVALID_ARG.  Offsets that decrease inside
  * the array are detected on the device and reported by
  * ak_check_device_error(). */
 ak_status ak_segmented_sort(void *keys, const int64_t *offsets, int64_t nseg, ak_dtype dtype,
@@ -264,7 +270,7 @@ ak_status ak_release_workspace(void);
  * sum, u the unit roundoff and d = 88 + 2 ceil(n / 2^22) the most roundings
  * a term passes through (first order).  Asynchronous on
  * `stream`; scratch: one value per 4096 keys (ak_temp_bytes with
- * AK_OP_ACCUMULATE).  Errors: n < 0, n >= 2^32, NULL pointers with n > 0,
+ * AK_OP_ACCUMULATE).  Errors: n < 0, n > AK_MAX_KEYS, NULL pointers with n > 0,
  * partial overlap -> AK_ERR_INVALID_ARG; unknown dtype ->
  * AK_ERR_UNSUPPORTED_DTYPE; a bound arena too small -> AK_ERR_NO_MEMORY. */
 ak_status ak_accumulate(const void *in, void *out, int64_t n, ak_dtype dtype, int32_t inclusive,

@@ -227,8 +227,8 @@ static ak_status check_keys(const void *keys, int64_t n, int dtype) {
         set_error("n < 0");
         return AK_ERR_INVALID_ARG;
     }
-    if (n >= (int64_t(1) << 32)) {
-        set_error("n >= 2^32 keys is not supported");
+    if (n > AK_MAX_KEYS) {
+        set_error("n > 2^31 keys is not supported (indices and grid-stride loops are 32-bit)");
         return AK_ERR_INVALID_ARG;
     }
     if (n > 0 && !keys) {
@@ -470,7 +470,7 @@ ak_status ak_learned_sample(const void *keys, int64_t n, ak_dtype dtype, uint64_
     g_last_error.clear();
     ak_status r = check_keys(keys, n, dtype);
     if (r != AK_OK) return r;
-    if (m < 0 || (m > 0 && (!out || n == 0)) || m >= (int64_t(1) << 32)) {
+    if (m < 0 || (m > 0 && (!out || n == 0)) || m > AK_MAX_KEYS) {
         set_error("bad sample size or output");
         return AK_ERR_INVALID_ARG;
     }

@@ -954,8 +954,8 @@ ak_status segmented_sort(Workspace *ws, int dt, void *keys, const int64_t *offse
     AK_HIP(hipMemcpyAsync(&ends[1], offsets + nseg, 8, hipMemcpyDeviceToHost, s));
     AK_HIP(hipStreamSynchronize(s));
     const int64_t n = ends[1] - ends[0];
-    if (ends[0] < 0 || n < 0 || n >= (int64_t(1) << 32)) {
-        set_error("offsets[nseg] - offsets[0] must be in [0, 2^32) and offsets[0] >= 0");
+    if (ends[0] < 0 || n < 0 || n > AK_MAX_KEYS) {
+        set_error("offsets[nseg] - offsets[0] must be in [0, 2^31] and offsets[0] >= 0");
         return AK_ERR_INVALID_ARG;
     }
     if (n == 0) return AK_OK;

@@ -68,6 +68,26 @@ def fingerprint(t: torch.Tensor) -> tuple:
     return int(t.numel()), int(z.sum()), int((z * z).sum())
 
 
+def _mix(t: torch.Tensor) -> torch.Tensor:
+    b = t.view(torch.int32).to(torch.int64) if t.element_size() == 4 else t.view(torch.int64)
+    z = b * -7046029254386353131
+    z = (z ^ ((z >> 31) & ((1 << 33) - 1))) * -4658895280553007687
+    return z ^ ((z >> 29) & ((1 << 35) - 1))
+
+
+def segment_fingerprints(t: torch.Tensor, seg_id: torch.Tensor, nseg: int) -> torch.Tensor:
+    """Per-segment multiset fingerprints: for every segment the count and
+    two wrapping sums of a 64-bit mix of its elements' bits ([nseg, 3]).  A
+    key that moved into another segment changes two rows."""
+    z = _mix(t)
+    cols = []
+    for v in (torch.ones_like(z), z, z * z):
+        c = torch.zeros(nseg, dtype=torch.int64, device=t.device)
+        c.index_add_(0, seg_id, v)
+        cols.append(c)
+    return torch.stack(cols, dim=1)
+
+
 def check_perm_sorts_stably(keys: torch.Tensor, perm: torch.Tensor, dt: str) -> None:
     n = keys.numel()
     p = perm.to(torch.int64) & 0xFFFFFFFF

@@ -42,6 +42,16 @@ def test_argument_errors_without_device_work():
     assert lib.ak_sort(fake, 10, 0, None) == 2
     assert lib.ak_sort(fake, 10, 7, None) == 2
     assert lib.ak_sort(fake, 1 << 32, 2, None) == 1
+    # the accepted range ends at 2^31 keys (32-bit indices and grid-stride
+    # loops): one key more is refused before any launch by every entry point
+    over = (1 << 31) + 1
+    assert lib.ak_sort(fake, over, 2, None) == 1
+    assert lib.ak_sortperm(fake, vp(0x10000000000), over, 2, None) == 1
+    assert lib.ak_sort_learned(fake, over, 4, None, None, None) == 1
+    assert lib.ak_rmi_codes(fake, over, 4, fake, 12, vp(0x10000000000), None) == 1
+    assert lib.ak_learned_sample(fake, over, 4, 0, 16, vp(0x10000000000), None) == 1
+    assert lib.ak_learned_sample(fake, 100, 4, 0, over, vp(0x10000000000), None) == 1
+    assert b"2^31" in lib.ak_last_error() or b"sample" in lib.ak_last_error()
     assert lib.ak_sort(fake, 0, 2, None) == 0           # n == 0: no launch
     assert lib.ak_sortperm(fake, None, 10, 2, None) == 1
     assert lib.ak_sortperm(fake, fake, 10, 2, None) == 1  # keys and perm overlap
@@ -119,6 +129,7 @@ def test_accumulate_argument_errors():
     a = vp(0x1000)
     assert f(a, vp(0x100000), -1, 2, 1, None) == 1          # n < 0
     assert f(a, vp(0x100000), 1 << 32, 2, 1, None) == 1     # too many keys
+    assert f(a, vp(0x100000000), (1 << 31) + 1, 2, 1, None) == 1   # one above AK_MAX_KEYS
     assert f(a, None, 8, 2, 1, None) == 1                   # out NULL
     assert f(None, vp(0x100000), 8, 2, 1, None) == 1        # in NULL
     assert f(a, vp(0x1008), 8, 2, 1, None) == 1             # partial overlap

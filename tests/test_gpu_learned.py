@@ -189,3 +189,65 @@ def test_workload5_full_size():
     assert is_sorted(lrn, "u64") and fingerprint(lrn) == fp
     del plain
     rank_checks(keys, lrn, "u64", samples=8)
+
+
+# the library's default sample fraction, 0.01 as a float32
+F32_FRAC = float(np.float32(0.01))
+
+
+def _oracle_stats(k: np.ndarray, dt: str, seed: int = 0, leaves: int = 4096, iters: int = 3,
+                  cap: int = 2048) -> dict:
+    """What ak_sort_learned must report, computed on the host: the sample the
+    sort draws (positions from the oracle's SplitMix64), sorted by the
+    oracle; the model fitted to it by ak_rmi_fit (the sort's own fit, whose
+    parameters the oracle cannot reproduce bit for bit from float64); then
+    the oracle's float32 codes of every key under that model, the top-bucket
+    histogram and the runs of one code longer than one on-chip chunk."""
+    n = k.size
+    m = rmi.sample_count(n, F32_FRAC)
+    srt = oracle.sort(k[rmi.sample_positions(seed, n, m)])
+    model = ak.rmi_fit(to_gpu(srt, dt), leaves=leaves, iters=iters, dtype=dt)
+    mdl = rmi.Model.from_array(model.cpu().numpy())
+    cb = rmi.code_bits(n)
+    code = rmi.codes(mdl, k, cb)
+    h, imb = rmi.bucket_stats(code, cb, 4096)
+    runs, fkeys, ckeys = rmi.fallback_stats(k, code, cap)
+    return {"n": n, "sample_size": m, "leaves": leaves, "code_bits": cb, "max_bucket": int(h.max()),
+            "imbalance": float(imb), "fallback_runs": runs, "fallback_keys": fkeys, "constant_keys": ckeys}
+
+
+@pytest.mark.parametrize("dist,n", [("mixture", 4096 * 512), ("uniform", 1 << 21), ("lognormal", 1_500_007),
+                                    ("zipf", 1_000_003), ("f32", 1 << 20)])
+def test_learned_stats_match_oracle(dist, n):
+    """The statistics the sort reports (largest of the 4096 buckets, its
+    ratio to the ideal bucket, fallback runs and their keys, runs of one
+    repeated key) equal the oracle's counts for the model the sort fits,
+    exactly; and the sort still equals the oracle's."""
+    k, dt = _keys(dist, n, seed=4)
+    ref = _oracle_stats(k, dt)
+    t = to_gpu(k, dt)
+    _, st = ak.sort_learned_(t, dtype=dt, stats=True)
+    print(dist, st, ref)
+    for f in ("n", "sample_size", "leaves", "code_bits", "max_bucket", "fallback_runs", "fallback_keys",
+              "constant_keys"):
+        assert st[f] == ref[f], (f, st[f], ref[f])
+    assert st["imbalance"] == pytest.approx(ref["imbalance"], rel=1e-12)
+    # every key outside the fallback runs went through an on-chip chunk of at
+    # most 2048 keys
+    assert st["chunks"] >= -(-(n - st["fallback_keys"]) // 2048)
+    assert np.array_equal(bits(to_host(t, dt)), bits(oracle.sort(k)))
+
+
+def test_uniform_bucket_balance_statistical_pin():
+    """Uniform uint64 keys: a bucket's share of the sample has relative
+    standard error sqrt(B/m) (B = 4096 buckets, m samples), so the largest
+    of 4096 buckets stays below 1 + 4.5 sqrt(B/m) of the ideal."""
+    n = 1 << 22
+    k, dt = _keys("uniform", n, seed=9)
+    t = to_gpu(k, dt)
+    _, st = ak.sort_learned_(t, dtype=dt, stats=True)
+    m = st["sample_size"]
+    assert m == rmi.sample_count(n, F32_FRAC)
+    assert st["imbalance"] <= 1 + 4.5 * np.sqrt(4096 / m), st
+    assert st["fallback_keys"] == 0
+    assert np.array_equal(to_host(t, dt), oracle.sort(k))

@@ -8,7 +8,7 @@ import torch
 import oracle
 import paper_2507_16710_amd as ak
 import synth
-from gpucheck import fingerprint, signed_order_key, to_gpu, to_host
+from gpucheck import fingerprint, segment_fingerprints, signed_order_key, to_gpu, to_host
 from pools import DTYPES, bits, random_keys
 
 pytestmark = pytest.mark.gpu
@@ -87,11 +87,16 @@ def test_workload4_full_size():
     keys, off = synth.workload4(device="cuda")
     orig = keys.clone()
     fp = fingerprint(keys)
+    nseg = off.numel() - 1
+    seg_id = torch.repeat_interleave(torch.arange(nseg, device="cuda"), off[1:] - off[:-1])
+    seg_fp = segment_fingerprints(keys, seg_id, nseg)
     ak.segmented_sort_(keys, off, dtype="u32")
     torch.cuda.synchronize()
     assert fingerprint(keys) == fp
+    # every segment keeps its own multiset (a key moved between segments
+    # would change two rows)
+    assert torch.equal(segment_fingerprints(keys, seg_id, nseg), seg_fp)
     k = signed_order_key(keys, "u32")
-    seg_id = torch.repeat_interleave(torch.arange(off.numel() - 1, device="cuda"), off[1:] - off[:-1])
     same = seg_id[1:] == seg_id[:-1]
     assert bool((k[1:][same] >= k[:-1][same]).all())
     offh = off.cpu().numpy()
