@@ -76,6 +76,22 @@ typedef enum {
  * with n > 0; AK_ERR_UNSUPPORTED_DTYPE for an unknown dtype. */
 ak_status ak_sort(void *keys, int64_t n, ak_dtype dtype, ak_stream_t stream);
 
+/* -------------------------------------------------------- sort, no alloc
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as ak_sort (bit for bit, same kernels), with all scratch in one
+ * static device array per GPU (about 37 MiB, held by every GPU the library
+ * runs on until the process ends) instead of a workspace.  The call
+ * allocates nothing, captures no graph and never synchronises; the array's
+ * run state is zeroed on the first call on a device, on that call's stream.
+ * Limit: n * key bytes <= AK_NOALLOC_MAX_KEY_BYTES (2^21 64-bit or 2^22
+ * 32-bit keys); larger n -> AK_ERR_INVALID_ARG before any launch.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (concurrent streams, or threads) race and must be ordered by the
+ * caller.  Errors otherwise as ak_sort. */
+#define AK_NOALLOC_MAX_KEY_BYTES ((int64_t)1 << 24)
+ak_status ak_sort_noalloc(void *keys, int64_t n, ak_dtype dtype, ak_stream_t stream);
+
 /* -------------------------------------------------------------- sortperm
  * Sec. II-B (sortperm): writes perm[0..n) (0-based uint32 indices) such that
  * keys[perm[0]] <= keys[perm[1]] <= ... under the order above, equal keys in

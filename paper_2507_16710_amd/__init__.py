@@ -73,6 +73,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     vp, i64, i32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64
     sig = {
         "ak_sort": [vp, i64, i32, vp],
+        "ak_sort_noalloc": [vp, i64, i32, vp],
         "ak_sortperm": [vp, vp, i64, i32, vp],
         "ak_segmented_sort": [vp, vp, i64, i32, vp],
         "ak_check_device_error": [vp],

@@ -35,8 +35,6 @@ int num_cus() {
 static std::mutex g_ws_mu;
 static std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
 
-constexpr int RUN_SLOTS = 4;
-
 // Zeroes n 8-byte words at p, then `tail` (< 8) more bytes after them.
 __global__ void k_zero_u64(uint64_t *p, size_t n, uint32_t tail) {
     const size_t t0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
@@ -66,7 +64,7 @@ Workspace *get_workspace(hipStream_t stream) {
     Workspace *ws = new Workspace();
     ws->device = dev;
     ws->stream = stream;
-    const size_t state_bytes = sizeof(RunState) * RUN_SLOTS + 256;
+    const size_t state_bytes = RUN_STATE_BYTES;
     if (hipMalloc((void **)&ws->state, state_bytes) != hipSuccess) {
         set_error("hipMalloc(run state) failed");
         delete ws;
@@ -124,6 +122,10 @@ ak_status ws_reserve(Workspace *ws, void **p, size_t *have, size_t need) {
 
 ak_status ws_reserve_lookback(Workspace *ws, size_t need) {
     if (need <= ws->lookback_bytes) return AK_OK;
+    if (ws->fixed_lookback) {
+        set_error("look-back region too small for this run");
+        return AK_ERR_INTERNAL;
+    }
     void *p = ws->lookback;
     size_t have = ws->lookback_bytes;
     ak_status r = ws_reserve(ws, &p, &have, need);
@@ -186,7 +188,8 @@ void ws_begin_call(Workspace *ws) {
     ws->last_route = 0;
     if (!ws->arena) return;
     ws->arena_used = 0;
-    ws->keys0_bytes = ws->keys1_bytes = ws->vals0_bytes = ws->lookback_bytes = 0;
+    ws->keys0_bytes = ws->keys1_bytes = ws->vals0_bytes = 0;
+    if (!ws->fixed_lookback) ws->lookback_bytes = 0;
     ws->misc_bytes = ws->misc2_bytes = 0;
     for (size_t &b : ws->aux_bytes) b = 0;
 }

@@ -175,6 +175,13 @@ struct Workspace {
     // route of this call's radix run on state slot 0: 0 none or on chip,
     // 1 digit passes only, 2 passes with the prefix-partitioned finish
     int last_route = 0;
+    // fixed_lookback: the look-back region is a fixed piece of memory that
+    // outlives calls (sized for the largest run the owner admits), so an
+    // arena carve never replaces or refills it; no_graph: launch directly,
+    // never capture or instantiate a graph (both for the entry point that
+    // allocates nothing)
+    bool fixed_lookback = false;
+    bool no_graph = false;
 };
 
 Workspace *get_workspace(hipStream_t stream);
@@ -193,6 +200,10 @@ ak_status ws_next_epoch(Workspace *ws, uint32_t *epoch);
 bool stream_capturing(hipStream_t s);
 
 int num_cus();
+// Run-state slots per workspace (several radix runs of one call) and the
+// bytes of the state block: the slots, then the device epoch counter.
+constexpr int RUN_SLOTS = 4;
+constexpr size_t RUN_STATE_BYTES = sizeof(RunState) * RUN_SLOTS + 256;
 
 // --------------------------------------------------------- radix driver
 // Sorts keys (sort mode, in place) or writes perm (sortperm mode) on

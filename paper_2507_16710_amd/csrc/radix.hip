@@ -1002,7 +1002,8 @@ static ak_status radix_sort_t(Workspace *ws, void *keys, uint32_t *perm, int64_t
             return r;
         return prefix_finish(ws, DT, keys, n64, st);
     }
-    if (n64 > GRAPH_MAX || stream_capturing(s)) return launch_run<DT, false>(s, ws, st, keys, perm, n, nplaces, nullptr, 0);
+    if (n64 > GRAPH_MAX || ws->no_graph || stream_capturing(s))
+        return launch_run<DT, false>(s, ws, st, keys, perm, n, nplaces, nullptr, 0);
 
     std::lock_guard<std::mutex> lk(g_graph_mu);
     GraphCache &c = g_graphs[ws];

@@ -70,6 +70,15 @@ def test_argument_errors_without_device_work():
     assert lib.ak_set_workspace(vp(0x1008), 1 << 20, None) == 1   # not 256-byte aligned
     assert lib.ak_set_workspace(vp(0x1000), 1024, None) == 1      # smaller than 4096 bytes
     assert lib.ak_status_string(3) == b"out of device memory"
+    # the entry point that allocates nothing: its size limit (16 MiB of keys)
+    # and argument errors are refused before any device call
+    assert lib.ak_sort_noalloc(fake, (1 << 21) + 1, 2, None) == 1
+    assert lib.ak_sort_noalloc(fake, (1 << 22) + 1, 5, None) == 1
+    assert b"at most" in lib.ak_last_error()
+    assert lib.ak_sort_noalloc(None, 10, 2, None) == 1
+    assert lib.ak_sort_noalloc(fake, -1, 2, None) == 1
+    assert lib.ak_sort_noalloc(fake, 10, 0, None) == 2
+    assert lib.ak_sort_noalloc(fake, 0, 2, None) == 0
 
 
 def test_temp_bytes_predictable():
