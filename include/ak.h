@@ -165,6 +165,7 @@ ak_status ak_check_device_error(ak_stream_t stream);
  *   train_iters  Newton iterations of every leaf fit (default 3)
  *   untrained    1: skip training and use equal-width key ranges (the method
  *                without the model, for comparisons)
+ *   model        AK_MODEL_RMI (default) or AK_MODEL_MLP (below)
  * `stats` may be NULL; if not, the call synchronises `stream` and fills it.
  * Integer and float dtypes are supported. */
 typedef struct {
@@ -174,8 +175,18 @@ typedef struct {
     int32_t train_iters;
     uint64_t seed;
     int32_t untrained;
-    int32_t reserved[3];
+    int32_t model;             /* AK_MODEL_RMI (0) or AK_MODEL_MLP (1)        */
+    int32_t reserved[2];
 } ak_learned_cfg;
+
+/* The CDF model of ak_sort_learned (cfg->model):
+ *   AK_MODEL_RMI  the two-level model above (train_iters: Newton steps of
+ *                 every leaf fit, default 3);
+ *   AK_MODEL_MLP  a 1-64-64-1 network (ak_mlp_fit; train_iters: Adam
+ *                 steps, default 300), tabulated into the same leaf table,
+ *                 so the per-key work of the sort is unchanged. */
+#define AK_MODEL_RMI 0
+#define AK_MODEL_MLP 1
 
 typedef struct {
     int64_t n;
@@ -235,6 +246,42 @@ ak_status ak_rmi_leaf_grad(const void *sorted_sample, int64_t m, ak_dtype dtype,
 /* codes[i] = model code of keys[i] (see above), 1 <= code_bits <= 24. */
 ak_status ak_rmi_codes(const void *keys, int64_t n, ak_dtype dtype, const float *model,
                        int32_t code_bits, uint32_t *codes, ak_stream_t stream);
+
+/* -------------------------------------------------------- MLP CDF model
+ * The alternative model of the learned sort: f(u) = w3 . tanh(W2 tanh(W1 u
+ * + c1) + c2) + c3 with 64 + 64 hidden units, W1 = sp(A1), W2 = sp(A2), w3 =
+ * sp(a3), sp = softplus (positive weights and increasing tanh: f increases
+ * with u, a monotone CDF estimate).  u in [0, 1] is the root's log-like key
+ * feature r (above) over the sample's range: u = (r - r_first) * s, s =
+ * 1 / (r_last - r_first) in float32.  Parameters are AK_MLP_PARAMS raw
+ * floats: A1[64] | c1[64] | A2[64][64] (row = layer-2 unit) | c2[64] |
+ * a3[64] | c3.  Loss: mean over K points of (f(u_k) - y_k)^2. */
+#define AK_MLP_PARAMS 4353
+
+/* Forward and backward over K training points (DEVICE arrays u, y of K
+ * floats) at `params` (DEVICE, AK_MLP_PARAMS floats): out (DEVICE,
+ * AK_MLP_PARAMS + 1 floats) gets dL/dparams (raw parameters) and then L.
+ * Float32 sums in a fixed order (64 points per workgroup, then the
+ * workgroups in order).  Errors: K < 1, K > 2^20 or a NULL pointer ->
+ * AK_ERR_INVALID_ARG. */
+ak_status ak_mlp_loss_grad(const float *u, const float *y, int64_t K, const float *params, float *out,
+                           ak_stream_t stream);
+
+/* Fits the network to an ascending sample of m keys and tabulates it:
+ *   training points: K = min(m, 4096) at ranks j_k = floor((2k+1) m / 2K),
+ *   y_k = j_k / m; start at the quantiles of the u_k (layer-1 unit i steps
+ *   at u[floor((2i+1) K / 128)]); `iters` Adam steps (lr 0.01, betas 0.9 /
+ *   0.999, eps 1e-8);
+ *   table: `model` (DEVICE, ak_rmi_model_floats(leaves) floats) gets the
+ *   root of ak_rmi_fit (equal feature widths) and leaf records that
+ *   interpolate f linearly in x = float32(image) between the knots u_i =
+ *   i / leaves, lower clamps lo_i = running maximum of clamp(f(u_i), 0, 1),
+ *   lo_0 = 0; `params` (DEVICE, AK_MLP_PARAMS floats, or NULL) gets the
+ *   trained raw parameters.
+ * Errors: m < 1, leaves not a power of two in [1, 16384], iters < 0 or
+ * > 100000 -> AK_ERR_INVALID_ARG. */
+ak_status ak_mlp_fit(const void *sorted_sample, int64_t m, ak_dtype dtype, int32_t iters, int32_t leaves,
+                     float *params, float *model, ak_stream_t stream);
 
 /* --------------------------------------------------------------- scratch */
 typedef enum { AK_OP_SORT = 0, AK_OP_SORTPERM = 1, AK_OP_SEGMENTED = 2, AK_OP_LEARNED = 3,

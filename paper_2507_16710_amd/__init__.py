@@ -44,7 +44,7 @@ class LearnedCfg(ctypes.Structure):
     _fields_ = [("leaves", ctypes.c_int32), ("buckets_log2", ctypes.c_int32),
                 ("sample_frac", ctypes.c_float), ("train_iters", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("untrained", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("model", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class LearnedStats(ctypes.Structure):
@@ -82,6 +82,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ak_rmi_fit": [vp, i64, i32, i32, i32, vp, vp],
         "ak_rmi_leaf_grad": [vp, i64, i32, vp, vp, vp],
         "ak_rmi_codes": [vp, i64, i32, vp, i32, vp, vp],
+        "ak_mlp_loss_grad": [vp, vp, i64, vp, vp, vp],
+        "ak_mlp_fit": [vp, i64, i32, i32, i32, vp, vp, vp],
         "ak_release_workspace": [],
         "ak_set_workspace": [vp, ctypes.c_size_t, vp],
         "ak_sort_route": [vp, vp],
@@ -191,10 +193,16 @@ def check_device_error(device=None) -> None:
                "ak_check_device_error")
 
 
-def make_cfg(leaves=0, buckets_log2=0, sample_frac=0.0, train_iters=0, seed=0, untrained=False) -> LearnedCfg:
+MODELS = {"rmi": 0, "mlp": 1}
+MLP_PARAMS = 4353
+
+
+def make_cfg(leaves=0, buckets_log2=0, sample_frac=0.0, train_iters=0, seed=0, untrained=False,
+             model: str = "rmi") -> LearnedCfg:
     c = LearnedCfg()
     c.leaves, c.buckets_log2, c.sample_frac = leaves, buckets_log2, sample_frac
     c.train_iters, c.seed, c.untrained = train_iters, seed, int(bool(untrained))
+    c.model = MODELS[model]
     return c
 
 
@@ -259,6 +267,36 @@ def rmi_codes(keys: torch.Tensor, model: torch.Tensor, code_bits: int, dtype: st
         _check(load_library().ak_rmi_codes(keys.data_ptr(), keys.numel(), DTYPE_CODE[dt], model.data_ptr(),
                                            code_bits, out.data_ptr(), _stream(keys)), "ak_rmi_codes")
     return out
+
+
+def mlp_loss_grad(u: torch.Tensor, y: torch.Tensor, params: torch.Tensor) -> torch.Tensor:
+    """Loss and gradient of the MLP CDF model over the points (u, y) at the
+    raw parameters: returns MLP_PARAMS gradient entries, then the loss."""
+    for t, name in ((u, "u"), (y, "y"), (params, "params")):
+        _gpu(t, name)
+        if t.dtype != torch.float32:
+            raise TypeError(f"{name} must be float32")
+    if u.numel() != y.numel() or params.numel() != MLP_PARAMS:
+        raise ValueError("u and y need one value per point; params needs MLP_PARAMS values")
+    out = torch.empty(MLP_PARAMS + 1, dtype=torch.float32, device=u.device)
+    with torch.cuda.device(u.device):
+        _check(load_library().ak_mlp_loss_grad(u.data_ptr(), y.data_ptr(), u.numel(), params.data_ptr(),
+                                               out.data_ptr(), _stream(u)), "ak_mlp_loss_grad")
+    return out
+
+
+def mlp_fit(sorted_sample: torch.Tensor, iters: int = 300, leaves: int = 4096, dtype: str | None = None):
+    """Trains the MLP CDF model on an ascending sample and tabulates it:
+    returns (raw parameters, model table in the two-level format)."""
+    _gpu(sorted_sample, "sorted_sample")
+    dt = _dtype(sorted_sample, dtype)
+    params = torch.zeros(MLP_PARAMS, dtype=torch.float32, device=sorted_sample.device)
+    model = torch.zeros(model_floats(leaves), dtype=torch.float32, device=sorted_sample.device)
+    with torch.cuda.device(sorted_sample.device):
+        _check(load_library().ak_mlp_fit(sorted_sample.data_ptr(), sorted_sample.numel(), DTYPE_CODE[dt], iters,
+                                         leaves, params.data_ptr(), model.data_ptr(), _stream(sorted_sample)),
+               "ak_mlp_fit")
+    return params, model
 
 
 def profile_enable(on: bool = True) -> None:

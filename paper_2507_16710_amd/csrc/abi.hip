@@ -442,7 +442,7 @@ static ak_learned_cfg resolve_cfg(const ak_learned_cfg *cfg) {
     if (c.leaves <= 0) c.leaves = 4096;
     if (c.buckets_log2 <= 0) c.buckets_log2 = 12;
     if (!(c.sample_frac > 0.f)) c.sample_frac = 0.01f;
-    if (c.train_iters <= 0) c.train_iters = 3;
+    if (c.train_iters <= 0) c.train_iters = c.model == AK_MODEL_MLP ? 300 : 3;
     return c;
 }
 
@@ -452,8 +452,11 @@ ak_status ak_sort_learned(void *keys, int64_t n, ak_dtype dtype, const ak_learne
     ak_status r = check_keys(keys, n, dtype);
     if (r != AK_OK) return r;
     ak_learned_cfg c = resolve_cfg(cfg);
-    if (c.leaves > 65536 || (c.leaves & (c.leaves - 1)) || c.buckets_log2 > 14 || c.sample_frac > 1.f) {
-        set_error("bad learned config (leaves: power of two <= 65536; buckets_log2 <= 14; sample_frac <= 1)");
+    if (c.leaves > 65536 || (c.leaves & (c.leaves - 1)) || c.buckets_log2 > 14 || c.sample_frac > 1.f ||
+        (c.model != AK_MODEL_RMI && c.model != AK_MODEL_MLP) ||
+        (c.model == AK_MODEL_MLP && (c.leaves > 16384 || c.train_iters > 100000))) {
+        set_error("bad learned config (leaves: power of two <= 65536, <= 16384 for the MLP; buckets_log2 <= 14; "
+                  "sample_frac <= 1; model RMI or MLP; MLP steps <= 100000)");
         return AK_ERR_INVALID_ARG;
     }
     if (n == 0) {
@@ -464,6 +467,34 @@ ak_status ak_sort_learned(void *keys, int64_t n, ak_dtype dtype, const ak_learne
     if (!ws) return r;
     if ((r = ws_arena_fits(ws, learned_temp_bytes(dtype, n, &c))) != AK_OK) return r;
     return learned_sort(ws, dtype, keys, n, &c, stats);
+}
+
+ak_status ak_mlp_loss_grad(const float *u, const float *y, int64_t K, const float *params, float *out,
+                           ak_stream_t stream) {
+    g_last_error.clear();
+    if (K < 1 || K > (int64_t(1) << 20) || !u || !y || !params || !out) {
+        set_error("bad arguments (1 <= K <= 2^20, non-NULL pointers)");
+        return AK_ERR_INVALID_ARG;
+    }
+    ak_status r;
+    Workspace *ws = ws_or_error(stream, &r);
+    if (!ws) return r;
+    return mlp_loss_grad(ws, u, y, K, params, out);
+}
+
+ak_status ak_mlp_fit(const void *sorted_sample, int64_t m, ak_dtype dtype, int32_t iters, int32_t leaves,
+                     float *params, float *model, ak_stream_t stream) {
+    g_last_error.clear();
+    ak_status r = check_keys(sorted_sample, m, dtype);
+    if (r != AK_OK) return r;
+    if (m < 1 || !model || leaves < 1 || leaves > 16384 || (leaves & (leaves - 1)) || iters < 0 ||
+        iters > 100000) {
+        set_error("bad arguments (m >= 1, model non-NULL, leaves a power of two <= 16384, 0 <= iters <= 100000)");
+        return AK_ERR_INVALID_ARG;
+    }
+    Workspace *ws = ws_or_error(stream, &r);
+    if (!ws) return r;
+    return mlp_fit(ws, dtype, sorted_sample, m, leaves, iters, model, params);
 }
 
 size_t ak_rmi_model_floats(int32_t leaves) { return leaves > 0 ? 8 + 4 * ((size_t)leaves + 1) : 0; }

@@ -261,5 +261,15 @@ ak_status rmi_leaf_grad(Workspace *ws, int dtype, const void *sorted, int64_t m,
                         float *out);
 ak_status rmi_codes(hipStream_t s, int dtype, const void *keys, int64_t n, const float *model, int cb,
                     uint32_t *codes);
+// Head of a model: root over the sorted sample's feature range in L equal
+// widths (rc, ra, rb = 0, L).
+ak_status rmi_root(hipStream_t s, int dtype, const void *sorted, uint32_t m, int L, float *model);
+// MLP model (mlp.hip): fit + table (params_out optional), scratch bytes,
+// and the forward/backward parity entry.
+ak_status mlp_fit(Workspace *ws, int dtype, const void *sorted, int64_t m, int L, int iters, float *model,
+                  float *params_out);
+size_t mlp_scratch_bytes(int64_t m);
+ak_status mlp_loss_grad(Workspace *ws, const float *u, const float *y, int64_t K, const float *params, float *out);
+
 
 }  // namespace ak

@@ -723,6 +723,13 @@ static ak_status fit_t(Workspace *ws, const void *sorted, uint32_t m, int L, int
     return AK_OK;
 }
 
+template <int DT>
+static ak_status root_t(hipStream_t s, const void *sorted, uint32_t m, int L, float *model) {
+    hipLaunchKernelGGL((k_rmi_root<DT>), dim3(1), dim3(64), 0, s, (const typename KT<DT>::U *)sorted, m, L, model);
+    AK_LAUNCH_CHECK("k_rmi_root");
+    return AK_OK;
+}
+
 static ak_status read_leaves(hipStream_t s, const float *model, int *L) {
     float head[8];
     AK_HIP(hipMemcpyAsync(head, model, sizeof(head), hipMemcpyDeviceToHost, s));
@@ -945,8 +952,12 @@ static ak_status learned_t(Workspace *ws, void *keys, int64_t n64, const ak_lear
                        cfg->seed, m, sample);
     AK_LAUNCH_CHECK("k_sample");
     if ((r = radix_sort(ws, DT, sample, nullptr, m, 1)) != AK_OK) return r;
-    // 2. fit
-    if ((r = fit_t<DT>(ws, sample, m, L, cfg->train_iters, model, cfg->untrained != 0)) != AK_OK) return r;
+    // 2. fit (the untrained model is the same for both model kinds)
+    if (cfg->model == AK_MODEL_MLP && !cfg->untrained) {
+        if ((r = mlp_fit(ws, DT, sample, m, L, cfg->train_iters, model, nullptr)) != AK_OK) return r;
+    } else if ((r = fit_t<DT>(ws, sample, m, L, cfg->train_iters, model, cfg->untrained != 0)) != AK_OK) {
+        return r;
+    }
     // 3. order by code
     if ((r = code_partition(ws, DT, keys, n, model, L, cb, 2)) != AK_OK) return r;
     // 4. chunks on chip
@@ -1033,7 +1044,7 @@ size_t learned_temp_bytes(int dt, int64_t n, const ak_learned_cfg *cfg) {
     const size_t kb = (size_t)dtype_bytes(dt);
     const uint32_t fb_cap = (uint32_t)(n / LEARNED_CAP_MIN + 2);
     const size_t aux0 = al(learned_aux0_bytes(kb, (uint32_t)m, L, fb_cap));
-    const size_t aux1 = al(fit_scratch_bytes((uint32_t)m, L, false));
+    const size_t aux1 = al(cfg->model == AK_MODEL_MLP ? mlp_scratch_bytes(m) : fit_scratch_bytes((uint32_t)m, L, false));
     return aux0 + aux1 + radix_temp_bytes(dt, m, false) + code_partition_bytes(dt, n) +
            segmented_scratch_bytes(dt, n, fb_cap, false) + al((size_t)4 << 14);
 }
@@ -1086,6 +1097,10 @@ static ak_status codes_t(hipStream_t s, const void *keys, int64_t n, const float
 ak_status rmi_codes(hipStream_t s, int dt, const void *keys, int64_t n, const float *model, int cb,
                     uint32_t *codes) {
     AK_DT_SWITCH(dt, codes_t, s, keys, n, model, cb, codes)
+}
+
+ak_status rmi_root(hipStream_t s, int dt, const void *sorted, uint32_t m, int L, float *model) {
+    AK_DT_SWITCH(dt, root_t, s, sorted, m, L, model)
 }
 
 }  // namespace ak
