@@ -117,6 +117,38 @@ def load_traffic(kernel: str):
     return d.get("kernels", {}).get(kernel)
 
 
+def cpu_single(ak_unused, synth, np):
+    """The oracle's plain (single-threaded) stable sort on workload 1 (the
+    whole 1M int64 input, median of 3) and on a 2^24-key sample of workload
+    2 (one run): the single-core baseline of the small configurations."""
+    import oracle
+    out = {}
+    k = synth.workload1(device="cpu").numpy()
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.sort(k)
+        ts.append(time.perf_counter() - t0)
+    ts.sort()
+    out["w1_i64_1M"] = {"ms": round(ts[1] * 1e3, 2), "GBps": round(k.size * 8 / ts[1] / 1e9, 4), "cores": 1}
+    k = synth.workload2(device="cpu").numpy()[: 1 << 24]
+    t0 = time.perf_counter()
+    oracle.sort(k)
+    dt = time.perf_counter() - t0
+    out["w2_f32_2^24_sample"] = {"ms": round(dt * 1e3, 1), "GBps": round(k.size * 4 / dt / 1e9, 4), "cores": 1,
+                                 "sample": "first 2^24 keys of workload 2"}
+    return out
+
+
+def route_bytes(ak, n: int, kb: int) -> int:
+    """HBM bytes of the last plain sort by the route it took: one histogram
+    read, a read and a write per digit pass, and a read and a write of the
+    on-chip finish when the prefix route ran."""
+    r = ak.sort_route()
+    passes = r["passes"]
+    return n * kb * (1 + 2 * passes + (2 if r["prefix_places"] else 0))
+
+
 def extras(torch, ak, synth, reps=3):
     out = {}
 
@@ -137,11 +169,27 @@ def extras(torch, ak, synth, reps=3):
     out["w2_f32_2^28"] = {"sort_ms": round(ms, 3), "sort_GBps": round(n * 4 / ms / 1e6, 1),
                           "sortperm_ms": round(msp, 3), "sortperm_GBps": round(n * 4 / msp / 1e6, 1)}
     del k
+    k = synth.workload2(device="cuda")
+    msl = t_of(lambda t: ak.sortperm_lowmem(t, dtype="f32"), k)
+    iota = torch.arange(k.numel(), dtype=torch.int32, device="cuda")
+    idx = torch.empty_like(iota)
+
+    def by_key(t):
+        # the payload is reset inside the timed region (a 1 GB device copy)
+        idx.copy_(iota)
+        ak.sort_by_key_(t, idx, dtype="f32")
+    msk = t_of(by_key, k)
+    out["w2_f32_2^28"].update({"sortperm_lowmem_ms": round(msl, 3), "sort_by_key_u32_ms": round(msk, 3)})
+    del k, idx, iota
     for v in ("uniform", "zipf", "lognormal"):
         k = synth.workload3(v, device="cuda")
         ms = t_of(lambda t: ak.sort_(t, dtype="i64"), k)
         n = k.numel()
-        out[f"w3_{v}_i64_2^30"] = {"sort_ms": round(ms, 3), "sort_GBps": round(n * 8 / ms / 1e6, 1)}
+        rb = route_bytes(ak, n, 8)
+        out[f"w3_{v}_i64_2^30"] = {"sort_ms": round(ms, 3), "sort_GBps": round(n * 8 / ms / 1e6, 1),
+                                   "route": ak.sort_route(),
+                                   "hbm_frac_route": round(rb / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                                   "hbm_frac_lsd136": round(n * 136 / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
         del k
         torch.cuda.empty_cache()
     # binary search (Sec. II-B): 2^24 int64 needles (half haystack members,
@@ -189,7 +237,7 @@ def extras(torch, ak, synth, reps=3):
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record()
-        ak.segmented_sort_(work, off, dtype="u32")
+        ak.segmented_sort_(work, off, dtype="u32", check=False)
         b.record()
         torch.cuda.synchronize()
         if r:
@@ -208,6 +256,8 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 31, help="keys (multiple of 4096)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--only", default="", help="time one workload only (for profiler runs): learned, plain, "
+                    "learned_mlp, w1, w2, w2_sortperm, w3_uniform, w3_zipf, w3_lognormal, w4")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -221,6 +271,9 @@ def main():
     import synth
 
     ak.load_library()
+    if args.only:
+        only(args, torch, ak, synth)
+        return
     n = args.n
     t0 = time.time()
     keys = synth.workload5(n=n, device="cuda")
@@ -261,6 +314,18 @@ def main():
 
     work.copy_(keys)
     _, stats = ak.sort_learned_(work, dtype="u64", stats=True)
+    # the same pipeline with the method's model replaced: the 1-64-64-1
+    # network (trained, tabulated), and no model (equal-width key ranges)
+    others = {}
+    for name, cfg in (("mlp", ak.make_cfg(model="mlp")), ("untrained", ak.make_cfg(untrained=True))):
+        ms_o = timed_steps(torch, lambda t: ak.sort_learned_(t, dtype="u64", cfg=cfg), keys, work, 3, 1)
+        work.copy_(keys)
+        _, st_o = ak.sort_learned_(work, dtype="u64", cfg=cfg, stats=True)
+        others[name] = {"ms_per_step": round(sum(ms_o) / len(ms_o), 3),
+                        "value": round(n * 8 / (sum(ms_o) / len(ms_o) / 1e3) / 1e9, 2), "unit": "GB/s",
+                        "imbalance": round(st_o["imbalance"], 3), "fallback_keys": st_o["fallback_keys"],
+                        "constant_keys": st_o["constant_keys"]}
+        log(f"learned ({name}): {min(ms_o):.2f} ms, imbalance {st_o['imbalance']:.2f}")
 
     ms_step = sum(learned_ms) / len(learned_ms)
     value = n * 8 / (ms_step / 1e3) / 1e9
@@ -276,6 +341,10 @@ def main():
     passes = (stats["code_bits"] + 7) // 8
     alg_bytes = n * 8 * (1 + 2 * passes + 2)
     plain_alg = n * 8 * (1 + 2 * 8)
+    work.copy_(keys)
+    ak.sort_(work, dtype="u64")
+    plain_route = ak.sort_route()
+    plain_route_bytes = route_bytes(ak, n, 8)
     line = {
         "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
@@ -285,7 +354,10 @@ def main():
                                "4096 leaves, 1% sample", "n": n, "key_bytes": 8, "seed": 0},
         "plain_radix": {"value": round(n * 8 / (plain_step / 1e3) / 1e9, 2), "unit": "GB/s",
                         "ms_per_step": round(plain_step, 3),
-                        "hbm_frac_alg": round(plain_alg / (plain_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+                        "hbm_frac_alg": round(plain_alg / (plain_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "route": plain_route,
+                        "hbm_frac_route": round(plain_route_bytes / (plain_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "learned_other_models": others,
         "learned_vs_plain": round(plain_step / ms_step, 3),
         "learned_hbm_frac_alg": round(alg_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "learned_stats": stats,
@@ -295,11 +367,37 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(torch, keys, np.uint64)
+        line["cpu_single_thread"] = cpu_single(ak, synth, np)
     del keys, work
     torch.cuda.empty_cache()
     if not args.no_extras:
         line["extras"] = extras(torch, ak, synth)
     print(json.dumps(line), flush=True)
+
+
+def only(args, torch, ak, synth):
+    """One workload, `--steps` timed sorts after `--warmup` (profiler runs)."""
+    name = args.only
+    if name in ("learned", "plain", "learned_mlp"):
+        src = synth.workload5(n=args.n, device="cuda")
+        fn = {"learned": lambda t: ak.sort_learned_(t, dtype="u64"),
+              "plain": lambda t: ak.sort_(t, dtype="u64"),
+              "learned_mlp": lambda t: ak.sort_learned_(t, dtype="u64", cfg=ak.make_cfg(model="mlp"))}[name]
+    elif name == "w1":
+        src, fn = synth.workload1(device="cuda"), (lambda t: ak.sort_(t, dtype="i64"))
+    elif name in ("w2", "w2_sortperm"):
+        src = synth.workload2(device="cuda")
+        fn = (lambda t: ak.sort_(t, dtype="f32")) if name == "w2" else (lambda t: ak.sortperm(t, dtype="f32"))
+    elif name.startswith("w3_"):
+        src, fn = synth.workload3(name[3:], device="cuda"), (lambda t: ak.sort_(t, dtype="i64"))
+    elif name == "w4":
+        src, off = synth.workload4(device="cuda")
+        fn = lambda t: ak.segmented_sort_(t, off, dtype="u32", check=False)
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    work = torch.empty_like(src)
+    ts = timed_steps(torch, fn, src, work, args.steps, args.warmup)
+    print(json.dumps({"only": name, "n": int(src.numel()), "ms": [round(t, 3) for t in ts]}), flush=True)
 
 
 if __name__ == "__main__":

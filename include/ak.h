@@ -59,8 +59,15 @@ typedef enum {
     AK_ERR_INTERNAL = 5           /* an internal consistency check failed    */
 } ak_status;
 
+/* Key types.  The 16- and 128-bit integers are the other widths the
+ * paper's benchmarks sort (Sec. IV-C: Int16 up to Int128); a 128-bit key
+ * is 16 bytes, little-endian (low 64-bit word first), signed ones in two's
+ * complement.  ak_sort, ak_sortperm, ak_sort_by_key, ak_sortperm_lowmem
+ * and ak_sort_noalloc take every type; the other calls take the six 32-
+ * and 64-bit types and return AK_ERR_UNSUPPORTED_DTYPE for the rest. */
 typedef enum {
-    AK_I32 = 1, AK_I64 = 2, AK_U32 = 3, AK_U64 = 4, AK_F32 = 5, AK_F64 = 6
+    AK_I32 = 1, AK_I64 = 2, AK_U32 = 3, AK_U64 = 4, AK_F32 = 5, AK_F64 = 6,
+    AK_I16 = 7, AK_U16 = 8, AK_I128 = 9, AK_U128 = 10
 } ak_dtype;
 
 /* ------------------------------------------------------------------ sort
@@ -107,6 +114,29 @@ ak_status ak_sortperm_u64(const uint64_t *keys, uint32_t *perm, int64_t n, ak_st
 ak_status ak_sortperm_f32(const float *keys, uint32_t *perm, int64_t n, ak_stream_t stream);
 ak_status ak_sortperm_f64(const double *keys, uint32_t *perm, int64_t n, ak_stream_t stream);
 
+/* ------------------------------------------------------- sort by key
+ * Sec. II-B (merge_sort_by_key): sorts keys[0..n) ascending in place and
+ * applies the same reordering to vals[0..n) (one payload of `val_bytes`
+ * bytes per key, a separate DEVICE array, also in place).  Stable: keys
+ * equal under the order keep their payloads in input order, so the result
+ * is unique (the oracle: the payloads gathered through ak_sortperm's
+ * permutation).  val_bytes is 4 or 8 (any 4- or 8-byte type, moved as
+ * bits).  The payload travels with the keys through every digit pass.
+ * Scratch: 2n keys + 2n payloads (ak_temp_bytes with AK_OP_SORT_BY_KEY is
+ * the bound for 8-byte payloads).  Errors: as ak_sort, plus vals == NULL,
+ * val_bytes not 4 or 8, or vals overlapping keys -> AK_ERR_INVALID_ARG. */
+ak_status ak_sort_by_key(void *keys, void *vals, int64_t n, ak_dtype dtype, int32_t val_bytes,
+                         ak_stream_t stream);
+
+/* ----------------------------------------------------- sortperm, low memory
+ * Sec. II-B (sortperm_lowmem): the permutation of ak_sortperm (identical
+ * output) with less scratch: only n uint32 indices (plus the per-tile
+ * counts), instead of 2n keys + n indices.  Every digit pass reads the
+ * indices and fetches their keys from the untouched key array (random
+ * reads after the first pass), so it is slower than ak_sortperm.
+ * Errors: as ak_sortperm. */
+ak_status ak_sortperm_lowmem(const void *keys, uint32_t *perm, int64_t n, ak_dtype dtype, ak_stream_t stream);
+
 /* ------------------------------------------------------- segmented sort
  * Batched form of Sec. II-B's sort: for s in [0, nseg) the segment
  * keys[offsets[s] .. offsets[s+1]) is sorted ascending in place, on its own.
@@ -125,6 +155,17 @@ ak_status ak_sortperm_f64(const double *keys, uint32_t *perm, int64_t n, ak_stre
  * ak_check_device_error(). */
 ak_status ak_segmented_sort(void *keys, const int64_t *offsets, int64_t nseg, ak_dtype dtype,
                             ak_stream_t stream);
+/* The same segmented sort with the key count n of the keys array given:
+ * scratch is sized from n (an upper bound of offsets[nseg]), and the
+ * batch's ends offsets[0] and offsets[nseg] are read and checked on the
+ * device, so the call never waits for the device (it synchronises only
+ * when the workspace must first grow).  Ends outside [0, n] or decreasing
+ * set the device error word (ak_check_device_error) and nothing is sorted;
+ * decreasing offsets inside the array are reported the same way.
+ * Errors (before any launch): n < 0, n > AK_MAX_KEYS, nseg < 0, NULL
+ * pointers -> AK_ERR_INVALID_ARG; n == 0 or nseg == 0 launches nothing. */
+ak_status ak_segmented_sort_n(void *keys, int64_t n, const int64_t *offsets, int64_t nseg, ak_dtype dtype,
+                              ak_stream_t stream);
 ak_status ak_segmented_sort_i32(int32_t *keys, const int64_t *offsets, int64_t nseg, ak_stream_t s);
 ak_status ak_segmented_sort_i64(int64_t *keys, const int64_t *offsets, int64_t nseg, ak_stream_t s);
 ak_status ak_segmented_sort_u32(uint32_t *keys, const int64_t *offsets, int64_t nseg, ak_stream_t s);
@@ -285,7 +326,7 @@ ak_status ak_mlp_fit(const void *sorted_sample, int64_t m, ak_dtype dtype, int32
 
 /* --------------------------------------------------------------- scratch */
 typedef enum { AK_OP_SORT = 0, AK_OP_SORTPERM = 1, AK_OP_SEGMENTED = 2, AK_OP_LEARNED = 3,
-               AK_OP_ACCUMULATE = 4 } ak_op;
+               AK_OP_ACCUMULATE = 4, AK_OP_SORT_BY_KEY = 5, AK_OP_SORTPERM_LOWMEM = 6 } ak_op;
 
 /* Bytes of device scratch one call of `op` on n keys needs (Sec. II-B: the
  * temporaries are known ahead of the call from the input size).  The value

@@ -22,14 +22,19 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libak.so")
 
-DTYPE_CODE = {"i32": 1, "i64": 2, "u32": 3, "u64": 4, "f32": 5, "f64": 6}
+DTYPE_CODE = {"i32": 1, "i64": 2, "u32": 3, "u64": 4, "f32": 5, "f64": 6,
+              "i16": 7, "u16": 8, "i128": 9, "u128": 10}
 _TORCH_DEFAULT = {torch.int32: "i32", torch.int64: "i64", torch.float32: "f32",
-                  torch.float64: "f64"}
-for _name, _dt in (("uint32", "u32"), ("uint64", "u64")):
+                  torch.float64: "f64", torch.int16: "i16"}
+for _name, _dt in (("uint16", "u16"), ("uint32", "u32"), ("uint64", "u64")):
     if hasattr(torch, _name):
         _TORCH_DEFAULT[getattr(torch, _name)] = _dt
-_WIDTH = {"i32": 4, "u32": 4, "f32": 4, "i64": 8, "u64": 8, "f64": 8}
-OPS = {"sort": 0, "sortperm": 1, "segmented": 2, "learned": 3, "accumulate": 4}
+# bytes per key; 128-bit keys (no torch dtype) are held as int64 pairs,
+# e.g. an (n, 2) int64 tensor, low word first
+_WIDTH = {"i32": 4, "u32": 4, "f32": 4, "i64": 8, "u64": 8, "f64": 8, "i16": 2, "u16": 2,
+          "i128": 16, "u128": 16}
+OPS = {"sort": 0, "sortperm": 1, "segmented": 2, "learned": 3, "accumulate": 4, "sort_by_key": 5,
+       "sortperm_lowmem": 6}
 
 
 class AKError(RuntimeError):
@@ -74,6 +79,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     sig = {
         "ak_sort": [vp, i64, i32, vp],
         "ak_sort_noalloc": [vp, i64, i32, vp],
+        "ak_sortperm_lowmem": [vp, vp, i64, i32, vp],
+        "ak_segmented_sort_n": [vp, i64, vp, i64, i32, vp],
+        "ak_sort_by_key": [vp, vp, i64, i32, i32, vp],
         "ak_sortperm": [vp, vp, i64, i32, vp],
         "ak_segmented_sort": [vp, vp, i64, i32, vp],
         "ak_check_device_error": [vp],
@@ -130,9 +138,17 @@ def _dtype(t: torch.Tensor, dtype: str | None) -> str:
     dt = dtype or _TORCH_DEFAULT.get(t.dtype)
     if dt not in DTYPE_CODE:
         raise TypeError(f"unsupported key dtype {t.dtype} (pass dtype=...)")
-    if t.element_size() != _WIDTH[dt]:
+    if dt in ("i128", "u128"):
+        if t.element_size() != 8 or t.numel() % 2:
+            raise TypeError("128-bit keys are held as pairs of 64-bit words (an even number of int64 elements)")
+    elif t.element_size() != _WIDTH[dt]:
         raise TypeError(f"dtype {dt} needs {_WIDTH[dt]}-byte elements, got {t.dtype}")
     return dt
+
+
+def _count(t: torch.Tensor, dt: str) -> int:
+    """Number of keys a tensor of dtype `dt` holds."""
+    return t.numel() * t.element_size() // _WIDTH[dt]
 
 
 def _gpu(t: torch.Tensor, name: str) -> None:
@@ -151,7 +167,7 @@ def sort_(keys: torch.Tensor, dtype: str | None = None) -> torch.Tensor:
     _gpu(keys, "keys")
     dt = _dtype(keys, dtype)
     with torch.cuda.device(keys.device):
-        _check(load_library().ak_sort(keys.data_ptr(), keys.numel(), DTYPE_CODE[dt], _stream(keys)), "ak_sort")
+        _check(load_library().ak_sort(keys.data_ptr(), _count(keys, dt), DTYPE_CODE[dt], _stream(keys)), "ak_sort")
     return keys
 
 
@@ -159,30 +175,71 @@ def sortperm(keys: torch.Tensor, dtype: str | None = None, out: torch.Tensor | N
     """Stable 0-based permutation (uint32 bits in an int32 tensor)."""
     _gpu(keys, "keys")
     dt = _dtype(keys, dtype)
+    n = _count(keys, dt)
     if out is None:
-        out = torch.empty(keys.numel(), dtype=torch.int32, device=keys.device)
+        out = torch.empty(n, dtype=torch.int32, device=keys.device)
     _gpu(out, "out")
+    if out.numel() != n or out.element_size() != 4:
+        raise ValueError("out must hold one 4-byte index per key")
     with torch.cuda.device(keys.device):
-        _check(load_library().ak_sortperm(keys.data_ptr(), out.data_ptr(), keys.numel(), DTYPE_CODE[dt],
-                                          _stream(keys)), "ak_sortperm")
+        _check(load_library().ak_sortperm(keys.data_ptr(), out.data_ptr(), n, DTYPE_CODE[dt], _stream(keys)),
+               "ak_sortperm")
     return out
 
 
-def segmented_sort_(keys: torch.Tensor, offsets: torch.Tensor, dtype: str | None = None) -> torch.Tensor:
-    """Sorts every segment [offsets[s], offsets[s+1]) of ``keys`` in place."""
+def sortperm_lowmem(keys: torch.Tensor, dtype: str | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """The permutation of ``sortperm`` with scratch for the indices only
+    (ak_sortperm_lowmem)."""
+    _gpu(keys, "keys")
+    dt = _dtype(keys, dtype)
+    n = _count(keys, dt)
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=keys.device)
+    _gpu(out, "out")
+    if out.numel() != n or out.element_size() != 4:
+        raise ValueError("out must hold one 4-byte index per key")
+    with torch.cuda.device(keys.device):
+        _check(load_library().ak_sortperm_lowmem(keys.data_ptr(), out.data_ptr(), n, DTYPE_CODE[dt], _stream(keys)),
+               "ak_sortperm_lowmem")
+    return out
+
+
+def sort_by_key_(keys: torch.Tensor, vals: torch.Tensor, dtype: str | None = None):
+    """Sorts ``keys`` in place and reorders ``vals`` (one 4- or 8-byte
+    payload per key, any dtype: its bits are moved) the same way
+    (ak_sort_by_key); returns (keys, vals)."""
+    _gpu(keys, "keys")
+    _gpu(vals, "vals")
+    dt = _dtype(keys, dtype)
+    n = _count(keys, dt)
+    vb = vals.numel() * vals.element_size() // max(n, 1) if n else 4
+    if vals.numel() * vals.element_size() != n * vb or vb not in (4, 8):
+        raise ValueError("vals must hold one 4- or 8-byte payload per key")
+    with torch.cuda.device(keys.device):
+        _check(load_library().ak_sort_by_key(keys.data_ptr(), vals.data_ptr(), n, DTYPE_CODE[dt], vb, _stream(keys)),
+               "ak_sort_by_key")
+    return keys, vals
+
+
+def segmented_sort_(keys: torch.Tensor, offsets: torch.Tensor, dtype: str | None = None,
+                    check: bool = True) -> torch.Tensor:
+    """Sorts every segment [offsets[s], offsets[s+1]) of ``keys`` in place
+    (ak_segmented_sort_n: asynchronous, the offsets are checked against
+    len(keys) on the device).  With check=True the call then waits and
+    raises if the device found offsets outside [0, len(keys)] or
+    decreasing; check=False returns at once (ak.check_device_error reports
+    such offsets later)."""
     _gpu(keys, "keys")
     _gpu(offsets, "offsets")
     if offsets.dtype != torch.int64:
         raise TypeError("offsets must be int64")
     dt = _dtype(keys, dtype)
-    if offsets.numel() >= 2:
-        # the library sees a raw pointer: the segments must lie inside keys
-        lo, hi = (int(x) for x in offsets[[0, -1]].tolist())
-        if lo < 0 or hi > keys.numel() or hi < lo:
-            raise ValueError(f"offsets span [{lo}, {hi}) but keys has {keys.numel()} elements")
     with torch.cuda.device(keys.device):
-        _check(load_library().ak_segmented_sort(keys.data_ptr(), offsets.data_ptr(), offsets.numel() - 1,
-                                                DTYPE_CODE[dt], _stream(keys)), "ak_segmented_sort")
+        _check(load_library().ak_segmented_sort_n(keys.data_ptr(), keys.numel(), offsets.data_ptr(),
+                                                  offsets.numel() - 1, DTYPE_CODE[dt], _stream(keys)),
+               "ak_segmented_sort_n")
+    if check:
+        check_device_error(keys.device)
     return keys
 
 

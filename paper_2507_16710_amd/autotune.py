@@ -69,7 +69,7 @@ def run(nseg: int, reps: int, seed: int = 0) -> dict:
                 a = torch.cuda.Event(enable_timing=True)
                 b = torch.cuda.Event(enable_timing=True)
                 a.record()
-                ak.segmented_sort_(work, off, dtype=dt)
+                ak.segmented_sort_(work, off, dtype=dt, check=False)
                 b.record()
                 torch.cuda.synchronize()
                 if r:

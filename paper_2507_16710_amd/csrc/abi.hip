@@ -7,6 +7,7 @@
 #include <utility>
 
 #include "ak_internal.h"
+#include "radix_kernels.h"
 
 namespace ak {
 
@@ -164,10 +165,10 @@ void radix_release(Workspace *ws);
 // Forgets every scratch buffer of the workspace, freeing the ones the
 // library allocated (arena buffers belong to the caller).
 static void drop_buffers(Workspace *ws) {
-    void **bufs[] = {&ws->keys0, &ws->keys1, &ws->vals0, (void **)&ws->lookback, &ws->misc, &ws->misc2};
-    size_t *sizes[] = {&ws->keys0_bytes, &ws->keys1_bytes, &ws->vals0_bytes, &ws->lookback_bytes, &ws->misc_bytes,
-                       &ws->misc2_bytes};
-    for (int i = 0; i < 6; ++i) {
+    void **bufs[] = {&ws->keys0, &ws->keys1, &ws->vals0, &ws->vals1, (void **)&ws->lookback, &ws->misc, &ws->misc2};
+    size_t *sizes[] = {&ws->keys0_bytes, &ws->keys1_bytes, &ws->vals0_bytes, &ws->vals1_bytes, &ws->lookback_bytes,
+                       &ws->misc_bytes, &ws->misc2_bytes};
+    for (int i = 0; i < 7; ++i) {
         if (*bufs[i] && !ws->arena) (void)hipFree(*bufs[i]);
         *bufs[i] = nullptr;
         *sizes[i] = 0;
@@ -188,7 +189,7 @@ void ws_begin_call(Workspace *ws) {
     ws->last_route = 0;
     if (!ws->arena) return;
     ws->arena_used = 0;
-    ws->keys0_bytes = ws->keys1_bytes = ws->vals0_bytes = 0;
+    ws->keys0_bytes = ws->keys1_bytes = ws->vals0_bytes = ws->vals1_bytes = 0;
     if (!ws->fixed_lookback) ws->lookback_bytes = 0;
     ws->misc_bytes = ws->misc2_bytes = 0;
     for (size_t &b : ws->aux_bytes) b = 0;
@@ -221,8 +222,9 @@ static bool overlaps(const void *a, size_t an, const void *b, size_t bn) {
     return x < y + bn && y < x + an;
 }
 
-static ak_status check_keys(const void *keys, int64_t n, int dtype) {
-    if (!dtype_ok(dtype)) {
+// `wide`: the entry point takes the 16- and 128-bit key types too.
+static ak_status check_keys(const void *keys, int64_t n, int dtype, bool wide = false) {
+    if (wide ? !dtype_ok(dtype) : !dtype_std(dtype)) {
         set_error("unknown dtype " + std::to_string(dtype));
         return AK_ERR_UNSUPPORTED_DTYPE;
     }
@@ -285,7 +287,7 @@ ak_status ak_sort_route(int64_t *info, ak_stream_t stream) {
 
 ak_status ak_sort(void *keys, int64_t n, ak_dtype dtype, ak_stream_t stream) {
     g_last_error.clear();
-    ak_status r = check_keys(keys, n, dtype);
+    ak_status r = check_keys(keys, n, dtype, true);
     if (r != AK_OK || n == 0) return r;
     Workspace *ws = ws_or_error(stream, &r);
     if (!ws) return r;
@@ -295,7 +297,7 @@ ak_status ak_sort(void *keys, int64_t n, ak_dtype dtype, ak_stream_t stream) {
 
 ak_status ak_sortperm(const void *keys, uint32_t *perm, int64_t n, ak_dtype dtype, ak_stream_t stream) {
     g_last_error.clear();
-    ak_status r = check_keys(keys, n, dtype);
+    ak_status r = check_keys(keys, n, dtype, true);
     if (r != AK_OK) return r;
     if (n > 0 && !perm) {
         set_error("perm is NULL");
@@ -312,6 +314,50 @@ ak_status ak_sortperm(const void *keys, uint32_t *perm, int64_t n, ak_dtype dtyp
     return radix_sort(ws, dtype, const_cast<void *>(keys), perm, n, 0);
 }
 
+// Sortperm with the smallest scratch (indices only); same checks and result.
+ak_status ak_sortperm_lowmem(const void *keys, uint32_t *perm, int64_t n, ak_dtype dtype, ak_stream_t stream) {
+    g_last_error.clear();
+    ak_status r = check_keys(keys, n, dtype, true);
+    if (r != AK_OK) return r;
+    if (n > 0 && !perm) {
+        set_error("perm is NULL");
+        return AK_ERR_INVALID_ARG;
+    }
+    if (n == 0) return AK_OK;
+    if (overlaps(keys, (size_t)n * dtype_bytes(dtype), perm, (size_t)n * 4)) {
+        set_error("perm overlaps keys");
+        return AK_ERR_INVALID_ARG;
+    }
+    Workspace *ws = ws_or_error(stream, &r);
+    if (!ws) return r;
+    if ((r = ws_arena_fits(ws, radix_temp_bytes_mode(dtype, M_LOWMEM, n))) != AK_OK) return r;
+    return radix_sort_mode(ws, dtype, M_LOWMEM, const_cast<void *>(keys), perm, n, 0);
+}
+
+ak_status ak_sort_by_key(void *keys, void *vals, int64_t n, ak_dtype dtype, int32_t val_bytes, ak_stream_t stream) {
+    g_last_error.clear();
+    ak_status r = check_keys(keys, n, dtype, true);
+    if (r != AK_OK) return r;
+    if (val_bytes != 4 && val_bytes != 8) {
+        set_error("val_bytes must be 4 or 8");
+        return AK_ERR_INVALID_ARG;
+    }
+    if (n > 0 && !vals) {
+        set_error("vals is NULL");
+        return AK_ERR_INVALID_ARG;
+    }
+    if (n == 0) return AK_OK;
+    if (overlaps(keys, (size_t)n * dtype_bytes(dtype), vals, (size_t)n * (size_t)val_bytes)) {
+        set_error("vals overlaps keys");
+        return AK_ERR_INVALID_ARG;
+    }
+    const int mode = val_bytes == 8 ? M_PAIRS8 : M_PAIRS4;
+    Workspace *ws = ws_or_error(stream, &r);
+    if (!ws) return r;
+    if ((r = ws_arena_fits(ws, radix_temp_bytes_mode(dtype, mode, n))) != AK_OK) return r;
+    return radix_sort_mode(ws, dtype, mode, keys, vals, n, 0);
+}
+
 #define AK_PERM_T(SUF, T, DT)                                                              \
     ak_status ak_sortperm_##SUF(const T *keys, uint32_t *perm, int64_t n, ak_stream_t s) { \
         return ak_sortperm(keys, perm, n, DT, s);                                          \
@@ -326,7 +372,7 @@ AK_PERM_T(f64, double, AK_F64)
 static ak_status search_entry(const void *v, int64_t n, const void *x, int64_t m, ak_dtype dtype, int64_t *out,
                               ak_stream_t stream, bool last) {
     g_last_error.clear();
-    if (!dtype_ok(dtype)) {
+    if (!dtype_std(dtype)) {
         set_error("unknown dtype " + std::to_string(dtype));
         return AK_ERR_UNSUPPORTED_DTYPE;
     }
@@ -383,7 +429,7 @@ ak_status ak_searchsortedlast(const void *sorted, int64_t n, const void *keys, i
 
 ak_status ak_segmented_sort(void *keys, const int64_t *offsets, int64_t nseg, ak_dtype dtype, ak_stream_t stream) {
     g_last_error.clear();
-    if (!dtype_ok(dtype)) {
+    if (!dtype_std(dtype)) {
         set_error("unknown dtype");
         return AK_ERR_UNSUPPORTED_DTYPE;
     }
@@ -400,6 +446,28 @@ ak_status ak_segmented_sort(void *keys, const int64_t *offsets, int64_t nseg, ak
     Workspace *ws = ws_or_error(stream, &r);
     if (!ws) return r;
     return segmented_sort(ws, dtype, keys, offsets, nseg);
+}
+
+ak_status ak_segmented_sort_n(void *keys, int64_t n, const int64_t *offsets, int64_t nseg, ak_dtype dtype,
+                              ak_stream_t stream) {
+    g_last_error.clear();
+    if (!dtype_std(dtype)) {
+        set_error("unknown dtype");
+        return AK_ERR_UNSUPPORTED_DTYPE;
+    }
+    if (nseg < 0 || n < 0 || n > AK_MAX_KEYS) {
+        set_error("nseg < 0, n < 0 or n > 2^31");
+        return AK_ERR_INVALID_ARG;
+    }
+    if (nseg == 0 || n == 0) return AK_OK;
+    if (!offsets || !keys) {
+        set_error("keys or offsets is NULL");
+        return AK_ERR_INVALID_ARG;
+    }
+    ak_status r;
+    Workspace *ws = ws_or_error(stream, &r);
+    if (!ws) return r;
+    return segmented_sort_n(ws, dtype, keys, n, offsets, nseg);
 }
 
 #define AK_SEG_T(SUF, T, DT)                                                                  \
@@ -558,18 +626,25 @@ size_t ak_temp_bytes(ak_op op, int64_t n, ak_dtype dtype) {
     switch (op) {
     case AK_OP_SORT: return radix_temp_bytes(dtype, n, false);
     case AK_OP_SORTPERM: return radix_temp_bytes(dtype, n, true);
+    case AK_OP_SORT_BY_KEY: return radix_temp_bytes_mode(dtype, M_PAIRS8, n);
+    case AK_OP_SORTPERM_LOWMEM: return radix_temp_bytes_mode(dtype, M_LOWMEM, n);
+    default: break;
+    }
+    if (!dtype_std(dtype)) return 0;
+    switch (op) {
     case AK_OP_SEGMENTED: return segmented_temp_bytes(dtype, n, n);
     case AK_OP_LEARNED: {
         ak_learned_cfg c = resolve_cfg(nullptr);
         return learned_temp_bytes(dtype, n, &c);
     }
     case AK_OP_ACCUMULATE: return accumulate_temp_bytes(n);
+    default: break;
     }
     return 0;
 }
 
 size_t ak_temp_bytes_segmented(int64_t n, int64_t nseg, ak_dtype dtype) {
-    if (!dtype_ok(dtype) || n <= 0 || nseg <= 0) return 0;
+    if (!dtype_std(dtype) || n <= 0 || nseg <= 0) return 0;
     return segmented_temp_bytes(dtype, n, nseg);
 }
 

@@ -48,9 +48,50 @@ template <> struct KT<AK_F64> {
     }
 };
 
-constexpr int key_bits(int dt) { return (dt == AK_I64 || dt == AK_U64 || dt == AK_F64) ? 64 : 32; }
+// The paper's benchmarks also sort Int16 and Int128 keys (Sec. IV-C):
+// 16-bit keys move as uint16_t, 128-bit keys as the compiler's unsigned
+// 128-bit integer (two 64-bit words, little-endian, low word first).
+using u128 = unsigned __int128;
+template <> struct KT<AK_U16> {
+    using U = uint16_t;
+    static __host__ __device__ __forceinline__ U image(U b) { return b; }
+};
+template <> struct KT<AK_I16> {
+    using U = uint16_t;
+    static __host__ __device__ __forceinline__ U image(U b) { return (U)(b ^ 0x8000u); }
+};
+template <> struct KT<AK_U128> {
+    using U = u128;
+    static __host__ __device__ __forceinline__ U image(U b) { return b; }
+};
+template <> struct KT<AK_I128> {
+    using U = u128;
+    static __host__ __device__ __forceinline__ U image(U b) { return b ^ ((u128)1 << 127); }
+};
+
+constexpr int key_bits(int dt) {
+    return (dt == AK_I64 || dt == AK_U64 || dt == AK_F64)   ? 64
+           : (dt == AK_I16 || dt == AK_U16)                 ? 16
+           : (dt == AK_I128 || dt == AK_U128)               ? 128
+                                                            : 32;
+}
+// Shape class of a key width: 0 for 16- and 32-bit keys, 1 for 64, 2 for 128.
+constexpr int key_class(int dt) { return key_bits(dt) <= 32 ? 0 : (key_bits(dt) == 64 ? 1 : 2); }
 inline int dtype_bytes(int dt) { return key_bits(dt) / 8; }
-inline bool dtype_ok(int dt) { return dt >= AK_I32 && dt <= AK_F64; }
+// every key type (sort, sortperm, sort by key, sortperm_lowmem, no-alloc sort)
+inline bool dtype_ok(int dt) { return dt >= AK_I32 && dt <= AK_U128; }
+// the six 32- and 64-bit key types (every other entry point)
+inline bool dtype_std(int dt) { return dt >= AK_I32 && dt <= AK_F64; }
+
+// Low and high 64 bits of a key image (the high half is 0 below 128 bits).
+__host__ __device__ __forceinline__ uint64_t img_lo(uint16_t t) { return t; }
+__host__ __device__ __forceinline__ uint64_t img_hi(uint16_t) { return 0; }
+__host__ __device__ __forceinline__ uint64_t img_lo(uint32_t t) { return t; }
+__host__ __device__ __forceinline__ uint64_t img_hi(uint32_t) { return 0; }
+__host__ __device__ __forceinline__ uint64_t img_lo(uint64_t t) { return t; }
+__host__ __device__ __forceinline__ uint64_t img_hi(uint64_t) { return 0; }
+__host__ __device__ __forceinline__ uint64_t img_lo(u128 t) { return (uint64_t)t; }
+__host__ __device__ __forceinline__ uint64_t img_hi(u128 t) { return (uint64_t)(t >> 64); }
 
 // ------------------------------------------------------------- wave64
 __device__ __forceinline__ uint32_t lane_id() {
@@ -97,7 +138,7 @@ __device__ __forceinline__ uint64_t lb_load(const uint64_t *p) {
 // ----------------------------------------------------- radix run state
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
-constexpr int MAX_PLACES = 8;
+constexpr int MAX_PLACES = 16;  // 8-bit digit places of a 128-bit key
 
 struct PassDesc {
     int32_t active;  // 0: every key has the same digit here; the pass is skipped
@@ -162,6 +203,7 @@ struct Workspace {
     void *keys0 = nullptr; size_t keys0_bytes = 0;
     void *keys1 = nullptr; size_t keys1_bytes = 0;
     void *vals0 = nullptr; size_t vals0_bytes = 0;
+    void *vals1 = nullptr; size_t vals1_bytes = 0;   // second payload buffer (sort by key)
     uint64_t *lookback = nullptr; size_t lookback_bytes = 0;
     RunState *state = nullptr;      // several run states (sample sort, main run)
     uint32_t *epoch_dev = nullptr;  // device copy of `epoch` (advanced by k_run_init)
@@ -209,6 +251,11 @@ constexpr size_t RUN_STATE_BYTES = sizeof(RunState) * RUN_SLOTS + 256;
 // Sorts keys (sort mode, in place) or writes perm (sortperm mode) on
 // `stream`, using run state slot `slot` of the workspace.
 ak_status radix_sort(Workspace *ws, int dtype, void *keys, uint32_t *perm, int64_t n, int slot);
+// The same run carrying `vals` as `mode` says (radix_kernels.h: M_KEYS,
+// M_PERM, M_PAIRS4, M_PAIRS8, M_LOWMEM), for every key type.
+ak_status radix_sort_mode(Workspace *ws, int dtype, int mode, void *keys, void *vals, int64_t n, int slot);
+// Scratch of radix_sort_mode.
+size_t radix_temp_bytes_mode(int dtype, int mode, int64_t n);
 // Binary search of keys x[0..m) in the sorted v[0..n) on stream s: out[i] =
 // first index not below x[i] (n if none), or with `last` the last index not
 // above x[i] (-1 if none).
@@ -241,6 +288,9 @@ int64_t small_sort_capacity(int dtype);
 
 // -------------------------------------------------------- segmented sort
 ak_status segmented_sort(Workspace *ws, int dtype, void *keys, const int64_t *offsets, int64_t nseg);
+// The same with the key count n given (scratch sized from n, the batch's
+// ends read and checked on the device): never waits for the device.
+ak_status segmented_sort_n(Workspace *ws, int dtype, void *keys, int64_t n, const int64_t *offsets, int64_t nseg);
 // Sorts disjoint ranges keys[lo[s] .. hi[s]) within keys[0 .. end), with
 // `tmp` as end keys of scratch (ranges with hi <= lo are skipped).
 ak_status segmented_sort_ranges(Workspace *ws, int dtype, void *keys, const int64_t *lo, const int64_t *hi,
@@ -270,6 +320,5 @@ ak_status mlp_fit(Workspace *ws, int dtype, const void *sorted, int64_t m, int L
                   float *params_out);
 size_t mlp_scratch_bytes(int64_t m);
 ak_status mlp_loss_grad(Workspace *ws, const float *u, const float *y, int64_t K, const float *params, float *out);
-
 
 }  // namespace ak

@@ -19,30 +19,45 @@ namespace ak {
 // + l); writes them sorted to out[0..len) (or, with VAL, the input indices
 // to vout).
 template <int DT, bool VAL, int W, int IPT>
-__device__ __forceinline__ void lds_sort_regs(typename KT<DT>::U (&k)[IPT], typename KT<DT>::U *out,
-                                              uint32_t *vout, uint32_t len,
+__device__ __forceinline__ void lds_sort_core(typename KT<DT>::U (&k)[IPT], uint32_t (&v)[IPT], uint32_t len,
                                               SmallSmem<typename KT<DT>::U, VAL, W, IPT> &sm, int tid) {
     using U = typename KT<DT>::U;
     constexpr int B = W * 64;
     const int lane = tid & 63, w = tid >> 6;
-    uint32_t v[IPT], rd[IPT];  // digit, then rank | digit << 16
-    uint64_t vor = 0, vand = ~0ull;
+    uint32_t rd[IPT];  // digit, then rank | digit << 16
+    // the bits that vary over the tile: OR and AND of the images, in two
+    // 64-bit halves (the high half is zero below 128-bit keys)
+    uint64_t olo = 0, alo = ~0ull, ohi = 0, ahi = ~0ull;
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         const uint32_t e = striped_elem<IPT>(w, j, lane);
         if (e < len) {
-            const uint64_t t = (uint64_t)KT<DT>::image(k[j]);
-            vor |= t;
-            vand &= t;
+            const auto t = KT<DT>::image(k[j]);
+            olo |= img_lo(t);
+            alo &= img_lo(t);
+            ohi |= img_hi(t);
+            ahi &= img_hi(t);
         }
         if (VAL) v[j] = e;
     }
     uint64_t ror, rand_;
-    block_or_and<W>(vor, vand, sm.red, ror, rand_, tid);
-    const uint64_t diff = ror ^ rand_;
-    if (diff != 0) {
-        const int lo = __builtin_ctzll(diff), hi = 63 - __builtin_clzll(diff);
+    block_or_and<W>(olo, alo, sm.red, ror, rand_, tid);
+    const uint64_t dlo = ror ^ rand_;
+    uint64_t dhi = 0;
+    if constexpr (key_bits(DT) > 64) {
+        block_or_and<W>(ohi, ahi, sm.red, ror, rand_, tid);
+        dhi = ror ^ rand_;
+    }
+    if (dlo != 0 || dhi != 0) {
+        const int lo = dlo ? __builtin_ctzll(dlo) : 64 + __builtin_ctzll(dhi);
+        const int hi = dhi ? 127 - __builtin_clzll(dhi) : 63 - __builtin_clzll(dlo);
         for (int shift = lo; shift <= hi; shift += RADIX_BITS) {
+            // per-thread indices re-derived every pass from an opaque copy
+            // of the thread id: hoisted out of the loop they would hold one
+            // register per key
+            int tq = tid;
+            asm volatile("" : "+v"(tq));
+            const int lane = tq & 63, w = tq >> 6;
 #pragma unroll
             for (int j = 0; j < IPT; ++j) {
                 const uint32_t e = striped_elem<IPT>(w, j, lane);
@@ -71,12 +86,54 @@ __device__ __forceinline__ void lds_sort_regs(typename KT<DT>::U (&k)[IPT], type
             grp_sync<W>();
         }
     }
+}
+
+template <int DT, bool VAL, int W, int IPT>
+__device__ __forceinline__ void lds_sort_regs(typename KT<DT>::U (&k)[IPT], typename KT<DT>::U *out,
+                                              uint32_t *vout, uint32_t len,
+                                              SmallSmem<typename KT<DT>::U, VAL, W, IPT> &sm, int tid) {
+    const int lane = tid & 63, w = tid >> 6;
+    uint32_t v[IPT];
+    lds_sort_core<DT, VAL, W, IPT>(k, v, len, sm, tid);
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         const uint32_t e = striped_elem<IPT>(w, j, lane);
         if (e < len) {
             if (!VAL) out[e] = k[j];
             else vout[e] = v[j];
+        }
+    }
+}
+
+// Sort by key of up to W*64*IPT keys on chip, in place: the keys sorted,
+// and the payloads vals[0..len) reordered the same way (every payload is
+// read through the tile's permutation before any is written).
+template <int DT, typename V, int W, int IPT>
+__device__ __forceinline__ void lds_sort_pairs(typename KT<DT>::U *keys, V *vals, uint32_t len,
+                                               SmallSmem<typename KT<DT>::U, true, W, IPT> &sm, int tid) {
+    using U = typename KT<DT>::U;
+    const int lane = tid & 63, w = tid >> 6;
+    U k[IPT];
+    uint32_t v[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const uint32_t e = striped_elem<IPT>(w, j, lane);
+        k[j] = e < len ? keys[e] : U(0);
+    }
+    lds_sort_core<DT, true, W, IPT>(k, v, len, sm, tid);
+    V pv[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const uint32_t e = striped_elem<IPT>(w, j, lane);
+        pv[j] = e < len ? vals[v[j]] : V(0);
+    }
+    __syncthreads();  // every payload read before any is written
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const uint32_t e = striped_elem<IPT>(w, j, lane);
+        if (e < len) {
+            keys[e] = k[j];
+            vals[e] = pv[j];
         }
     }
 }

@@ -1,738 +1,26 @@
-// LSD radix sort for gfx950: up-front multi-place histogram, digit-offset
-// scan with device-side pass skipping, and one-sweep digit passes (stable
-// in-tile ranking by wave ballots, decoupled look-back across tiles,
-// LDS-staged coalesced scatter).  Also the single-workgroup on-chip sort for
-// small inputs.
-//
-// What is computed is the paper's sort / sortperm (Sec. II-B): a stable
-// ascending sort under the Julia Base order.  The paper builds its sorter
-// as a merge sort in a portable kernel language; this file instead uses
-// 8-bit LSD radix passes because ballots and per-wave LDS counters are
-// available on gfx950 (the paper names wave-level intrinsics as what radix
-// sort needs, Sec. I-B), and the prefix scan across tiles is the decoupled
-// look-back scan that the paper cites for its accumulate (Sec. II-B).
+// Driver of the LSD radix sort (kernels and launch sequences in
+// radix_impl.h): shape choice, scratch sizes, the cached launch graphs of
+// small runs, the sort / sortperm runs of the six 32- and 64-bit key types,
+// and the code-digit passes of the learned sort.
 #include <cstdlib>
 #include <map>
 #include <mutex>
 
-#include "radix_common.h"
-#include "radix_kernels.h"
-#include "lds_sort.h"
-#include "rmi_device.h"
+#include "radix_impl.h"
 
 namespace ak {
 
-// ---------------------------------------------------------------- init
-// Zeroes the run's counters and takes the next 16 look-back epochs from the
-// workspace counter (restarting at 16 before 2^30; the host mirrors this and
-// clears the look-back words at that point).
-__global__ void k_run_init(RunState *st, uint32_t *epoch_dev) {
-    const int tid = threadIdx.x;
-    for (int i = tid; i < MAX_PLACES * RADIX; i += blockDim.x) (&st->hist[0][0])[i] = 0;
-    if (tid < MAX_PLACES) st->tile_ctr[tid] = 0;
-    if (tid == 0) {
-        st->hist_done = 0;
-        uint32_t e = *epoch_dev + 16;
-        if (e + 16 >= (1u << 30)) e = 16;
-        *epoch_dev = e;
-        st->epoch_base = e;
-    }
-}
-
-// Exclusive digit offsets per place; a place where one digit holds every
-// key is inactive (its pass would be a copy).  Active passes are numbered
-// so that each pass kernel can pick its source and destination buffers
-// without a host round trip.  Run by one workgroup of B >= 256 threads,
-// reading counts that other workgroups accumulated with device-scope
-// atomics.
-//
-// pfx_cap > 0 (key-only runs that can finish on chip): if the top k = 2..4
-// places spread the keys so that the expected largest run of equal prefix,
-// n * prod over those places of (largest digit count / n), is at most
-// pfx_cap keys, and the run then saves at least two passes, only the active
-// places among those k keep their passes and the run is marked prefix-
-// partitioned: the keys leave the passes ordered by their top k places,
-// and the chunk sort finishes each run of equal prefix.  The estimate
-// assumes independent places; a wrong guess costs time (longer runs go to
-// the segmented fallback), never order.
-template <int B>
-__device__ void scan_places(RunState *st, uint32_t n, int nplaces, uint32_t *s_buf, uint32_t *s_wsum,
-                            int *s_active, uint32_t *s_pmax, uint32_t pfx_cap) {
-    const int tid = threadIdx.x;
-    // every place's count in flight at once (one round trip, not one per place)
-    uint32_t cnt[MAX_PLACES];
-#pragma unroll
-    for (int p = 0; p < MAX_PLACES; ++p)
-        cnt[p] = (p < nplaces && tid < RADIX)
-                     ? __hip_atomic_load(&st->hist[p][tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                     : 0u;
-    if (tid < MAX_PLACES) s_pmax[tid] = 0;
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < MAX_PLACES; ++p) {
-        if (p >= nplaces) break;
-        const uint32_t c = cnt[p];
-        const int trivial = __syncthreads_or(tid < RADIX && c == n);
-        if (tid < RADIX) {
-            s_buf[tid] = c;
-            if (c) atomicMax(&s_pmax[p], c);
-        }
-        __syncthreads();
-        block_exscan<B, RADIX>(s_buf, s_buf, s_wsum, tid);
-        if (tid < RADIX) st->base[p][tid] = s_buf[tid];
-        if (tid == 0) s_active[p] = !trivial;
-        __syncthreads();
-    }
-    if (tid == 0) {
-        int q = 0, top = -1;
-        for (int p = 0; p < nplaces; ++p) {
-            q += s_active[p];
-            if (s_active[p]) top = p;
-        }
-        int lo = 0, qk = q;  // lowest place that keeps its pass; passes kept
-        uint32_t kp = 0;
-        if (pfx_cap > 0 && top >= 1) {
-            for (int k = 2; k <= 4 && k <= top + 1; ++k) {
-                double e = (double)n;
-                for (int i = 0; i < k; ++i) e *= (double)s_pmax[top - i] / (double)n;
-                if (e <= (double)pfx_cap) {
-                    int qa = 0;
-                    for (int p = top - k + 1; p <= top; ++p) qa += s_active[p];
-                    if (qa + 2 <= q) {
-                        kp = (uint32_t)k;
-                        lo = top - k + 1;
-                        qk = qa;
-                    }
-                    break;
-                }
-            }
-        }
-        int j = 0;
-        for (int p = 0; p < MAX_PLACES; ++p) {
-            PassDesc d;
-            d.active = (p < nplaces && p >= lo) ? s_active[p] : 0;
-            d.j = d.active ? j++ : -1;
-            d.q = qk;
-            d.shift = p * RADIX_BITS;
-            st->desc[p] = d;
-        }
-        st->q = qk;
-        st->pfx_active = kp != 0;
-        st->pfx_places = kp;
-        st->pfx_shift = lo * RADIX_BITS;
-        st->pfx_mask = kp >= 4 ? 0xFFFFFFFFu : ((1u << (kp * RADIX_BITS)) - 1u);
-    }
-}
-
-// ---------------------------------------------------------- histogram
-// One read of the keys; counts the digit of every place.  LDS counters per
-// workgroup, then one global atomic per nonzero bin.  The lanes of a wave
-// that hold the first lane's digit add their count once instead of as
-// conflicting LDS atomics on one address (all 64 for a constant high place
-// of small keys, the frequent digit of a skewed place).
-// Code digits use 1024-thread workgroups: the staged model table (64 KB at
-// 4096 leaves) leaves room for two workgroups per CU.
-template <int DT, bool CODE>
-__global__ __launch_bounds__(CODE ? 1024 : 256) void k_hist(const typename KT<DT>::U *__restrict__ keys, uint32_t n,
-                                                            int nplaces, RunState *st, const float *model, int cb,
-                                                            int staged, uint32_t pfx_cap) {
-    extern __shared__ float4 s_leaves[];
-    using U = typename KT<DT>::U;
-    constexpr int B = CODE ? 1024 : 256, ITEMS = 8;
-    __shared__ uint32_t s_h[MAX_PLACES * RADIX];
-    const int tid = threadIdx.x;
-    for (int i = tid; i < MAX_PLACES * RADIX; i += B) s_h[i] = 0;
-    RmiHead h;
-    const RmiLeaf *leaves = nullptr;
-    float scale = 0.f;
-    if (CODE) {
-        h = rmi_head(model);
-        leaves = rmi_stage(model, staged ? s_leaves : nullptr);
-        scale = (float)(1u << cb);
-    }
-    __syncthreads();
-    const uint32_t stride = gridDim.x * B * ITEMS;
-    for (uint32_t base = blockIdx.x * B * ITEMS; base < n; base += stride) {
-        U v[ITEMS];
-#pragma unroll
-        for (int it = 0; it < ITEMS; ++it) {
-            const uint32_t i = base + it * B + tid;
-            v[it] = i < n ? __builtin_nontemporal_load(keys + i) : U(0);
-        }
-        // model codes: one uniform branch per batch, so the staged table is
-        // read with LDS instructions (not flat loads through a pointer that
-        // may be LDS or global)
-        U cv[ITEMS];
-        if constexpr (CODE) {
-            auto codes = [&](const RmiLeaf *lv) {
-#pragma unroll
-                for (int it = 0; it < ITEMS; ++it) cv[it] = (U)rmi_code(h, lv, KT<DT>::image(v[it]), cb, scale);
-            };
-            if (staged) codes(reinterpret_cast<const RmiLeaf *>(s_leaves));
-            else codes(rmi_leaves(model));
-        }
-#pragma unroll
-        for (int it = 0; it < ITEMS; ++it) {
-            const uint32_t i = base + it * B + tid;
-            if (i >= n) break;
-            const U t = CODE ? cv[it] : KT<DT>::image(v[it]);
-            const uint64_t act = ballot64(true);
-            // key digits: every place of the key, unrolled (constant shifts)
-            constexpr int KP = (int)sizeof(U);
-#pragma unroll
-            for (int p = 0; p < (CODE ? MAX_PLACES : KP); ++p) {
-                if (CODE && p >= nplaces) break;
-                const uint32_t d = (uint32_t)(t >> (p * RADIX_BITS)) & (RADIX - 1);
-                // the lanes that share the first lane's digit add once when
-                // there are many of them (all lanes of a constant place, the
-                // frequent digit of a skewed one); otherwise every lane adds
-                // one (a single atomic instruction)
-                const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-                const uint64_t m0 = ballot64(d == d0);
-                if (__popcll(m0) > 8) {
-                    if (count_below(act) == 0) atomicAdd(&s_h[p * RADIX + d0], (uint32_t)__popcll(m0));
-                    if (d != d0) atomicAdd(&s_h[p * RADIX + d], 1u);
-                } else {
-                    atomicAdd(&s_h[p * RADIX + d], 1u);
-                }
-            }
-        }
-    }
-    __syncthreads();
-    for (int i = tid; i < nplaces * RADIX; i += B)
-        if (s_h[i]) atomicAdd(&st->hist[i / RADIX][i % RADIX], s_h[i]);
-    // the last workgroup to finish turns the counts into digit offsets
-    __shared__ int s_last;
-    __shared__ uint32_t s_wsum[B / 64];
-    __shared__ int s_active[MAX_PLACES];
-    __shared__ uint32_t s_pmax[MAX_PLACES];
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) s_last = atomicAdd(&st->hist_done, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    scan_places<B>(st, n, nplaces, s_h, s_wsum, s_active, s_pmax, pfx_cap);
-}
-
-// ----------------------------------------------------- one-sweep pass
-// One workgroup per tile of W*64*IPT keys, tiles taken in launch order from
-// an atomic counter (so every tile's predecessors are already running).
-// LDS: the per-wave 16-bit digit counters of the ranking phase share their
-// bytes with the key staging buffer of the scatter phase.
-// Sort mode with a second scratch buffer and an odd number q >= 3 of
-// active passes: route the passes through both scratch buffers so the last
-// one writes the caller's keys.
-__device__ __forceinline__ bool odd_route(int q, const void *t1) { return t1 != nullptr && (q & 1) && q >= 3; }
-
-// Keys whose model codes a code pass forms together (their table reads in
-// flight at once; the persistent code passes run two waves per SIMD, too
-// few to hide one read's latency behind another wave).
-#ifndef AK_CODE_GROUP
-#define AK_CODE_GROUP 2
-#endif
-constexpr int CODE_GROUP = AK_CODE_GROUP;
-
-template <typename U, bool VAL, bool CODE, int W, int IPT>
-struct OsSmem {
-    static constexpr int TILE = W * 64 * IPT;
-    static constexpr size_t KEYS = (size_t)TILE * sizeof(U) + (VAL ? (size_t)TILE * 4 : 0) + (CODE ? TILE : 0);
-    static constexpr size_t CNT = (size_t)W * RADIX * 2;
-    static constexpr size_t RAW = KEYS > CNT ? KEYS : CNT;
-};
-
-// Register budget: for 64-bit keys two workgroups per CU (W/2 waves per
-// SIMD) for one-tile workgroups, one for the persistent ones (W/4); 32-bit
-// keys use larger tiles that would spill under the tighter budget.
-template <int DT, bool VAL, int W, int IPT, bool CODE, bool PERS>
-__global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(
-    PERS ? W / 4 : (key_bits(DT) == 64 ? W / 2 : 1)))) void k_onesweep(OnesweepArgs a) {
-    using U = typename KT<DT>::U;
-    using SM = OsSmem<U, VAL, CODE, W, IPT>;
-    constexpr int B = W * 64, TILE = B * IPT;
-    constexpr int K = B / RADIX;  // threads per digit in the look-back
-    static_assert(B >= RADIX && B % RADIX == 0, "block must cover the radix");
-    const PassDesc pd = a.st->desc[a.place];
-    if (!pd.active) return;
-
-    __shared__ __align__(16) uint8_t s_raw[SM::RAW];
-    __shared__ uint32_t s_tot[RADIX], s_start[RADIX], s_glob[RADIX];
-    __shared__ uint32_t s_wsum[W];
-    __shared__ uint32_t s_tile;
-    uint16_t *s_cnt = reinterpret_cast<uint16_t *>(s_raw);
-    U *s_keys = reinterpret_cast<U *>(s_raw);
-    uint32_t *s_vals = reinterpret_cast<uint32_t *>(s_raw + (size_t)TILE * sizeof(U));
-    uint8_t *s_dig = s_raw + (size_t)TILE * sizeof(U) + (VAL ? (size_t)TILE * 4 : 0);
-
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    extern __shared__ float4 s_leaves[];
-
-    // buffers of this pass: sort mode ping-pongs between the keys and
-    // keys0; sortperm mode reads the const keys first, then keys0/keys1,
-    // and its values end in perm after the last active pass.
-    const int j = pd.j, q = pd.q;
-    const U *src;
-    U *dst;
-    const uint32_t *vsrc = nullptr;
-    uint32_t *vdst = nullptr;
-    if (!VAL) {
-        if (odd_route(q, a.t1)) {
-            // keys -> t0 -> t1 -> t0 ... -> t1 -> keys: the last pass writes
-            // the caller's buffer, so no copy back
-            auto buf = [&](int i) { return (U *)((i == 0 || i == q) ? a.keys : ((i & 1) ? a.t0 : a.t1)); };
-            src = buf(j);
-            dst = buf(j + 1);
-        } else {
-            src = (const U *)((j & 1) ? a.t0 : a.keys);
-            dst = (U *)((j & 1) ? a.keys : a.t0);
-        }
-    } else {
-        src = (const U *)(j == 0 ? a.keys : (((j - 1) & 1) ? a.t1 : a.t0));
-        dst = (U *)((j & 1) ? a.t1 : a.t0);
-        auto vb = [&](int i) { return (((q - 1 - i) & 1) == 0) ? a.perm : a.v0; };
-        vsrc = j == 0 ? nullptr : vb(j - 1);
-        vdst = vb(j);
-    }
-    const bool last = (j == q - 1);
-    const int shift = pd.shift;
-
-    RmiHead h;
-    const RmiLeaf *leaves = nullptr;
-    float scale = 0.f;
-    if (CODE) {
-        h = rmi_head(a.model);
-        leaves = rmi_stage(a.model, a.staged ? s_leaves : nullptr);
-        scale = (float)(1u << a.cb);
-    }
-    // Tiles are claimed in order from the pass counter, so a tile's
-    // predecessors are always held by running workgroups.  PERS = false: one
-    // tile per workgroup (grid = tiles).  PERS (always for code digits, whose
-    // persistent grid reuses the staged model table): each workgroup claims
-    // its next tile and issues that tile's loads before it waits in the
-    // look-back, so the HBM latency overlaps the wait.  A workgroup holds at
-    // most two claims, the tile it works on and the next, so the smallest
-    // unfinished tile always belongs to a workgroup that can finish it.
-    const uint32_t ntiles = (a.n + TILE - 1) / TILE;
-    auto load_tile = [&](uint32_t t, int w_, int lane_, U(&kk)[IPT], uint32_t(&vv)[IPT]) {
-        const uint32_t tb = t * (uint32_t)TILE;
-        const uint32_t tv = min((uint32_t)TILE, a.n - tb);
-        const U *sp = src + tb + w_ * 64 * IPT + lane_;
-        if (tv == (uint32_t)TILE) {
-#pragma unroll
-            for (int jj = 0; jj < IPT; ++jj) kk[jj] = __builtin_nontemporal_load(sp + jj * 64);
-        } else {
-#pragma unroll
-            for (int jj = 0; jj < IPT; ++jj) {
-                const uint32_t e = striped_elem<IPT>(w_, jj, lane_);
-                kk[jj] = e < tv ? __builtin_nontemporal_load(sp + jj * 64) : U(0);
-            }
-        }
-        if (VAL) {
-#pragma unroll
-            for (int jj = 0; jj < IPT; ++jj) {
-                const uint32_t e = striped_elem<IPT>(w_, jj, lane_);
-                vv[jj] = e >= tv ? 0u : (vsrc ? __builtin_nontemporal_load(vsrc + tb + e) : tb + e);
-            }
-        }
-    };
-    if (tid == 0) s_tile = atomicAdd(&a.st->tile_ctr[a.place], 1u);
-    __syncthreads();
-    uint32_t tile = s_tile;
-    if (tile >= ntiles) return;
-    U k[IPT];
-    uint32_t v[IPT];
-    load_tile(tile, w, lane, k, v);
-    while (true) {
-    // Per-thread indices are re-derived each iteration from an opaque copy
-    // of the thread id: hoisted out of the loop they would stay live across
-    // tiles and cost registers (occupancy).
-    int tid = threadIdx.x;
-    if (PERS) asm volatile("" : "+v"(tid));
-    const int lane = tid & 63, w = tid >> 6;
-    const uint32_t tbase = tile * (uint32_t)TILE;
-    const uint32_t tvalid = min((uint32_t)TILE, a.n - tbase);
-    uint32_t rd[IPT];  // digit, then rank | digit << 16
-    if constexpr (CODE) {
-        // one uniform branch: the staged table is read with LDS
-        // instructions (a pointer that may be LDS or global would be read
-        // with slower flat loads).  No per-key bounds test: the ranking
-        // ignores the digits past the tile's end (keys there are zero, and
-        // the clamped leaf index keeps their table reads in bounds), and a
-        // test would become a branch around each key's table reads that
-        // serialises their latency.
-        auto code_digits = [&](const RmiLeaf *lv) {
-            constexpr int G = IPT % CODE_GROUP == 0 ? CODE_GROUP : (IPT % 2 == 0 ? 2 : 1);
-#pragma unroll
-            for (int j0 = 0; j0 < IPT; j0 += G) {
-                U t[G];
-                uint32_t c[G];
-#pragma unroll
-                for (int g = 0; g < G; ++g) t[g] = KT<DT>::image(k[j0 + g]);
-                rmi_code_group<G>(h, lv, t, a.cb, scale, c);
-#pragma unroll
-                for (int g = 0; g < G; ++g) rd[j0 + g] = (c[g] >> shift) & (RADIX - 1);
-            }
-        };
-        if (a.staged) code_digits(reinterpret_cast<const RmiLeaf *>(s_leaves));
-        else code_digits(rmi_leaves(a.model));
-    } else {
-#pragma unroll
-        for (int jj = 0; jj < IPT; ++jj) {
-            const uint32_t e = striped_elem<IPT>(w, jj, lane);
-            const U t = KT<DT>::image(k[jj]);
-            rd[jj] = e < tvalid ? (uint32_t)(t >> shift) & (RADIX - 1) : 0u;
-        }
-    }
-
-    rank_match_packed<RADIX_BITS, W, IPT, uint16_t>(rd, tvalid, s_cnt, s_tot, tid);
-
-    // publish this tile's digit counts first, so successors can look back
-    // (the first tile of a group is inclusive within its group)
-    uint64_t *lb = a.lookback + (size_t)tile * RADIX;
-    const uint32_t epoch = a.st->epoch_base + (uint32_t)a.place;
-    for (int d = tid; d < RADIX; d += B)
-        lb_store(lb + d, lb_pack(epoch, tile % LB_GROUP == 0 ? LB_INC : LB_AGG, s_tot[d]));
-    // the next claim (every thread read s_tile before rank_match's barriers;
-    // block_exscan's barriers publish the new value)
-    if (PERS && tid == 0) s_tile = atomicAdd(&a.st->tile_ctr[a.place], 1u);
-
-    block_exscan<B, RADIX>(s_tot, s_start, s_wsum, tid);
-    rank_finish_packed<RADIX_BITS, W, IPT, uint16_t>(rd, s_cnt, s_start, tid);
-
-    uint32_t next = ntiles;
-    U kn[IPT];
-    uint32_t vn[IPT];
-    if (PERS) {
-        next = s_tile;
-        if (next < ntiles) load_tile(next, w, lane, kn, vn);
-    }
-
-    // two-level decoupled look-back (K*LB_M words per round trip): inside
-    // the tile's group, then over the words of the groups before it
-    {
-        const int d = tid / K, kk = tid % K;
-        const uint32_t g = tile / LB_GROUP, jl = tile % LB_GROUP;
-        uint64_t *lbg = a.lookback + (size_t)ntiles * RADIX;
-        uint32_t lexcl = 0, gexcl = 0;
-        if (jl > 0) {
-            // stops at the group's first tile at the latest (inclusive word)
-            lexcl = lookback_prefix<K, LB_M>(a.lookback + d, (int64_t)tile - 1, epoch, kk);
-            if (kk == 0) lb_store(lb + d, lb_pack(epoch, LB_INC, lexcl + s_tot[d]));
-        }
-        const bool glast = jl == LB_GROUP - 1;
-        if (glast && kk == 0)
-            lb_store(lbg + (size_t)g * RADIX + d, lb_pack(epoch, g == 0 ? LB_INC : LB_AGG, lexcl + s_tot[d]));
-        if (g > 0) {
-            gexcl = lookback_prefix<K, LB_M>(lbg + d, (int64_t)g - 1, epoch, kk);
-            if (glast && kk == 0)
-                lb_store(lbg + (size_t)g * RADIX + d, lb_pack(epoch, LB_INC, gexcl + lexcl + s_tot[d]));
-        }
-        if (kk == 0) s_glob[d] = a.st->base[a.place][d] + gexcl + lexcl - s_start[d];
-    }
-    __syncthreads();  // counters are dead from here on: their bytes hold keys
-
-#pragma unroll
-    for (int jj = 0; jj < IPT; ++jj) {
-        const uint32_t e = striped_elem<IPT>(w, jj, lane);
-        if (e < tvalid) {
-            const uint32_t r = rd[jj] & 0xFFFFu;
-            s_keys[r] = k[jj];
-            if (CODE) s_dig[r] = (uint8_t)(rd[jj] >> 16);
-            if (VAL) s_vals[r] = v[jj];
-        }
-    }
-    __syncthreads();
-
-    // coalesced scatter: consecutive threads write consecutive slots of a
-    // digit's run
-#pragma unroll
-    for (int jj = 0; jj < IPT; ++jj) {
-        const uint32_t i = (uint32_t)(jj * B + tid);
-        if (i < tvalid) {
-            const U key = s_keys[i];
-            const uint32_t d = CODE ? (uint32_t)s_dig[i] : (uint32_t)(KT<DT>::image(key) >> shift) & (RADIX - 1);
-            const uint32_t pos = s_glob[d] + i;
-            if (!VAL || !last) __builtin_nontemporal_store(key, dst + pos);
-            if (VAL) __builtin_nontemporal_store(s_vals[i], vdst + pos);
-        }
-    }
-    if (!PERS || next >= ntiles) break;
-    __syncthreads();  // the tile's LDS is reused by the next one
-    tile = next;
-#pragma unroll
-    for (int jj = 0; jj < IPT; ++jj) {
-        k[jj] = kn[jj];
-        if (VAL) v[jj] = vn[jj];
-    }
-    }
-}
-
-// ------------------------------------------- reduce-then-scan passes
-// The same stable digit pass without any waiting between workgroups: a
-// read-only kernel counts every chunk's digits, a scan turns the counts
-// into each chunk's output offset per digit (global digit offset plus the
-// counts of the chunks before it), and the scatter kernel walks its chunk's
-// tiles in order, carrying the running offsets in LDS.  One more read of
-// the keys per pass than the one-sweep pass, no look-back.
-
-// Source and destination of pass pd (the one-sweep pass's routing).
-template <typename U, bool VAL>
-__device__ __forceinline__ void pass_route(const OnesweepArgs &a, const PassDesc &pd, const U *&src, U *&dst,
-                                           const uint32_t *&vsrc, uint32_t *&vdst) {
-    const int j = pd.j, q = pd.q;
-    vsrc = nullptr;
-    vdst = nullptr;
-    if (!VAL) {
-        if (odd_route(q, a.t1)) {
-            auto buf = [&](int i) { return (U *)((i == 0 || i == q) ? a.keys : ((i & 1) ? a.t0 : a.t1)); };
-            src = buf(j);
-            dst = buf(j + 1);
-        } else {
-            src = (const U *)((j & 1) ? a.t0 : a.keys);
-            dst = (U *)((j & 1) ? a.keys : a.t0);
-        }
-    } else {
-        src = (const U *)(j == 0 ? a.keys : (((j - 1) & 1) ? a.t1 : a.t0));
-        dst = (U *)((j & 1) ? a.t1 : a.t0);
-        auto vb = [&](int i) { return (((q - 1 - i) & 1) == 0) ? a.perm : a.v0; };
-        vsrc = j == 0 ? nullptr : vb(j - 1);
-        vdst = vb(j);
-    }
-}
-
-// Digit counts of chunk blockIdx.x (TILE * chunk_tiles keys) at this place.
-template <int DT, bool VAL, bool CODE, int TILE>
-__global__ __launch_bounds__(256) void k_rts_count(OnesweepArgs a) {
-    using U = typename KT<DT>::U;
-    constexpr int B = 256;
-    const PassDesc pd = a.st->desc[a.place];
-    if (!pd.active) return;
-    __shared__ uint32_t s_h[RADIX];
-    extern __shared__ float4 s_leaves[];
-    const int tid = threadIdx.x;
-    s_h[tid] = 0;
-    RmiHead h;
-    const RmiLeaf *leaves = nullptr;
-    float scale = 0.f;
-    if (CODE) {
-        h = rmi_head(a.model);
-        leaves = rmi_stage(a.model, a.staged ? s_leaves : nullptr);
-        scale = (float)(1u << a.cb);
-    }
-    const U *src;
-    U *dst;
-    const uint32_t *vsrc;
-    uint32_t *vdst;
-    pass_route<U, VAL>(a, pd, src, dst, vsrc, vdst);
-    const int shift = pd.shift;
-    __syncthreads();
-    const uint32_t c = blockIdx.x;
-    const uint32_t lo = c * a.chunk_tiles * (uint32_t)TILE;
-    const uint32_t hi = min(a.n, lo + a.chunk_tiles * (uint32_t)TILE);
-    constexpr int ITEMS = 8;
-    for (uint32_t base = lo; base < hi; base += B * ITEMS) {
-        U v[ITEMS];
-#pragma unroll
-        for (int it = 0; it < ITEMS; ++it) {
-            const uint32_t i = base + it * B + tid;
-            v[it] = i < hi ? __builtin_nontemporal_load(src + i) : U(0);
-        }
-#pragma unroll
-        for (int it = 0; it < ITEMS; ++it) {
-            const uint32_t i = base + it * B + tid;
-            if (i >= hi) break;
-            U t = KT<DT>::image(v[it]);
-            if (CODE) t = (U)rmi_code(h, leaves, t, a.cb, scale);
-            const uint32_t d = (uint32_t)(t >> shift) & (RADIX - 1);
-            const uint64_t act = ballot64(true);
-            const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-            if (ballot64(d == d0) == act) {
-                if (count_below(act) == 0) atomicAdd(&s_h[d0], (uint32_t)__popcll(act));
-            } else {
-                atomicAdd(&s_h[d], 1u);
-            }
-        }
-    }
-    __syncthreads();
-    a.ccnt[(size_t)tid * a.nchunks + c] = s_h[tid];
-}
-
-// Per digit (one workgroup each): exclusive scan of the chunk counts plus
-// the digit's global offset, in place.
-__global__ __launch_bounds__(1024) void k_rts_scan(OnesweepArgs a) {
-    const PassDesc pd = a.st->desc[a.place];
-    if (!pd.active) return;
-    __shared__ uint32_t s_wsum[16];
-    __shared__ uint32_t s_carry;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int d = blockIdx.x;
-    uint32_t *row = a.ccnt + (size_t)d * a.nchunks;
-    if (tid == 0) s_carry = a.st->base[a.place][d];
-    __syncthreads();
-    for (uint32_t b0 = 0; b0 < a.nchunks; b0 += 1024) {
-        const uint32_t i = b0 + tid;
-        const uint32_t v = i < a.nchunks ? row[i] : 0u;
-        const uint32_t incl = wave_incl_scan(v);
-        if (lane == 63) s_wsum[w] = incl;
-        __syncthreads();
-        uint32_t run = s_carry;
-        for (int ww = 0; ww < w; ++ww) run += s_wsum[ww];
-        if (i < a.nchunks) row[i] = run + incl - v;
-        __syncthreads();
-        if (tid == 1023) s_carry = run + incl;
-        __syncthreads();
-    }
-}
-
-// Scatter of chunk blockIdx.x: its tiles in order, each ranked stably on
-// chip and written to the chunk's running digit offsets.
-template <int DT, bool VAL, int W, int IPT, bool CODE>
-__global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(
-    CODE ? W / 4 : (key_bits(DT) == 64 ? W / 2 : 1)))) void k_rts_scatter(OnesweepArgs a) {
-    using U = typename KT<DT>::U;
-    using SM = OsSmem<U, VAL, CODE, W, IPT>;
-    constexpr int B = W * 64, TILE = B * IPT;
-    const PassDesc pd = a.st->desc[a.place];
-    if (!pd.active) return;
-    __shared__ __align__(16) uint8_t s_raw[SM::RAW];
-    __shared__ uint32_t s_tot[RADIX], s_start[RADIX], s_glob[RADIX], s_run[RADIX];
-    __shared__ uint32_t s_wsum[W];
-    uint16_t *s_cnt = reinterpret_cast<uint16_t *>(s_raw);
-    U *s_keys = reinterpret_cast<U *>(s_raw);
-    uint32_t *s_vals = reinterpret_cast<uint32_t *>(s_raw + (size_t)TILE * sizeof(U));
-    uint8_t *s_dig = s_raw + (size_t)TILE * sizeof(U) + (VAL ? (size_t)TILE * 4 : 0);
-    extern __shared__ float4 s_leaves[];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const U *src;
-    U *dst;
-    const uint32_t *vsrc;
-    uint32_t *vdst;
-    pass_route<U, VAL>(a, pd, src, dst, vsrc, vdst);
-    const bool last = pd.j == pd.q - 1;
-    const int shift = pd.shift;
-    RmiHead h;
-    const RmiLeaf *leaves = nullptr;
-    float scale = 0.f;
-    if (CODE) {
-        h = rmi_head(a.model);
-        leaves = rmi_stage(a.model, a.staged ? s_leaves : nullptr);
-        scale = (float)(1u << a.cb);
-    }
-    const uint32_t c = blockIdx.x;
-    for (int d = tid; d < RADIX; d += B) s_run[d] = a.ccnt[(size_t)d * a.nchunks + c];
-    const uint32_t t0 = c * a.chunk_tiles;
-    const uint32_t t1 = min((a.n + TILE - 1) / TILE, t0 + a.chunk_tiles);
-    // tile t's keys (and values) in registers, striped; the next tile's are
-    // loaded before tile t is ranked, so their latency overlaps the work
-    auto load_tile = [&](uint32_t t, int w_, int lane_, U(&kk)[IPT], uint32_t(&vv)[IPT]) {
-        const uint32_t tb = t * (uint32_t)TILE;
-        const uint32_t tv = min((uint32_t)TILE, a.n - tb);
-        const U *sp = src + tb + w_ * 64 * IPT + lane_;
-#pragma unroll
-        for (int jj = 0; jj < IPT; ++jj) {
-            const uint32_t e = striped_elem<IPT>(w_, jj, lane_);
-            kk[jj] = e < tv ? __builtin_nontemporal_load(sp + jj * 64) : U(0);
-            if (VAL) vv[jj] = e >= tv ? 0u : (vsrc ? __builtin_nontemporal_load(vsrc + tb + e) : tb + e);
-        }
-    };
-    U k[IPT];
-    uint32_t v[IPT];
-    if (t0 < t1) load_tile(t0, w, lane, k, v);
-    for (uint32_t tile = t0; tile < t1; ++tile) {
-        // per-thread indices re-derived each tile from an opaque copy of the
-        // thread id (hoisted out of the loop they would be spilled)
-        int tid = threadIdx.x;
-        asm volatile("" : "+v"(tid));
-        const int lane = tid & 63, w = tid >> 6;
-        const uint32_t tbase = tile * (uint32_t)TILE;
-        const uint32_t tvalid = min((uint32_t)TILE, a.n - tbase);
-        U kn[IPT];
-        uint32_t vn[IPT], rd[IPT];
-        if (tile + 1 < t1) load_tile(tile + 1, w, lane, kn, vn);
-#pragma unroll
-        for (int jj = 0; jj < IPT; ++jj) {
-            const uint32_t e = striped_elem<IPT>(w, jj, lane);
-            U t = KT<DT>::image(k[jj]);
-            if (CODE) t = (U)rmi_code(h, leaves, t, a.cb, scale);
-            rd[jj] = e < tvalid ? (uint32_t)(t >> shift) & (RADIX - 1) : 0u;
-        }
-        rank_match_packed<RADIX_BITS, W, IPT, uint16_t>(rd, tvalid, s_cnt, s_tot, tid);
-        block_exscan<B, RADIX>(s_tot, s_start, s_wsum, tid);
-        rank_finish_packed<RADIX_BITS, W, IPT, uint16_t>(rd, s_cnt, s_start, tid);
-        for (int d = tid; d < RADIX; d += B) {
-            s_glob[d] = s_run[d] - s_start[d];
-            s_run[d] += s_tot[d];
-        }
-        __syncthreads();  // counters are dead from here on: their bytes hold keys
-#pragma unroll
-        for (int jj = 0; jj < IPT; ++jj) {
-            const uint32_t e = striped_elem<IPT>(w, jj, lane);
-            if (e < tvalid) {
-                const uint32_t r = rd[jj] & 0xFFFFu;
-                s_keys[r] = k[jj];
-                if (CODE) s_dig[r] = (uint8_t)(rd[jj] >> 16);
-                if (VAL) s_vals[r] = v[jj];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int jj = 0; jj < IPT; ++jj) {
-            const uint32_t i = (uint32_t)(jj * B + tid);
-            if (i < tvalid) {
-                const U key = s_keys[i];
-                const uint32_t d = CODE ? (uint32_t)s_dig[i] : (uint32_t)(KT<DT>::image(key) >> shift) & (RADIX - 1);
-                const uint32_t pos = s_glob[d] + i;
-                if (!VAL || !last) __builtin_nontemporal_store(key, dst + pos);
-                if (VAL) __builtin_nontemporal_store(s_vals[i], vdst + pos);
-            }
-        }
-        __syncthreads();  // the tile's LDS is reused by the next one
-#pragma unroll
-        for (int jj = 0; jj < IPT; ++jj) {
-            k[jj] = kn[jj];
-            if (VAL) v[jj] = vn[jj];
-        }
-    }
-}
-
-// ---------------------------------------------------------- finalize
-// Sort mode: after a single active pass (or an odd number without the
-// second scratch buffer) the result sits in keys0 and is copied back.  Sortperm mode: with no active pass (all keys
-// equal) the permutation is the identity.
-template <typename U, bool VAL>
-__global__ __launch_bounds__(256) void k_finalize(const RunState *st, U *keys, const U *t0, const U *t1,
-                                                  uint32_t *perm, uint32_t n) {
-    const int q = st->q;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    if (!VAL) {
-        if ((q & 1) == 0 || odd_route(q, t1)) return;
-        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-            __builtin_nontemporal_store(__builtin_nontemporal_load(t0 + i), keys + i);
-    } else {
-        if (q != 0) return;
-        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) perm[i] = i;
-    }
-}
-
-template <int DT, bool VAL, int W, int IPT>
-__global__ __launch_bounds__(W * 64) void k_small_sort(const typename KT<DT>::U *in, typename KT<DT>::U *out,
-                                                       uint32_t *perm, uint32_t n) {
-    using U = typename KT<DT>::U;
-    __shared__ SmallSmem<U, VAL, W, IPT> sm;
-    lds_sort_tile<DT, VAL, W, IPT>(in, out, perm, n, sm, threadIdx.x);
-}
-
-// ------------------------------------------------------------ driver
-// default shape per (64-bit keys, values), from the tuning sweep (per
-// pass, same box): 32-bit keys 16 waves x 16 keys, one tile per workgroup
-// (2^28 float32: 1.14 ms; no persistent shape was faster); 32-bit keys with
-// indices 16 x 12 persistent (1.94 -> 1.60 ms); 64-bit keys 8 x 24
+// Default pass shapes (OS_DEFAULT, radix_kernels.h) from the tuning sweep
+// (per pass, same box): 32-bit keys 16 waves x 16 keys, one tile per
+// workgroup (2^28 float32: 1.14 ms; no persistent shape was faster); 32-bit
+// keys with indices 16 x 12 persistent (1.94 -> 1.60 ms); 64-bit keys 8 x 24
 // persistent (2^30 int64: 7.43 -> 6.07 ms); 64-bit keys with indices 16 x 8
 // persistent (2^28 int64: 3.21 -> 2.50 ms).  Large tiles amortise the
 // per-tile work (digit scan, look-back, barriers) over more keys and make
-// the digit runs of the scatter longer.
-static const int OS_DEFAULT[2][2] = {{3, 3}, {3, 2}};
-// default shape of the code-digit passes per key width.  64-bit keys: a
+// the digit runs of the scatter longer.  Payloads of 8 bytes and 128-bit
+// keys take the largest tile whose staging buffer leaves room for a second
+// workgroup or the persistent grid.
+// Default shape of the code-digit passes per key width.  64-bit keys: a
 // 10240-key tile, the largest whose staging buffer still fits the LDS beside
 // the 64 KB model table, held by 8 waves x 20 keys (2^31 mixture keys, per
 // pass: 16 x 6 keys 20.7 ms, 16 x 8 keys 18.0 ms, 16 x 10 keys 16.1 ms,
@@ -751,11 +39,13 @@ static int env_variant(const char *name) {
 // -> 205 us; 2^20 float32: 140 -> 128 us).  Sortperm keeps its shapes.
 constexpr int64_t SMALL_SHAPE_MAX = int64_t(1) << 21;
 
-int os_variant(int dt, bool val, int64_t n) {
-    static const int forced = env_variant("AK_OS_VARIANT");
-    if (forced >= 0) return forced;
-    if (!val && n <= SMALL_SHAPE_MAX) return 0;
-    return OS_DEFAULT[key_bits(dt) == 64][val];
+int os_variant(int dt, int mode, int64_t n) {
+    if (os_all_variants(dt, mode)) {
+        static const int forced = env_variant("AK_OS_VARIANT");
+        if (forced >= 0) return forced;
+    }
+    if (mode == M_KEYS && n <= SMALL_SHAPE_MAX) return 0;
+    return OS_DEFAULT[key_class(dt)][mode_vclass(mode)];
 }
 
 int os_code_variant(int dt) {
@@ -763,34 +53,27 @@ int os_code_variant(int dt) {
     return forced >= 0 ? forced : OS_CODE_DEFAULT[key_bits(dt) == 64];
 }
 
-constexpr int SMALL_W = 4, SMALL_IPT = 16;
-
 int64_t small_sort_capacity(int) { return SMALL_W * 64 * SMALL_IPT; }
 
-static inline int tile_keys(int dt, bool val, int64_t n) { return os_tile(dt, val, n); }
-
-static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
-
-// Bytes of the chunk counts of a reduce-then-scan pass over `tiles` tiles
-// (at most one chunk per tile).
-static size_t rts_bytes(size_t tiles) { return tiles * RADIX * 4; }
-
-// Key-only runs above this size may take the prefix-partitioned finish
-// (smaller ones replay a captured graph of plain passes).
-constexpr int64_t PREFIX_MIN = int64_t(1) << 22;
-
-size_t radix_temp_bytes(int dt, int64_t n, bool perm) {
+size_t radix_temp_bytes_mode(int dt, int mode, int64_t n) {
     if (n <= small_sort_capacity(dt)) return 0;
     const size_t kb = (size_t)dtype_bytes(dt);
-    const size_t tiles = (size_t)((n + tile_keys(dt, perm, n) - 1) / tile_keys(dt, perm, n));
-    // two key-sized ping-pong buffers (sort: the second one lets an odd
-    // number of passes end in the caller's buffer; sortperm: the const keys
-    // are never written), the look-back words, and the index buffer
-    size_t b = 2 * al256((size_t)n * kb) + al256(lookback_words(tiles) * 8) + al256(rts_bytes(tiles));
-    if (perm) b += al256((size_t)n * 4);
-    if (!perm && n > PREFIX_MIN) b += prefix_finish_bytes(dt, n);
+    const int tile = os_tile(dt, mode, n);
+    const size_t tiles = (size_t)((n + tile - 1) / tile);
+    // the look-back words and per-tile counts; two key-sized ping-pong
+    // buffers (sort: the second one lets an odd number of passes end in the
+    // caller's buffer; sortperm: the const keys are never written), except
+    // for the low-memory sortperm, which moves indices only; one index
+    // buffer (sortperm) or two payload buffers (sort by key)
+    size_t b = al256(lookback_words(tiles) * 8) + al256(rts_bytes(tiles));
+    if (mode != M_LOWMEM) b += 2 * al256((size_t)n * kb);
+    if (mode == M_PERM || mode == M_LOWMEM) b += al256((size_t)n * 4);
+    if (mode == M_PAIRS4 || mode == M_PAIRS8) b += 2 * al256((size_t)n * (mode == M_PAIRS8 ? 8 : 4));
+    if (mode == M_KEYS && prefix_dtype(dt) && n > PREFIX_MIN) b += prefix_finish_bytes(dt, n);
     return b;
 }
+
+size_t radix_temp_bytes(int dt, int64_t n, bool perm) { return radix_temp_bytes_mode(dt, perm ? M_PERM : M_KEYS, n); }
 
 size_t code_partition_bytes(int dt, int64_t n) {
     const size_t kb = (size_t)dtype_bytes(dt);
@@ -798,8 +81,7 @@ size_t code_partition_bytes(int dt, int64_t n) {
     return 2 * al256((size_t)n * kb) + al256(lookback_words(tiles) * 8) + al256(rts_bytes(tiles));
 }
 
-// Reduce-then-scan passes ($AK_OS_RTS=1) instead of one-sweep passes.
-static bool os_rts() {
+bool os_rts() {
     static const bool p = [] {
         const char *e = getenv("AK_OS_RTS");
         return e && *e == '1';
@@ -809,141 +91,12 @@ static bool os_rts() {
 
 // Tiles per reduce-then-scan chunk: enough chunks for four workgroups per
 // CU, at most 16 tiles each.
-static uint32_t rts_chunk_tiles(uint32_t tiles) {
+uint32_t rts_chunk_tiles(uint32_t tiles) {
     const uint32_t want = (uint32_t)num_cus() * 4;
     return std::max<uint32_t>(1, std::min<uint32_t>(16, (tiles + want - 1) / want));
 }
 
-template <int DT, bool VAL, bool CODE, int V>
-static void launch_rts_v(hipStream_t s, uint32_t tiles, OnesweepArgs a, size_t stage) {
-    constexpr OsShape sh = CODE ? OS_CODE_SHAPES[key_bits(DT) == 64][V] : OS_SHAPES[key_bits(DT) == 64][VAL][V];
-    constexpr int TILE = sh.w * 64 * sh.ipt;
-    a.chunk_tiles = rts_chunk_tiles(tiles);
-    a.nchunks = (tiles + a.chunk_tiles - 1) / a.chunk_tiles;
-    hipLaunchKernelGGL((k_rts_count<DT, VAL, CODE, TILE>), dim3(a.nchunks), dim3(256), stage, s, a);
-    hipLaunchKernelGGL(k_rts_scan, dim3(RADIX), dim3(1024), 0, s, a);
-    hipLaunchKernelGGL((k_rts_scatter<DT, VAL, sh.w, sh.ipt, CODE>), dim3(a.nchunks), dim3(sh.w * 64), stage, s, a);
-}
-
-template <int DT, bool VAL, bool CODE, int V>
-static void launch_pass_v(hipStream_t s, uint32_t tiles, const OnesweepArgs &a, size_t stage) {
-    if (os_rts()) {
-        launch_rts_v<DT, VAL, CODE, V>(s, tiles, a, stage);
-        return;
-    }
-    constexpr OsShape sh = CODE ? OS_CODE_SHAPES[key_bits(DT) == 64][V] : OS_SHAPES[key_bits(DT) == 64][VAL][V];
-    // code digits: persistent grid (the staged table leaves room for one
-    // workgroup per CU); key digits: a persistent grid of at most two
-    // workgroups per CU (the shapes' LDS admits one or two), or one
-    // workgroup per tile
-    if constexpr (CODE) {
-        const uint32_t grid = std::min<uint32_t>(tiles, (uint32_t)num_cus() * (stage ? 1 : 2));
-        hipLaunchKernelGGL((k_onesweep<DT, VAL, sh.w, sh.ipt, true, true>), dim3(grid), dim3(sh.w * 64), stage, s, a);
-    } else if constexpr (sh.pers) {
-        const uint32_t grid = std::min<uint32_t>(tiles, (uint32_t)num_cus() * 2);
-        hipLaunchKernelGGL((k_onesweep<DT, VAL, sh.w, sh.ipt, false, true>), dim3(grid), dim3(sh.w * 64), 0, s, a);
-    } else {
-        hipLaunchKernelGGL((k_onesweep<DT, VAL, sh.w, sh.ipt, false, false>), dim3(tiles), dim3(sh.w * 64), 0, s, a);
-    }
-}
-
-template <int DT, bool VAL, bool CODE>
-static ak_status launch_passes(hipStream_t stream, Workspace *ws, RunState *st, const void *keys_in, void *t0, void *t1,
-                               uint32_t *v0, uint32_t *perm, uint32_t n, int nplaces, const float *model, int cb,
-                               size_t stage) {
-    const int var = CODE ? os_code_variant(DT) : os_variant(DT, VAL, n);
-    const int TILE = CODE ? os_code_tile(DT) : os_tile(DT, VAL, n);
-    const uint32_t tiles = (n + TILE - 1) / TILE;
-    OnesweepArgs a{};
-    a.keys = const_cast<void *>(keys_in);
-    a.t0 = t0;
-    a.t1 = t1;
-    a.v0 = v0;
-    a.perm = perm;
-    a.lookback = ws->lookback;
-    a.ccnt = (uint32_t *)ws->aux[4];
-    a.st = st;
-    a.n = n;
-    a.model = model;
-    a.cb = cb;
-    a.staged = stage > 0;
-    for (int p = 0; p < nplaces; ++p) {
-        a.place = p;
-        ProfScope ps(CODE ? "onesweep_code_pass" : (VAL ? "onesweep_pair_pass" : "onesweep_pass"), stream);
-        switch (var) {
-        case 0: launch_pass_v<DT, VAL, CODE, 0>(stream, tiles, a, stage); break;
-        case 1: launch_pass_v<DT, VAL, CODE, 1>(stream, tiles, a, stage); break;
-        case 2: launch_pass_v<DT, VAL, CODE, 2>(stream, tiles, a, stage); break;
-        default: launch_pass_v<DT, VAL, CODE, 3>(stream, tiles, a, stage); break;
-        }
-        AK_LAUNCH_CHECK("k_onesweep");
-    }
-    return AK_OK;
-}
-
-// The whole multi-workgroup run: init (epochs, counters), histogram with
-// the digit scan fused into its last workgroup, one pass per place (inactive
-// ones exit at once), and the device-decided copy-back / identity.
-template <int DT, bool CODE>
-static ak_status launch_run(hipStream_t s, Workspace *ws, RunState *st, void *keys, uint32_t *perm, uint32_t n,
-                            int nplaces, const float *model, int cb, size_t stage = 0, uint32_t pfx_cap = 0) {
-    using U = typename KT<DT>::U;
-    const bool pm = perm != nullptr;
-    hipLaunchKernelGGL(k_run_init, dim3(1), dim3(256), 0, s, st, ws->epoch_dev);
-    AK_LAUNCH_CHECK("k_run_init");
-    constexpr int HB = CODE ? 1024 : 256;
-    const uint32_t hgrid = (uint32_t)std::min<int64_t>(((int64_t)n + HB * 8 - 1) / (HB * 8),
-                                                       (int64_t)num_cus() * (CODE ? 2 : 8));
-    {
-        ProfScope ps(CODE ? "code_hist" : "digit_hist", s);
-        hipLaunchKernelGGL((k_hist<DT, CODE>), dim3(hgrid), dim3(HB), stage, s, (const U *)keys, n, nplaces, st,
-                           model, cb, (int)(stage > 0), pfx_cap);
-    }
-    AK_LAUNCH_CHECK("k_hist");
-    ak_status r;
-    if (pm) {
-        if constexpr (CODE) return AK_ERR_INTERNAL;  // code digits order keys only
-        else
-            r = launch_passes<DT, true, false>(s, ws, st, keys, ws->keys0, ws->keys1, (uint32_t *)ws->vals0, perm,
-                                               n, nplaces, model, cb, stage);
-    } else
-        r = launch_passes<DT, false, CODE>(s, ws, st, keys, ws->keys0, ws->keys1, nullptr, nullptr, n, nplaces, model,
-                                           cb, stage);
-    if (r != AK_OK) return r;
-    const uint32_t fgrid = (uint32_t)std::min<int64_t>(((int64_t)n + 1023) / 1024, (int64_t)num_cus() * 8);
-    if (pm)
-        hipLaunchKernelGGL((k_finalize<U, true>), dim3(fgrid), dim3(256), 0, s, st, (U *)nullptr, (const U *)nullptr,
-                           (const U *)nullptr, perm, n);
-    else
-        hipLaunchKernelGGL((k_finalize<U, false>), dim3(fgrid), dim3(256), 0, s, st, (U *)keys,
-                           (const U *)ws->keys0, (const U *)ws->keys1, (uint32_t *)nullptr, n);
-    AK_LAUNCH_CHECK("k_finalize");
-    return AK_OK;
-}
-
 // ------------------------------------------------------- graph replay
-// Runs of up to GRAPH_MAX keys are latency-bound (about p+3 launches of a
-// few microseconds of work each), so their launch sequence is captured once
-// per (dtype, mode, n, pointers, workspace generation) and replayed.
-// Epochs come from the device counter, so replays never meet stale words.
-constexpr int64_t GRAPH_MAX = int64_t(1) << 22;
-
-struct GraphKey {
-    int dt;
-    int slot;
-    uint32_t n;
-    const void *keys;
-    const void *perm;
-    uint32_t gen;
-    bool operator<(const GraphKey &o) const {
-        if (dt != o.dt) return dt < o.dt;
-        if (slot != o.slot) return slot < o.slot;
-        if (n != o.n) return n < o.n;
-        if (keys != o.keys) return keys < o.keys;
-        if (perm != o.perm) return perm < o.perm;
-        return gen < o.gen;
-    }
-};
 struct GraphCache {
     hipStream_t capture = nullptr;
     std::map<GraphKey, hipGraphExec_t> graphs;
@@ -961,54 +114,10 @@ void radix_release(Workspace *ws) {
     g_graphs.erase(it);
 }
 
-template <int DT>
-static ak_status radix_sort_t(Workspace *ws, void *keys, uint32_t *perm, int64_t n64, int slot) {
-    using U = typename KT<DT>::U;
-    hipStream_t s = ws->stream;
-    const uint32_t n = (uint32_t)n64;
-    const bool pm = perm != nullptr;
-    if (n64 <= small_sort_capacity(DT)) {
-        if (pm)
-            hipLaunchKernelGGL((k_small_sort<DT, true, SMALL_W, SMALL_IPT>), dim3(1), dim3(SMALL_W * 64), 0, s,
-                               (const U *)keys, (U *)nullptr, perm, n);
-        else
-            hipLaunchKernelGGL((k_small_sort<DT, false, SMALL_W, SMALL_IPT>), dim3(1), dim3(SMALL_W * 64), 0, s,
-                               (const U *)keys, (U *)keys, (uint32_t *)nullptr, n);
-        AK_LAUNCH_CHECK("k_small_sort");
-        return AK_OK;
-    }
-    const size_t kb = sizeof(U);
-    ak_status r;
-    if ((r = ws_reserve(ws, &ws->keys0, &ws->keys0_bytes, (size_t)n * kb)) != AK_OK) return r;
-    if ((r = ws_reserve(ws, &ws->keys1, &ws->keys1_bytes, (size_t)n * kb)) != AK_OK) return r;
-    if (pm && (r = ws_reserve(ws, &ws->vals0, &ws->vals0_bytes, (size_t)n * 4)) != AK_OK) return r;
-    const int TILE = tile_keys(DT, pm, n64);
-    const size_t tiles = (n + TILE - 1) / TILE;
-    if ((r = ws_reserve_lookback(ws, lookback_words(tiles) * 8)) != AK_OK) return r;
-    if ((r = ws_reserve(ws, &ws->aux[4], &ws->aux_bytes[4], rts_bytes(tiles))) != AK_OK) return r;
-    // key-only runs too large for a captured graph may finish on chip once
-    // their top places are placed (decided on the device from the digit
-    // counts; plain passes otherwise)
-    const bool pfx = !pm && n64 > PREFIX_MIN && !stream_capturing(s);
-    if (pfx && (r = prefix_reserve(ws, DT, n64)) != AK_OK) return r;
-    if (slot == 0) ws->last_route = pfx ? 2 : 1;
-    uint32_t epoch;
-    if ((r = ws_next_epoch(ws, &epoch)) != AK_OK) return r;
-    RunState *st = ws->state + slot;
-    const int nplaces = (int)(sizeof(U) * 8 / RADIX_BITS);
-    if (pfx) {
-        if ((r = launch_run<DT, false>(s, ws, st, keys, perm, n, nplaces, nullptr, 0, 0,
-                                       (uint32_t)(prefix_chunk_keys() / 4))) != AK_OK)
-            return r;
-        return prefix_finish(ws, DT, keys, n64, st);
-    }
-    if (n64 > GRAPH_MAX || ws->no_graph || stream_capturing(s))
-        return launch_run<DT, false>(s, ws, st, keys, perm, n, nplaces, nullptr, 0);
-
+ak_status graph_run(Workspace *ws, const GraphKey &key, const std::function<ak_status(hipStream_t)> &record) {
     std::lock_guard<std::mutex> lk(g_graph_mu);
     GraphCache &c = g_graphs[ws];
     if (!c.capture) AK_HIP(hipStreamCreateWithFlags(&c.capture, hipStreamNonBlocking));
-    const GraphKey key{DT, slot, n, keys, perm, ws->gen};
     auto it = c.graphs.find(key);
     if (it == c.graphs.end()) {
         if (c.graphs.size() >= GRAPH_CACHE_MAX) {
@@ -1017,7 +126,7 @@ static ak_status radix_sort_t(Workspace *ws, void *keys, uint32_t *perm, int64_t
         }
         hipGraph_t g = nullptr;
         AK_HIP(hipStreamBeginCapture(c.capture, hipStreamCaptureModeRelaxed));
-        ak_status lr = launch_run<DT, false>(c.capture, ws, st, keys, perm, n, nplaces, nullptr, 0);
+        ak_status lr = record(c.capture);
         hipError_t ce = hipStreamEndCapture(c.capture, &g);
         if (lr != AK_OK) {
             if (g) (void)hipGraphDestroy(g);
@@ -1030,22 +139,36 @@ static ak_status radix_sort_t(Workspace *ws, void *keys, uint32_t *perm, int64_t
         if (ie != hipSuccess) return hip_fail(ie, "hipGraphInstantiate");
         it = c.graphs.emplace(key, ex).first;
     }
-    ProfScope ps("radix_graph", s);
-    AK_HIP(hipGraphLaunch(it->second, s));
+    ProfScope ps("radix_graph", ws->stream);
+    AK_HIP(hipGraphLaunch(it->second, ws->stream));
     return AK_OK;
+}
+
+// ------------------------------------------------------------ entries
+template <int DT>
+static ak_status std_t(Workspace *ws, void *keys, uint32_t *perm, int64_t n, int slot) {
+    if (perm) return radix_sort_t<DT, M_PERM>(ws, keys, perm, n, slot);
+    return radix_sort_t<DT, M_KEYS>(ws, keys, nullptr, n, slot);
 }
 
 ak_status radix_sort(Workspace *ws, int dt, void *keys, uint32_t *perm, int64_t n, int slot) {
     switch (dt) {
-    case AK_I32: return radix_sort_t<AK_I32>(ws, keys, perm, n, slot);
-    case AK_I64: return radix_sort_t<AK_I64>(ws, keys, perm, n, slot);
-    case AK_U32: return radix_sort_t<AK_U32>(ws, keys, perm, n, slot);
-    case AK_U64: return radix_sort_t<AK_U64>(ws, keys, perm, n, slot);
-    case AK_F32: return radix_sort_t<AK_F32>(ws, keys, perm, n, slot);
-    case AK_F64: return radix_sort_t<AK_F64>(ws, keys, perm, n, slot);
+    case AK_I32: return std_t<AK_I32>(ws, keys, perm, n, slot);
+    case AK_I64: return std_t<AK_I64>(ws, keys, perm, n, slot);
+    case AK_U32: return std_t<AK_U32>(ws, keys, perm, n, slot);
+    case AK_U64: return std_t<AK_U64>(ws, keys, perm, n, slot);
+    case AK_F32: return std_t<AK_F32>(ws, keys, perm, n, slot);
+    case AK_F64: return std_t<AK_F64>(ws, keys, perm, n, slot);
     }
+    if (dtype_ok(dt)) return radix_sort_wide(ws, dt, perm ? M_PERM : M_KEYS, keys, perm, n, slot);
     set_error("radix_sort: unknown dtype");
     return AK_ERR_UNSUPPORTED_DTYPE;
+}
+
+ak_status radix_sort_mode(Workspace *ws, int dt, int mode, void *keys, void *vals, int64_t n, int slot) {
+    if (mode == M_KEYS || mode == M_PERM) return radix_sort(ws, dt, keys, (uint32_t *)vals, n, slot);
+    if (dtype_std(dt)) return radix_sort_pairs_std(ws, dt, mode, keys, vals, n, slot);
+    return radix_sort_wide(ws, dt, mode, keys, vals, n, slot);
 }
 
 // ------------------------------------------- code-digit passes (learned)
@@ -1066,8 +189,8 @@ static ak_status code_partition_t(Workspace *ws, void *keys, uint32_t n, const f
     uint32_t epoch;
     if ((r = ws_next_epoch(ws, &epoch)) != AK_OK) return r;
     const int nplaces = (cb + RADIX_BITS - 1) / RADIX_BITS;
-    return launch_run<DT, true>(ws->stream, ws, ws->state + slot, keys, nullptr, n, nplaces, model, cb,
-                                rmi_stage_bytes(L));
+    return launch_run<DT, M_KEYS, true>(ws->stream, ws, ws->state + slot, keys, nullptr, n, nplaces, model, cb,
+                                        rmi_stage_bytes(L));
 }
 
 ak_status code_partition(Workspace *ws, int dt, void *keys, uint32_t n, const float *model, int L, int cb,

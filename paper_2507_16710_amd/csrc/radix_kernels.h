@@ -1,14 +1,38 @@
 // Kernel argument blocks and launch shapes of the radix kernels.
 #pragma once
 
+#include <type_traits>
+
 #include "ak_internal.h"
 
 namespace ak {
 
+// What a radix run carries with the keys:
+//   M_KEYS    nothing (sort in place);
+//   M_PERM    uint32 indices: made in the first pass, the last pass writes
+//             only them (sortperm);
+//   M_PAIRS4  a 4-byte payload per key, moved with the keys through every
+//             pass, both ending in the caller's buffers (sort by key);
+//   M_PAIRS8  the same with an 8-byte payload;
+//   M_LOWMEM  uint32 indices only: each pass gathers its keys through them
+//             from the untouched key array, so no key scratch is needed
+//             (sortperm with the smallest scratch).
+enum : int { M_KEYS = 0, M_PERM = 1, M_PAIRS4 = 2, M_PAIRS8 = 3, M_LOWMEM = 4 };
+template <int M>
+struct ModeT {
+    static constexpr bool VAL = M != M_KEYS;
+    static constexpr bool PAIRS = M == M_PAIRS4 || M == M_PAIRS8;
+    using V = typename std::conditional<M == M_PAIRS8, uint64_t, uint32_t>::type;
+    // value class of the shape tables: 0 none, 1 four bytes, 2 eight bytes
+    static constexpr int VCLASS = M == M_KEYS ? 0 : (M == M_PAIRS8 ? 2 : 1);
+};
+constexpr int mode_vclass(int m) { return m == M_KEYS ? 0 : (m == M_PAIRS8 ? 2 : 1); }
+
 struct OnesweepArgs {
-    void *keys;           // sort: keys (in/out); sortperm: the const keys
+    void *keys;           // sort / pairs: keys (in/out); sortperm / lowmem: the const keys
     void *t0, *t1;        // key scratch buffers
-    uint32_t *v0, *perm;  // value scratch, permutation output
+    void *v0, *v1;        // value scratch buffers
+    void *vals;           // sortperm / lowmem: the permutation output; pairs: the caller's payload
     uint64_t *lookback;   // tiles x RADIX look-back words, then groups x RADIX group words
     RunState *st;
     const float *model;   // learned model (code digits only)
@@ -46,13 +70,21 @@ struct OsShape {
     bool pers;
 };
 constexpr int OS_NVAR = 4;
-constexpr OsShape OS_SHAPES[2][2][OS_NVAR] = {
-    // 32-bit keys: keys only, with values
+// [key class: 16/32-bit, 64-bit, 128-bit][value class: none, 4 bytes,
+// 8 bytes][variant]
+constexpr OsShape OS_SHAPES[3][3][OS_NVAR] = {
+    // 16- and 32-bit keys
     {{{16, 8, false}, {16, 6, false}, {16, 12, false}, {16, 16, false}},
-     {{8, 12, false}, {16, 8, false}, {16, 6, false}, {16, 12, true}}},
-    // 64-bit keys: keys only, with values
+     {{8, 12, false}, {16, 8, false}, {16, 6, false}, {16, 12, true}},
+     {{16, 4, false}, {16, 6, false}, {8, 8, false}, {16, 8, true}}},
+    // 64-bit keys
     {{{16, 4, false}, {16, 8, false}, {16, 12, true}, {8, 24, true}},
-     {{16, 4, false}, {8, 6, false}, {16, 8, true}, {8, 16, true}}},
+     {{16, 4, false}, {8, 6, false}, {16, 8, true}, {8, 16, true}},
+     {{16, 4, false}, {8, 6, false}, {16, 6, true}, {8, 12, true}}},
+    // 128-bit keys (16 bytes staged per key)
+    {{{16, 4, false}, {8, 4, false}, {16, 3, false}, {8, 8, true}},
+     {{16, 2, false}, {8, 4, false}, {16, 4, false}, {8, 6, true}},
+     {{16, 2, false}, {8, 4, false}, {16, 4, false}, {8, 6, true}}},
 };
 // Shapes of the code-digit passes (keys only; one persistent workgroup per
 // CU next to the staged model table, so registers are not the limit and
@@ -62,16 +94,33 @@ constexpr OsShape OS_CODE_SHAPES[2][OS_NVAR] = {
     {{16, 8, true}, {16, 6, true}, {16, 12, true}, {8, 12, true}},
     {{8, 20, true}, {16, 8, true}, {8, 16, true}, {16, 10, true}},
 };
-int os_variant(int dt, bool val, int64_t n);
+// default shape per (key class, value class): see radix.hip for the sweep
+constexpr int OS_DEFAULT[3][3] = {{3, 3, 3}, {3, 2, 3}, {0, 1, 1}};
+int os_variant(int dt, int mode, int64_t n);
 int os_code_variant(int dt);
-inline int os_tile(int dt, bool val, int64_t n) {
-    const OsShape s = OS_SHAPES[key_bits(dt) == 64][val][os_variant(dt, val, n)];
+inline int os_tile(int dt, int mode, int64_t n) {
+    const OsShape s = OS_SHAPES[key_class(dt)][mode_vclass(mode)][os_variant(dt, mode, n)];
     return s.w * 64 * s.ipt;
 }
 inline int os_code_tile(int dt) {
     const OsShape s = OS_CODE_SHAPES[key_bits(dt) == 64][os_code_variant(dt)];
     return s.w * 64 * s.ipt;
 }
+// Whether every variant of the table is compiled for (dtype, mode): the
+// six original key types without payloads; the others compile their
+// default variant (and, keys only, the small-input one).
+constexpr bool os_all_variants(int dt, int mode) { return dt >= AK_I32 && dt <= AK_F64 && mode <= M_PERM; }
+
+// Reduce-then-scan passes ($AK_OS_RTS=1) instead of one-sweep passes, and
+// the tiles per reduce-then-scan chunk.
+bool os_rts();
+uint32_t rts_chunk_tiles(uint32_t tiles);
+
+// Radix runs of the modes and key types radix.hip does not instantiate:
+// the six 32/64-bit key types with payloads or the low-memory sortperm
+// (radix_pairs.hip), and the 16- and 128-bit key types (radix_wide.hip).
+ak_status radix_sort_pairs_std(Workspace *ws, int dt, int mode, void *keys, void *vals, int64_t n, int slot);
+ak_status radix_sort_wide(Workspace *ws, int dt, int mode, void *keys, void *vals, int64_t n, int slot);
 
 template <typename U, bool VAL, int W, int IPT>
 struct SmallSmem {

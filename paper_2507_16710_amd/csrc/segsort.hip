@@ -6,10 +6,15 @@
 //                                 histograms, then one-sweep passes whose
 //                                 look-back stays inside the segment (tiles of
 //                                 all huge segments share persistent grids)
-//   long   (b_max < len < xl_min) one 1024-thread workgroup, multi-pass LSD
+//   long   (c_max < len < xl_min) one 1024-thread workgroup, multi-pass LSD
 //                                 radix through a scratch copy (one bucket per
 //                                 power of two, longest first, so the tail is
 //                                 short ones); its own persistent kernel
+//   big    (b_max < len <= c_max) one 512-thread workgroup, on-chip sort of
+//                                 up to 16384 keys (one read, one write; 32
+//                                 keys per lane, 256 registers); its own
+//                                 persistent kernel, segments above 8192 keys
+//                                 first
 //   medium (a_max < len <= b_max) one workgroup, on-chip sort
 //   short  (2 <= len <= a_max)    one wave per segment, on-chip sort
 // The on-chip classes share a second persistent kernel.  Their tile shapes
@@ -37,9 +42,17 @@ namespace ak {
 constexpr int SEG_W = 4;              // waves of a persistent workgroup
 constexpr int B_XL = 0;               // huge segments
 constexpr int NB_LONG = 24;           // long buckets 1..24: 32 - floor(log2(len))
-constexpr int B_MED = NB_LONG + 1;    // medium bucket
-constexpr int B_SHORT = NB_LONG + 2;  // short bucket
-constexpr int NB = NB_LONG + 3;
+constexpr int B_BIG2 = NB_LONG + 1;   // big bucket, above BIG_SPLIT keys
+constexpr int B_BIG1 = NB_LONG + 2;   // big bucket, up to BIG_SPLIT keys
+constexpr int B_MED = NB_LONG + 3;    // medium bucket
+constexpr int B_SHORT = NB_LONG + 4;  // short bucket
+constexpr int NB = NB_LONG + 5;
+constexpr int BIG_W = 8;              // waves of the big class's workgroup (256 VGPRs each)
+constexpr int BIG_SPLIT = BIG_W * 64 * 16;
+// keys per lane of the big class's largest tile (LDS: 128 KB of keys)
+template <typename U>
+constexpr int big_ipt() { return 32; }
+inline uint32_t big_cap(int) { return (uint32_t)BIG_W * 64u * 32u; }
 constexpr int XL_W = 8, XL_IPT = 8;   // huge-class tile: 4096 keys
 constexpr int XL_TILE = XL_W * 64 * XL_IPT;
 constexpr int XL_HT = 16;             // tiles per histogram work item
@@ -60,7 +73,7 @@ struct SegArgs {
     int64_t nseg;
     int64_t base;       // off[0]
     int64_t end;        // off[nseg]
-    uint32_t a_max, b_max, xl_min;
+    uint32_t a_max, b_max, c_max, xl_min;
     uint32_t xl_cap;    // room for huge segments in the arrays below
     uint32_t *xl_pre;   // xl_cap+1 tile prefix of the huge segments
     uint32_t *xl_tseg;  // huge segment of every tile
@@ -80,6 +93,7 @@ struct SegState {
     uint32_t next_item;     // work counter of the on-chip classes
     uint32_t nitems;
     uint32_t next_long;     // work counter of the long class
+    uint32_t next_big;      // work counter of the big class
     uint32_t error;
     uint32_t xl_count;      // huge segments (<= xl_cap)
     uint32_t xl_tiles;      // their tiles
@@ -97,16 +111,35 @@ struct SegTune {
     int xl_min = 32768;   // shortest segment of the huge class
 };
 
-__device__ __forceinline__ int seg_bucket(uint32_t len, uint32_t a_max, uint32_t b_max, uint32_t xl_min) {
+__device__ __forceinline__ int seg_bucket(uint32_t len, uint32_t a_max, uint32_t b_max, uint32_t c_max,
+                                          uint32_t xl_min) {
     if (len <= 1) return -1;
     if (len <= a_max) return B_SHORT;
     if (len <= b_max) return B_MED;
     if (len >= xl_min) return B_XL;
+    if (len <= c_max) return len > (uint32_t)BIG_SPLIT ? B_BIG2 : B_BIG1;
     const int lg = 31 - __builtin_clz(len);
     return 32 - lg < NB_LONG ? 32 - lg : NB_LONG;
 }
 
-__global__ void k_seg_setargs(SegArgs *a, SegArgs v) { *a = v; }
+// Writes the argument block.  With device_bounds the batch's ends are read
+// here from the CSR offsets, base = off[0] and end = off[nseg], and checked
+// against the key count `bound`: ends outside [0, bound] or decreasing set
+// the error word and empty the batch (every kernel then finds no work).
+__global__ void k_seg_setargs(SegArgs *a, SegArgs v, SegState *st, int device_bounds, int64_t bound) {
+    if (device_bounds) {
+        const int64_t b = v.off[0], e = v.hi[v.nseg - 1];
+        if (b < 0 || e < b || e > bound) {
+            atomicOr(&st->error, 1u);
+            v.nseg = 0;
+            v.base = v.end = 0;
+        } else {
+            v.base = b;
+            v.end = e;
+        }
+    }
+    *a = v;
+}
 
 // Also advances the look-back epoch (30-bit; 16 per call): on wrap the
 // words are cleared by k_xl_lbclear before any pass uses them.
@@ -121,6 +154,7 @@ __global__ void k_seg_reset(SegState *st) {
         st->next_item = 0;
         st->nitems = 0;
         st->next_long = 0;
+        st->next_big = 0;
         uint32_t e = st->epoch + 16;
         st->lb_clear = 0;
         if (e < 16 || e + 16 >= (1u << 30)) {
@@ -142,7 +176,7 @@ __global__ __launch_bounds__(256) void k_seg_count(const SegArgs *ap, SegState *
         if (hi < lo || lo < a.base || hi > a.end) {
             atomicOr(&st->error, 1u);
         } else {
-            const int b = seg_bucket((uint32_t)(hi - lo), a.a_max, a.b_max, a.xl_min);
+            const int b = seg_bucket((uint32_t)(hi - lo), a.a_max, a.b_max, a.c_max, a.xl_min);
             if (b >= 0) atomicAdd(&s_c[b], 1u);
         }
     }
@@ -173,7 +207,8 @@ __global__ __launch_bounds__(256) void k_seg_place(const SegArgs *ap, SegState *
     uint32_t mine = 0;
     if (s < a.nseg) {
         const int64_t lo = a.off[s], hi = a.hi[s];
-        if (hi >= lo && lo >= a.base && hi <= a.end) b = seg_bucket((uint32_t)(hi - lo), a.a_max, a.b_max, a.xl_min);
+        if (hi >= lo && lo >= a.base && hi <= a.end)
+            b = seg_bucket((uint32_t)(hi - lo), a.a_max, a.b_max, a.c_max, a.xl_min);
         if (b >= 0) mine = atomicAdd(&s_c[b], 1u);
     }
     __syncthreads();
@@ -199,7 +234,7 @@ __global__ __launch_bounds__(LONG_W * 64) __attribute__((amdgpu_waves_per_eu(WPE
     const SegArgs a = *ap;
     U *keys = (U *)a.keys;
     U *tmp = (U *)a.tmp;
-    const uint32_t first = st->start[B_XL + 1], med0 = st->start[B_MED];
+    const uint32_t first = st->start[B_XL + 1], med0 = st->start[B_BIG2];
     while (true) {
         if (threadIdx.x == 0) s_item = first + atomicAdd(&st->next_long, 1u);
         __syncthreads();
@@ -209,6 +244,38 @@ __global__ __launch_bounds__(LONG_W * 64) __attribute__((amdgpu_waves_per_eu(WPE
         const int64_t s = a.list[item];
         const int64_t lo = a.off[s], len = a.hi[s] - lo;
         sort_long<DT, LONG_W, LONG_IPT>(keys + lo, tmp + (lo - a.base), (uint32_t)len, sm);
+    }
+}
+
+// Big class: one 1024-thread workgroup per segment, sorted on chip; the
+// smaller tile shape for segments up to BIG_SPLIT keys (fewer idle lanes per
+// ranking step), the 128 KB one above.
+template <typename U>
+union BigSmem {
+    SmallSmem<U, false, BIG_W, 16> lo;
+    SmallSmem<U, false, BIG_W, big_ipt<U>()> hi;
+};
+
+template <int DT>
+__global__ __launch_bounds__(BIG_W * 64) void k_seg_big(const SegArgs *ap, SegState *st) {
+    using U = typename KT<DT>::U;
+    __shared__ BigSmem<U> sm;
+    __shared__ uint32_t s_item;
+    const SegArgs a = *ap;
+    U *keys = (U *)a.keys;
+    const uint32_t first = st->start[B_BIG2], end = st->start[B_MED];
+    while (true) {
+        if (threadIdx.x == 0) s_item = first + atomicAdd(&st->next_big, 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        __syncthreads();
+        if (item >= end) break;
+        const int64_t s = a.list[item];
+        const int64_t lo = a.off[s];
+        const uint32_t len = (uint32_t)(a.hi[s] - lo);
+        if (len <= (uint32_t)BIG_SPLIT) lds_sort_tile<DT, false, BIG_W, 16>(keys + lo, keys + lo, nullptr, len, sm.lo, threadIdx.x);
+        else lds_sort_tile<DT, false, BIG_W, big_ipt<U>()>(keys + lo, keys + lo, nullptr, len, sm.hi, threadIdx.x);
+        __syncthreads();
     }
 }
 
@@ -736,6 +803,14 @@ static int seg_long_variant() {
 }
 
 template <int DT>
+static ak_status launch_seg_big(hipStream_t s, const SegArgs *a, SegState *st) {
+    // 256 registers per lane: one workgroup per CU
+    hipLaunchKernelGGL((k_seg_big<DT>), dim3((unsigned)num_cus()), dim3(BIG_W * 64), 0, s, a, st);
+    AK_LAUNCH_CHECK("k_seg_big");
+    return AK_OK;
+}
+
+template <int DT>
 static ak_status launch_seg_long(hipStream_t s, const SegArgs *a, SegState *st) {
     if (seg_long_variant() == 0)
         hipLaunchKernelGGL((k_seg_long<DT, LONG_W / 2>), dim3((unsigned)num_cus() * 2), dim3(LONG_W * 64), 0, s, a,
@@ -806,6 +881,16 @@ static ak_status seg_launch_all(int dt, const SegTune &t, int64_t nseg, int grid
     }
     if (r != AK_OK) return r;
     switch (dt) {
+    case AK_I32: r = launch_seg_big<AK_I32>(s, a, st); break;
+    case AK_I64: r = launch_seg_big<AK_I64>(s, a, st); break;
+    case AK_U32: r = launch_seg_big<AK_U32>(s, a, st); break;
+    case AK_U64: r = launch_seg_big<AK_U64>(s, a, st); break;
+    case AK_F32: r = launch_seg_big<AK_F32>(s, a, st); break;
+    case AK_F64: r = launch_seg_big<AK_F64>(s, a, st); break;
+    default: r = AK_ERR_UNSUPPORTED_DTYPE;
+    }
+    if (r != AK_OK) return r;
+    switch (dt) {
     case AK_I32: return launch_seg_sort<AK_I32>(t, dim3(grid), s, a, st);
     case AK_I64: return launch_seg_sort<AK_I64>(t, dim3(grid), s, a, st);
     case AK_U32: return launch_seg_sort<AK_U32>(t, dim3(grid), s, a, st);
@@ -821,7 +906,7 @@ static ak_status seg_launch_all(int dt, const SegTune &t, int64_t nseg, int grid
 // digit counts, tile maps) plus the huge segments' look-back words.
 struct SegLayout {
     SegTune t;
-    uint32_t a_max, b_max, xl_min, xl_cap;
+    uint32_t a_max, b_max, c_max, xl_min, xl_cap;
     size_t off_pre, off_desc, off_hist, off_tseg, off_apre, off_amap, misc2_need;
     size_t max_tiles, lb_words;
 };
@@ -841,6 +926,7 @@ static SegLayout seg_layout(int dt, int64_t n, int64_t nseg) {
     const uint32_t cap_b = 256u * (uint32_t)t.ipt_b;
     L.b_max = t.b_max > 0 ? std::min<uint32_t>((uint32_t)t.b_max, cap_b) : cap_b;
     L.xl_min = (uint32_t)std::max(t.xl_min, (int)L.b_max + 1);
+    L.c_max = big_cap(dt);
     L.xl_cap = (uint32_t)std::min<int64_t>(nseg, n / L.xl_min + 1);
     L.max_tiles = (size_t)n / XL_TILE + L.xl_cap + 1;
     L.off_pre = al((size_t)nseg * 4);
@@ -868,8 +954,11 @@ size_t segmented_temp_bytes(int dt, int64_t n, int64_t nseg) { return segmented_
 // Sorts the ranges keys[lo[s] .. hi[s]) (base <= lo <= hi <= end, ranges
 // disjoint) through the captured launch sequence; `tmp` holds end - base
 // keys of scratch laid out like keys[base ..).
+// device_bounds: base and end are read from the offsets on the device (the
+// caller gives only the key count as `end`, base 0), so the call never
+// waits for the device unless scratch must grow.
 static ak_status seg_run(Workspace *ws, int dt, void *keys, const int64_t *lo, const int64_t *hi, int64_t nseg,
-                         int64_t base, int64_t end, void *tmp) {
+                         int64_t base, int64_t end, void *tmp, bool device_bounds = false) {
     hipStream_t s = ws->stream;
     const int64_t n = end - base;
     const SegLayout L = seg_layout(dt, n, nseg);
@@ -907,6 +996,7 @@ static ak_status seg_run(Workspace *ws, int dt, void *keys, const int64_t *lo, c
     v.a_max = L.a_max;
     v.b_max = L.b_max;
     v.xl_min = L.xl_min;
+    v.c_max = L.c_max;
     v.xl_cap = L.xl_cap;
     v.xl_pre = (uint32_t *)((char *)ws->misc2 + L.off_pre);
     v.xl_desc = (XlDesc *)((char *)ws->misc2 + L.off_desc);
@@ -917,7 +1007,7 @@ static ak_status seg_run(Workspace *ws, int dt, void *keys, const int64_t *lo, c
     v.xl_amap = (uint32_t *)((char *)ws->misc2 + L.off_amap);
     v.xl_lb = (uint64_t *)ws->aux[3];
     v.xl_lb_words = ws->aux_bytes[3] / 8;
-    hipLaunchKernelGGL(k_seg_setargs, dim3(1), dim3(1), 0, s, c.args, v);
+    hipLaunchKernelGGL(k_seg_setargs, dim3(1), dim3(1), 0, s, c.args, v, c.state, (int)device_bounds, end);
     AK_LAUNCH_CHECK("k_seg_setargs");
 
     SegPlanKey key{dt, nseg, t.ipt_a, t.ipt_b, grid};
@@ -962,6 +1052,17 @@ ak_status segmented_sort(Workspace *ws, int dt, void *keys, const int64_t *offse
     ak_status r = ws_arena_fits(ws, segmented_temp_bytes(dt, n, nseg));
     if (r != AK_OK) return r;
     return seg_run(ws, dt, keys, offsets, offsets + 1, nseg, ends[0], ends[1], nullptr);
+}
+
+ak_status segmented_sort_n(Workspace *ws, int dt, void *keys, int64_t n, const int64_t *offsets, int64_t nseg) {
+    if (nseg >= (int64_t(1) << 31)) {
+        set_error("nseg >= 2^31");
+        return AK_ERR_INVALID_ARG;
+    }
+    if (n == 0) return AK_OK;
+    ak_status r = ws_arena_fits(ws, segmented_temp_bytes(dt, n, nseg));
+    if (r != AK_OK) return r;
+    return seg_run(ws, dt, keys, offsets, offsets + 1, nseg, 0, n, nullptr, true);
 }
 
 ak_status segmented_sort_ranges(Workspace *ws, int dt, void *keys, const int64_t *lo, const int64_t *hi,

@@ -40,7 +40,7 @@ def test_argument_errors_without_device_work():
     assert lib.ak_sort(fake, -1, 2, None) == 1
     assert lib.ak_sort(None, 10, 2, None) == 1
     assert lib.ak_sort(fake, 10, 0, None) == 2
-    assert lib.ak_sort(fake, 10, 7, None) == 2
+    assert lib.ak_sort(fake, 10, 11, None) == 2
     assert lib.ak_sort(fake, 1 << 32, 2, None) == 1
     # the accepted range ends at 2^31 keys (32-bit indices and grid-stride
     # loops): one key more is refused before any launch by every entry point
@@ -58,6 +58,15 @@ def test_argument_errors_without_device_work():
     assert lib.ak_segmented_sort(fake, fake, -1, 3, None) == 1
     assert lib.ak_segmented_sort(fake, fake, 0, 3, None) == 0
     assert lib.ak_segmented_sort(None, fake, 5, 3, None) == 1
+    # the asynchronous form takes the key count: checked before any launch
+    assert lib.ak_segmented_sort_n(fake, -1, fake, 3, 3, None) == 1
+    assert lib.ak_segmented_sort_n(fake, (1 << 31) + 1, fake, 3, 3, None) == 1
+    assert lib.ak_segmented_sort_n(fake, 100, fake, -1, 3, None) == 1
+    assert lib.ak_segmented_sort_n(None, 100, fake, 3, 3, None) == 1
+    assert lib.ak_segmented_sort_n(fake, 100, None, 3, 3, None) == 1
+    assert lib.ak_segmented_sort_n(fake, 100, fake, 3, 9, None) == 2
+    assert lib.ak_segmented_sort_n(fake, 100, fake, 0, 3, None) == 0
+    assert lib.ak_segmented_sort_n(fake, 0, fake, 3, 3, None) == 0
     bad = (ctypes.c_int32 * 8)(4095, 12, 0, 0, 0, 0, 0, 0)   # leaves not a power of two
     assert lib.ak_sort_learned(fake, 10, 4, bad, None, None) == 1
     assert lib.ak_rmi_codes(fake, 10, 4, fake, 25, fake, None) == 1
@@ -79,6 +88,47 @@ def test_argument_errors_without_device_work():
     assert lib.ak_sort_noalloc(fake, -1, 2, None) == 1
     assert lib.ak_sort_noalloc(fake, 10, 0, None) == 2
     assert lib.ak_sort_noalloc(fake, 0, 2, None) == 0
+
+
+def test_new_sort_family_argument_errors():
+    """Sort by key, the low-memory sortperm and the 16/128-bit key types:
+    bad arguments refused before any launch; the calls that take only the
+    six 32/64-bit types refuse the others."""
+    lib = _lib()
+    vp = ctypes.c_void_p
+    k, v = vp(0x1000), vp(0x10000000)
+    for dt in (2, 7, 10):
+        assert lib.ak_sort_by_key(k, v, 10, dt, 3, None) == 1            # val_bytes not 4 or 8
+        assert lib.ak_sort_by_key(k, None, 10, dt, 4, None) == 1         # vals NULL
+        assert lib.ak_sort_by_key(k, vp(0x1004), 10, dt, 8, None) == 1   # vals overlaps keys
+        assert lib.ak_sort_by_key(k, v, (1 << 31) + 1, dt, 4, None) == 1
+        assert lib.ak_sort_by_key(k, v, 0, dt, 4, None) == 0
+        assert lib.ak_sortperm_lowmem(k, None, 10, dt, None) == 1
+        assert lib.ak_sortperm_lowmem(k, vp(0x1004), 10, dt, None) == 1
+        assert lib.ak_sortperm_lowmem(k, v, 0, dt, None) == 0
+    assert lib.ak_sort_by_key(k, v, 10, 11, 4, None) == 2
+    assert lib.ak_sortperm_lowmem(k, v, 10, 0, None) == 2
+    # 16- and 128-bit keys: sort family only
+    for dt in (7, 8, 9, 10):
+        assert lib.ak_segmented_sort(k, v, 3, dt, None) == 2
+        assert lib.ak_sort_learned(k, 100, dt, None, None, None) == 2
+        assert lib.ak_accumulate(k, v, 100, dt, 1, None) == 2
+        assert lib.ak_searchsortedfirst(k, 100, v, 10, dt, vp(0x20000000), None) == 2
+        assert lib.ak_rmi_codes(k, 100, dt, v, 12, vp(0x20000000), None) == 2
+        assert lib.ak_temp_bytes(2, 1 << 20, dt) == 0
+    # scratch: sort by key holds two payload buffers more than sort; the
+    # low-memory sortperm only the indices (and per-tile words)
+    n = 1 << 24
+    for dt, kb in ((5, 4), (2, 8), (7, 2), (9, 16)):
+        s_ = lib.ak_temp_bytes(0, n, dt)
+        kv = lib.ak_temp_bytes(5, n, dt)
+        low = lib.ak_temp_bytes(6, n, dt)
+        full = lib.ak_temp_bytes(1, n, dt)
+        assert kv >= 2 * n * kb + 2 * n * 8
+        # indices plus one look-back word per (tile, digit)
+        assert 4 * n <= low <= 4 * n * 1.5 + (1 << 22) and low < full, (dt, low, full)
+        assert kb < 4 or low * 2 < full
+        assert s_ >= 2 * n * kb
 
 
 def test_temp_bytes_predictable():

@@ -63,7 +63,7 @@ def test_outside_range_untouched_and_repeated_calls():
 def test_bad_offsets_reported():
     k = torch.zeros(100, dtype=torch.int32, device="cuda")
     off = torch.tensor([0, 50, 40, 100], dtype=torch.int64, device="cuda")
-    ak.segmented_sort_(k, off, dtype="u32")
+    ak.segmented_sort_(k, off, dtype="u32", check=False)
     with pytest.raises(ak.AKError):
         ak.check_device_error()
     ak.check_device_error()        # the flag was cleared
@@ -79,6 +79,30 @@ def test_workload4_scaled():
     keys, off = synth.workload4(nseg=4000, seed=2)
     k = keys.numpy().view(np.uint32)
     assert np.array_equal(_seg(k, off.numpy(), "u32"), oracle.segsort(k, off.numpy()))
+
+
+def test_segmented_sort_returns_before_the_device_finishes():
+    """The segmented sort never waits for the device (ak_segmented_sort_n:
+    the batch's ends are read on the device): right after the call on the
+    100,000-segment batch the stream still has work, and the result is
+    every segment sorted with its own multiset."""
+    keys, off = synth.workload4(device="cuda")
+    nseg = off.numel() - 1
+    seg_id = torch.repeat_interleave(torch.arange(nseg, device="cuda"), off[1:] - off[:-1])
+    seg_fp = segment_fingerprints(keys, seg_id, nseg)
+    work = keys.clone()
+    ak.segmented_sort_(work, off, dtype="u32")        # scratch and graph ready
+    work.copy_(keys)
+    torch.cuda.synchronize()
+    ak.segmented_sort_(work, off, dtype="u32", check=False)
+    busy = not torch.cuda.current_stream().query()
+    torch.cuda.synchronize()
+    ak.check_device_error()
+    assert busy, "the call waited for the device"
+    assert torch.equal(segment_fingerprints(work, seg_id, nseg), seg_fp)
+    k = signed_order_key(work, "u32")
+    same = seg_id[1:] == seg_id[:-1]
+    assert bool((k[1:][same] >= k[:-1][same]).all())
 
 
 def test_workload4_full_size():

@@ -32,7 +32,8 @@ def test_arena_paths_bit_exact(dt):
     n = 300_001
     nseg = len(segments(n)) - 1
     need = max(ak.temp_bytes("sort", n, dt), ak.temp_bytes("sortperm", n, dt),
-               ak.temp_bytes_segmented(n, nseg, dt), ak.temp_bytes("learned", n, dt))
+               ak.temp_bytes_segmented(n, nseg, dt), ak.temp_bytes("learned", n, dt),
+               ak.temp_bytes("sort_by_key", n, dt), ak.temp_bytes("sortperm_lowmem", n, dt))
     arena = torch.empty(need, dtype=torch.uint8, device="cuda")
     ak.set_workspace(arena)
     try:
@@ -48,6 +49,15 @@ def test_arena_paths_bit_exact(dt):
             t = to_gpu(k, dt)
             p = ak.sortperm(t, dtype=dt)
             assert np.array_equal(p.cpu().numpy().view(np.uint32), oracle.sortperm(k))
+            print(f"arena dt={dt} round={it} sortperm_lowmem", flush=True)
+            p = ak.sortperm_lowmem(t, dtype=dt)
+            assert np.array_equal(p.cpu().numpy().view(np.uint32), oracle.sortperm(k))
+            print(f"arena dt={dt} round={it} sort_by_key", flush=True)
+            t = to_gpu(k, dt)
+            v = torch.arange(k.size, dtype=torch.int64, device="cuda") * 3 - 7
+            ak.sort_by_key_(t, v, dtype=dt)
+            rk, rv = oracle.sort_by_key(k, (np.arange(k.size, dtype=np.int64) * 3 - 7))
+            assert np.array_equal(bits(to_host(t, dt)), bits(rk)) and np.array_equal(v.cpu().numpy(), rv)
             print(f"arena dt={dt} round={it} segmented", flush=True)
             t = to_gpu(k, dt)
             ak.segmented_sort_(t, torch.from_numpy(off).cuda(), dtype=dt)
@@ -80,15 +90,19 @@ def test_arena_paths_bit_exact(dt):
 
 
 def test_segment_offsets_beyond_keys_are_refused():
-    """Offsets that run past the key array are refused by the binding before
-    the library is called (the C call sees only a raw pointer)."""
-    t = torch.zeros(1000, dtype=torch.int64, device="cuda")
+    """Offsets that run past the key array (or start below 0) are found on
+    the device against the key count the call is given: the error word is
+    set and no key is touched."""
+    t = torch.arange(1000, 0, -1, dtype=torch.int64, device="cuda")
+    before = t.clone()
     off = torch.tensor([0, 500, 2000], dtype=torch.int64, device="cuda")
-    with pytest.raises(ValueError):
+    with pytest.raises(ak.AKError):
         ak.segmented_sort_(t, off, dtype="i64")
     off = torch.tensor([-1, 500], dtype=torch.int64, device="cuda")
-    with pytest.raises(ValueError):
+    with pytest.raises(ak.AKError):
         ak.segmented_sort_(t, off, dtype="i64")
+    assert torch.equal(t, before)
+    ak.check_device_error()                      # cleared by the raise
 
 
 def test_arena_prefix_route_exact_size():
