@@ -9,7 +9,7 @@ sweep takes seconds) under every tuning the library accepts:
   ipt_b      keys per lane of the one-workgroup class  (8, 16; 32 for 32-bit)
   grid_mult  persistent workgroups per CU             (2, 4, 8)
   b_max      on-chip limit of the one-workgroup class (full capacity, half)
-  xl_min     shortest segment of the many-workgroup class (8192, 32768, 131072)
+  xl_min     shortest segment of the many-workgroup class (8192 ... 131072)
 
 and writes the fastest per key width to ``tune_gfx950.json`` next to
 ``libak.so`` (read by the library at its first segmented call).  Every
@@ -33,7 +33,7 @@ TABLE = os.path.join(HERE, "tune_gfx950.json")
 
 def candidates(key_bits: int):
     b_opts = (8, 16, 32) if key_bits == 32 else (8, 16)
-    for ipt_a, ipt_b, gm, xl in itertools.product((2, 4), b_opts, (2, 4, 8), (8192, 32768, 131072)):
+    for ipt_a, ipt_b, gm, xl in itertools.product((2, 4), b_opts, (2, 4, 8), (8192, 16384, 32768, 65536, 131072)):
         cap = 256 * ipt_b
         for b_max in (0, cap // 2):
             yield {"ipt_a": ipt_a, "ipt_b": ipt_b, "grid_mult": gm, "b_max": b_max, "xl_min": xl}
