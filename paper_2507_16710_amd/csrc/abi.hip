@@ -1,6 +1,7 @@
 // The C ABI (include/ak.h): argument checks, per-(device, stream) workspace
 // cache, error reporting, and dispatch into the drivers.
 #include <algorithm>
+#include <cstddef>
 #include <map>
 #include <mutex>
 #include <string>
@@ -277,8 +278,8 @@ ak_status ak_sort_route(int64_t *info, ak_stream_t stream) {
     if (!ws) return AK_ERR_HIP;
     AK_HIP(hipStreamSynchronize(ws->stream));
     if (ws->last_route == 0) return AK_OK;
-    RunState st;
-    AK_HIP(hipMemcpy(&st, ws->state, sizeof(RunState), hipMemcpyDeviceToHost));
+    RunState st;   // the fields before the digit counts
+    AK_HIP(hipMemcpy(&st, ws->state, offsetof(RunState, hist), hipMemcpyDeviceToHost));
     info[0] = st.pfx_active ? (int64_t)st.pfx_places : 0;
     info[1] = st.q;
     if (ws->last_route == 2 && st.pfx_active) return prefix_counts(ws, info + 2);

@@ -147,9 +147,13 @@ struct PassDesc {
     int32_t shift;   // bit offset of the digit
 };
 
+// Copies of the digit counts that the histogram's workgroups add into
+// (workgroup g into copy g % HIST_REP), so that fewer device-scope atomics
+// queue on one address; the digit scan sums them.
+constexpr int HIST_REP = 8;
+
 // Device-resident state of one radix run.
 struct RunState {
-    uint32_t hist[MAX_PLACES][RADIX];  // digit counts per place
     uint32_t base[MAX_PLACES][RADIX];  // exclusive digit offsets per place
     uint32_t tile_ctr[MAX_PLACES];     // dynamic tile ids per pass
     PassDesc desc[MAX_PLACES];
@@ -164,6 +168,9 @@ struct RunState {
     int32_t pfx_shift;                 // bit offset of the prefix field
     uint32_t pfx_mask;                 // prefix field mask (after the shift)
     uint32_t pfx_places;               // digit places in the prefix field
+    // digit counts per place, in HIST_REP copies; zero between runs (the
+    // digit scan clears what it read)
+    uint32_t hist[HIST_REP][MAX_PLACES][RADIX];
 };
 
 // ------------------------------------------------------------- errors

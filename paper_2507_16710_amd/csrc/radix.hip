@@ -48,6 +48,14 @@ int os_variant(int dt, int mode, int64_t n) {
     return OS_DEFAULT[key_class(dt)][mode_vclass(mode)];
 }
 
+int hist_variant() {
+    static const int v = [] {
+        const int e = env_variant("AK_HIST_VARIANT");
+        return e >= 0 ? e : 0;
+    }();
+    return v;
+}
+
 int os_code_variant(int dt) {
     static const int forced = env_variant("AK_OS_CODE_VARIANT");
     return forced >= 0 ? forced : OS_CODE_DEFAULT[key_bits(dt) == 64];

@@ -28,12 +28,12 @@
 namespace ak {
 
 // ---------------------------------------------------------------- init
-// Zeroes the run's counters and takes the next 16 look-back epochs from the
-// workspace counter (restarting at 16 before 2^30; the host mirrors this and
-// clears the look-back words at that point).
+// Zeroes the run's counters (the digit counts are zero already: the digit
+// scan of the previous run cleared them) and takes the next 16 look-back
+// epochs from the workspace counter (restarting at 16 before 2^30; the host
+// mirrors this and clears the look-back words at that point).
 static __global__ void k_run_init(RunState *st, uint32_t *epoch_dev) {
     const int tid = threadIdx.x;
-    for (int i = tid; i < MAX_PLACES * RADIX; i += blockDim.x) (&st->hist[0][0])[i] = 0;
     if (tid < MAX_PLACES) st->tile_ctr[tid] = 0;
     if (tid == 0) {
         st->hist_done = 0;
@@ -49,7 +49,8 @@ static __global__ void k_run_init(RunState *st, uint32_t *epoch_dev) {
 // so that each pass kernel can pick its source and destination buffers
 // without a host round trip.  Run by one workgroup of B >= 256 threads,
 // reading counts that other workgroups accumulated with device-scope
-// atomics.
+// atomics into the HIST_REP copies, which it sums and then clears for the
+// next run.
 //
 // pfx_cap > 0 (key-only runs that can finish on chip): if the top k = 2..4
 // places spread the keys so that the expected largest run of equal prefix,
@@ -67,10 +68,18 @@ __device__ void scan_places(RunState *st, uint32_t n, int nplaces, uint32_t *s_b
     // every place's count in flight at once (one round trip, not one per place)
     uint32_t cnt[MAXP];
 #pragma unroll
+    for (int p = 0; p < MAXP; ++p) {
+        cnt[p] = 0;
+        if (p < nplaces && tid < RADIX) {
+#pragma unroll
+            for (int r = 0; r < HIST_REP; ++r)
+                cnt[p] += __hip_atomic_load(&st->hist[r][p][tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+#pragma unroll
     for (int p = 0; p < MAXP; ++p)
-        cnt[p] = (p < nplaces && tid < RADIX)
-                     ? __hip_atomic_load(&st->hist[p][tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                     : 0u;
+        if (p < nplaces && tid < RADIX)
+            for (int r = 0; r < HIST_REP; ++r) st->hist[r][p][tid] = 0;
     if (tid < MAX_PLACES) s_pmax[tid] = 0;
     __syncthreads();
 #pragma unroll
@@ -130,6 +139,26 @@ __device__ void scan_places(RunState *st, uint32_t n, int nplaces, uint32_t *s_b
 }
 
 // ---------------------------------------------------------- histogram
+// End of a histogram workgroup: the last one to finish (after every other
+// workgroup's counts are visible) turns the counts into digit offsets.
+// s_buf holds at least RADIX words.
+template <int B, int MAXP>
+__device__ __forceinline__ void hist_tail(RunState *st, uint32_t n, int nplaces, uint32_t *s_buf,
+                                          uint32_t pfx_cap) {
+    __shared__ int s_last;
+    __shared__ uint32_t s_wsum[B / 64];
+    __shared__ int s_active[MAX_PLACES];
+    __shared__ uint32_t s_pmax[MAX_PLACES];
+    const int tid = threadIdx.x;
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) s_last = atomicAdd(&st->hist_done, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    scan_places<B, MAXP>(st, n, nplaces, s_buf, s_wsum, s_active, s_pmax, pfx_cap);
+}
+
 // One read of the keys; counts the digit of every place.  LDS counters per
 // workgroup, then one global atomic per nonzero bin.  The lanes of a wave
 // that hold the first lane's digit add their count once instead of as
@@ -207,20 +236,125 @@ __global__ __launch_bounds__(CODE ? 1024 : 256) void k_hist(const typename KT<DT
         }
     }
     __syncthreads();
+    uint32_t(*gh)[RADIX] = st->hist[blockIdx.x % HIST_REP];
     for (int i = tid; i < nplaces * RADIX; i += B)
-        if (s_h[i]) atomicAdd(&st->hist[i / RADIX][i % RADIX], s_h[i]);
-    // the last workgroup to finish turns the counts into digit offsets
-    __shared__ int s_last;
-    __shared__ uint32_t s_wsum[B / 64];
-    __shared__ int s_active[MAX_PLACES];
-    __shared__ uint32_t s_pmax[MAX_PLACES];
-    __threadfence();
+        if (s_h[i]) atomicAdd(&gh[i / RADIX][i % RADIX], s_h[i]);
+    hist_tail<B, HP>(st, n, nplaces, s_h, pfx_cap);
+}
+
+// Histogram of the keys of 16-, 32- and 64-bit key types.  Every lane of a
+// wave adds to its own copy of the counters (copy = lane % 32, 32 copies of
+// every counter word), so the 32 lanes that one LDS cycle serves always hit
+// 32 distinct banks, whatever their digits; shared counters make random
+// digits collide in banks (about 3 conflict cycles per access measured on
+// 2^28 float32 keys).  The copies hold 16-bit counts, bins d and d + 128 of
+// a place in the two halves of one word (16 KB of LDS per digit place);
+// they are folded into 32-bit registers often enough that no 16-bit count
+// can wrap, and added to the global copies once per workgroup.  One
+// workgroup of B threads per CU for 64-bit keys (128 KB), two for narrower
+// keys; ITEMS keys per lane per batch.
+template <int DT, int B, int ITEMS>
+__global__ __launch_bounds__(B) void k_hist_lp(const typename KT<DT>::U *__restrict__ keys, uint32_t n,
+                                               RunState *st, uint32_t pfx_cap) {
+    using U = typename KT<DT>::U;
+    constexpr int NP = (int)sizeof(U);   // digit places
+    constexpr int ROWS = NP * 128;       // counter words per copy
+    constexpr int NR = (ROWS + B - 1) / B;
+    // adds one 16-bit count takes per batch at most: two lanes of every wave
+    // share a copy, ITEMS keys each
+    constexpr int PER_BATCH = (B / 32) * ITEMS;
+    constexpr int FOLD = 32768 / PER_BATCH;  // batches between folds
+    static_assert(FOLD >= 1, "16-bit counts must not wrap");
+    __shared__ uint32_t s_h[ROWS * 32];
+    const int tid = threadIdx.x;
+    const uint32_t copy = (uint32_t)tid & 31u;
+    {
+        uint4 *z = reinterpret_cast<uint4 *>(s_h);
+        for (int i = tid; i < ROWS * 8; i += B) z[i] = make_uint4(0, 0, 0, 0);
+    }
+    uint32_t lo[NR], hi[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) lo[j] = hi[j] = 0;
+    // every copy of a counter word summed into registers (and cleared when
+    // more keys follow); lane r starts at copy r % 32, so a wave's 32 lanes
+    // of one LDS cycle read 32 distinct banks
+    auto fold = [&](bool clear) {
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            const int r = j * B + tid;
+            if (r < ROWS) {
+                uint32_t a = 0, b = 0;
+#pragma unroll 8
+                for (int k = 0; k < 32; ++k) {
+                    const int idx = r * 32 + ((k + r) & 31);
+                    const uint32_t v = s_h[idx];
+                    a += v & 0xFFFFu;
+                    b += v >> 16;
+                    if (clear) s_h[idx] = 0;
+                }
+                lo[j] += a;
+                hi[j] += b;
+            }
+        }
+    };
+    // the digits of four places held in one 32-bit word of the key image
+    auto count4 = [&](uint32_t x, int p0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (p0 + q >= NP) break;
+            const uint32_t w = (x >> (8 * q)) & 127u;
+            const uint32_t half = (x >> (8 * q + 7)) & 1u;
+            atomicAdd(&s_h[((p0 + q) * 128 + w) * 32 + copy], half * 0xFFFFu + 1u);
+        }
+    };
+    auto count = [&](U v) {
+        const U t = KT<DT>::image(v);
+        count4((uint32_t)t, 0);
+        if constexpr (NP > 4) count4((uint32_t)((uint64_t)t >> 32), 4);
+    };
     __syncthreads();
-    if (tid == 0) s_last = atomicAdd(&st->hist_done, 1u) == gridDim.x - 1;
+    const uint32_t per = (uint32_t)B * ITEMS;
+    const uint32_t stride = gridDim.x * per;
+    int batches = 0;
+    for (uint32_t base = blockIdx.x * per; base < n; base += stride) {
+        U v[ITEMS];
+        if (base + per <= n) {
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it) v[it] = __builtin_nontemporal_load(keys + base + it * B + tid);
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it) count(v[it]);
+        } else {
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it) {
+                const uint32_t i = base + it * B + tid;
+                v[it] = i < n ? __builtin_nontemporal_load(keys + i) : U(0);
+            }
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it)
+                if (base + it * B + tid < n) count(v[it]);
+        }
+        if (++batches == FOLD) {
+            __syncthreads();
+            fold(true);
+            __syncthreads();
+            batches = 0;
+        }
+    }
     __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    scan_places<B, HP>(st, n, nplaces, s_h, s_wsum, s_active, s_pmax, pfx_cap);
+    fold(false);
+    uint32_t(*h)[MAX_PLACES][RADIX] = st->hist;
+    const int rep = blockIdx.x % HIST_REP;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const int r = j * B + tid;
+        if (r < ROWS) {
+            const int p = r >> 7, w = r & 127;
+            if (lo[j]) atomicAdd(&h[rep][p][w], lo[j]);
+            if (hi[j]) atomicAdd(&h[rep][p][w + 128], hi[j]);
+        }
+    }
+    __syncthreads();   // s_h is reused by the digit scan
+    hist_tail<B, NP>(st, n, NP, s_h, pfx_cap);
 }
 
 // ----------------------------------------------------- one-sweep pass
@@ -865,15 +999,38 @@ static ak_status launch_run(hipStream_t s, Workspace *ws, RunState *st, void *ke
     using U = typename KT<DT>::U;
     hipLaunchKernelGGL(k_run_init, dim3(1), dim3(256), 0, s, st, ws->epoch_dev);
     AK_LAUNCH_CHECK("k_run_init");
-    constexpr int HB = CODE ? 1024 : 256;
-    const uint32_t hgrid = (uint32_t)std::min<int64_t>(((int64_t)n + HB * 8 - 1) / (HB * 8),
-                                                       (int64_t)num_cus() * (CODE ? 2 : 8));
     {
         ProfScope ps(CODE ? "code_hist" : "digit_hist", s);
-        hipLaunchKernelGGL((k_hist<DT, CODE>), dim3(hgrid), dim3(HB), stage, s, (const U *)keys, n, nplaces, st,
-                           model, cb, (int)(stage > 0), pfx_cap);
+        // the lane-private histogram for 16- to 64-bit key digits (shape
+        // $AK_HIST_VARIANT 0..2; 3: the shared-counter kernel)
+        const int hv = hist_variant();
+        if constexpr (!CODE && key_bits(DT) <= 64) {
+            if (hv < 3) {
+                constexpr int NP = (int)sizeof(U);
+                auto launch = [&](auto bc, auto ic) {
+                    constexpr int B = decltype(bc)::value, IT = decltype(ic)::value;
+                    // workgroups per CU: 160 KB of LDS, 2048 threads
+                    const int per_cu = std::min(160 / (NP * 16), 2048 / B);
+                    const uint32_t grid = (uint32_t)std::min<int64_t>(((int64_t)n + B * IT - 1) / (B * IT),
+                                                                      (int64_t)num_cus() * per_cu);
+                    hipLaunchKernelGGL((k_hist_lp<DT, B, IT>), dim3(grid), dim3(B), 0, s, (const U *)keys, n, st,
+                                       pfx_cap);
+                };
+                if (hv == 0) launch(std::integral_constant<int, 1024>{}, std::integral_constant<int, 8>{});
+                else if (hv == 1) launch(std::integral_constant<int, 1024>{}, std::integral_constant<int, 16>{});
+                else launch(std::integral_constant<int, 512>{}, std::integral_constant<int, 16>{});
+                AK_LAUNCH_CHECK("k_hist_lp");
+            }
+        }
+        if (CODE || key_bits(DT) > 64 || hv >= 3) {
+            constexpr int HB = CODE ? 1024 : 256;
+            const uint32_t hgrid = (uint32_t)std::min<int64_t>(((int64_t)n + HB * 8 - 1) / (HB * 8),
+                                                               (int64_t)num_cus() * (CODE ? 2 : 8));
+            hipLaunchKernelGGL((k_hist<DT, CODE>), dim3(hgrid), dim3(HB), stage, s, (const U *)keys, n, nplaces,
+                               st, model, cb, (int)(stage > 0), pfx_cap);
+            AK_LAUNCH_CHECK("k_hist");
+        }
     }
-    AK_LAUNCH_CHECK("k_hist");
     OnesweepArgs a{};
     a.keys = keys;
     a.t0 = ws->keys0;

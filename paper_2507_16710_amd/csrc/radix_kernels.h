@@ -114,6 +114,10 @@ constexpr bool os_all_variants(int dt, int mode) { return dt >= AK_I32 && dt <= 
 // Reduce-then-scan passes ($AK_OS_RTS=1) instead of one-sweep passes, and
 // the tiles per reduce-then-scan chunk.
 bool os_rts();
+// Shape of the digit histogram of 16- to 64-bit keys: 0..2 the lane-private
+// kernel (1024 x 8, 1024 x 16, 512 x 16 keys per batch), 3 the shared-
+// counter one ($AK_HIST_VARIANT overrides the default).
+int hist_variant();
 uint32_t rts_chunk_tiles(uint32_t tiles);
 
 // Radix runs of the modes and key types radix.hip does not instantiate:

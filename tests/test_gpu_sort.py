@@ -180,3 +180,31 @@ def test_active_pass_counts(dt):
             assert np.array_equal(bits(got), bits(oracle.sort(k))), (dt, q, n)
             if n == 300_001 and q in (1, 3):
                 assert np.array_equal(_run_perm(k, dt), oracle.sortperm(k)), (dt, q, n)
+
+
+@pytest.mark.parametrize("dt", ["u32", "u64"])
+def test_histogram_folds_on_skewed_keys(dt):
+    """Sizes at which every histogram workgroup folds its 16-bit LDS counts
+    into registers several times (above 2**28 64-bit and 2**29 32-bit keys
+    at one workgroup per CU), on keys whose top bytes are constant and whose
+    lowest byte is 0x55 for half of them: one bin of each constant place
+    takes every count, so a wrapped count would show as wrong digit offsets
+    or a constant place taken for active.  Exactly the three low places
+    run."""
+    kb = 4 if dt == "u32" else 8
+    n = (5 << 28) + 12345 if kb == 4 else (5 << 27) + 12345
+    g = torch.Generator(device="cuda").manual_seed(77)
+    low = torch.randint(0, 1 << 24, (n,), generator=g, device="cuda", dtype=torch.int64)
+    half = torch.rand(n, generator=g, device="cuda") < 0.5
+    low = torch.where(half, (low & ~0xFF) | 0x55, low)
+    if kb == 4:
+        t = (low | (0xAB << 24)).to(torch.int32)
+    else:
+        t = low | (0x123456789A << 24)
+    del low, half
+    fp = fingerprint(t)
+    print(f"histogram folds dt={dt} n={n}", flush=True)
+    ak.sort_(t, dtype=dt)
+    route = ak.sort_route()
+    assert route["passes"] == 3 and route["prefix_places"] == 0, route
+    assert is_sorted(t, dt) and fingerprint(t) == fp
