@@ -160,7 +160,6 @@ struct RunState {
     int32_t q;                         // number of active passes
     uint32_t error;                    // device-detected input error flag
     uint32_t epoch_base;               // look-back epoch of this run's first pass
-    uint32_t hist_done;                // histogram workgroups finished
     // prefix-partitioned sort (decided with the digit offsets): the passes
     // order the keys by the `pfx_places` top active places only, and the
     // chunk sort finishes every run of equal prefix on chip

@@ -36,7 +36,6 @@ static __global__ void k_run_init(RunState *st, uint32_t *epoch_dev) {
     const int tid = threadIdx.x;
     if (tid < MAX_PLACES) st->tile_ctr[tid] = 0;
     if (tid == 0) {
-        st->hist_done = 0;
         uint32_t e = *epoch_dev + 16;
         if (e + 16 >= (1u << 30)) e = 16;
         *epoch_dev = e;
@@ -47,10 +46,9 @@ static __global__ void k_run_init(RunState *st, uint32_t *epoch_dev) {
 // Exclusive digit offsets per place; a place where one digit holds every
 // key is inactive (its pass would be a copy).  Active passes are numbered
 // so that each pass kernel can pick its source and destination buffers
-// without a host round trip.  Run by one workgroup of B >= 256 threads,
-// reading counts that other workgroups accumulated with device-scope
-// atomics into the HIST_REP copies, which it sums and then clears for the
-// next run.
+// without a host round trip.  Run by one workgroup of B >= 256 threads
+// after the histogram kernel (whose workgroups added their counts into the
+// HIST_REP copies); it sums the copies and clears them for the next run.
 //
 // pfx_cap > 0 (key-only runs that can finish on chip): if the top k = 2..4
 // places spread the keys so that the expected largest run of equal prefix,
@@ -66,20 +64,25 @@ __device__ void scan_places(RunState *st, uint32_t n, int nplaces, uint32_t *s_b
                             int *s_active, uint32_t *s_pmax, uint32_t pfx_cap) {
     const int tid = threadIdx.x;
     // every place's count in flight at once (one round trip, not one per place)
+    // every copy of every place in flight at once (one round trip; the
+    // places a run does not have hold zeros)
     uint32_t cnt[MAXP];
 #pragma unroll
-    for (int p = 0; p < MAXP; ++p) {
-        cnt[p] = 0;
-        if (p < nplaces && tid < RADIX) {
+    for (int p = 0; p < MAXP; ++p) cnt[p] = 0;
+    if (tid < RADIX) {
+        uint32_t v[MAXP][HIST_REP];
 #pragma unroll
-            for (int r = 0; r < HIST_REP; ++r)
-                cnt[p] += __hip_atomic_load(&st->hist[r][p][tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        for (int p = 0; p < MAXP; ++p)
+#pragma unroll
+            for (int r = 0; r < HIST_REP; ++r) v[p][r] = st->hist[r][p][tid];
+#pragma unroll
+        for (int p = 0; p < MAXP; ++p)
+#pragma unroll
+            for (int r = 0; r < HIST_REP; ++r) {
+                cnt[p] += v[p][r];
+                st->hist[r][p][tid] = 0;
+            }
     }
-#pragma unroll
-    for (int p = 0; p < MAXP; ++p)
-        if (p < nplaces && tid < RADIX)
-            for (int r = 0; r < HIST_REP; ++r) st->hist[r][p][tid] = 0;
     if (tid < MAX_PLACES) s_pmax[tid] = 0;
     __syncthreads();
 #pragma unroll
@@ -87,10 +90,11 @@ __device__ void scan_places(RunState *st, uint32_t n, int nplaces, uint32_t *s_b
         if (p >= nplaces) break;
         const uint32_t c = cnt[p];
         const int trivial = __syncthreads_or(tid < RADIX && c == n);
-        if (tid < RADIX) {
-            s_buf[tid] = c;
-            if (c) atomicMax(&s_pmax[p], c);
-        }
+        uint32_t m = tid < RADIX ? c : 0u;   // the wave's largest count, then one LDS atomic
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
+        if (tid < RADIX) s_buf[tid] = c;
+        if ((tid & 63) == 0 && m) atomicMax(&s_pmax[p], m);
         __syncthreads();
         block_exscan<B, RADIX>(s_buf, s_buf, s_wsum, tid);
         if (tid < RADIX) st->base[p][tid] = s_buf[tid];
@@ -139,27 +143,22 @@ __device__ void scan_places(RunState *st, uint32_t n, int nplaces, uint32_t *s_b
 }
 
 // ---------------------------------------------------------- histogram
-// End of a histogram workgroup: the last one to finish (after every other
-// workgroup's counts are visible) turns the counts into digit offsets.
-// s_buf holds at least RADIX words.
-template <int B, int MAXP>
-__device__ __forceinline__ void hist_tail(RunState *st, uint32_t n, int nplaces, uint32_t *s_buf,
-                                          uint32_t pfx_cap) {
-    __shared__ int s_last;
-    __shared__ uint32_t s_wsum[B / 64];
+// The digit scan as its own one-workgroup kernel after the histogram: the
+// kernel boundary makes every workgroup's counts visible.  (A "last
+// workgroup finishes" handoff inside the histogram needs a device-scope
+// release fence in every workgroup, which on gfx950 writes back the L2 of
+// its XCD: about 50 us at one million keys.)
+template <int MAXP>
+__global__ __launch_bounds__(256) void k_scan_places(RunState *st, uint32_t n, int nplaces, uint32_t pfx_cap) {
+    __shared__ uint32_t s_buf[RADIX];
+    __shared__ uint32_t s_wsum[4];
     __shared__ int s_active[MAX_PLACES];
     __shared__ uint32_t s_pmax[MAX_PLACES];
-    const int tid = threadIdx.x;
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) s_last = atomicAdd(&st->hist_done, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    scan_places<B, MAXP>(st, n, nplaces, s_buf, s_wsum, s_active, s_pmax, pfx_cap);
+    scan_places<256, MAXP>(st, n, nplaces, s_buf, s_wsum, s_active, s_pmax, pfx_cap);
 }
 
-// One read of the keys; counts the digit of every place.  LDS counters per
+// Histogram of code digits (learned sort) and of 128-bit keys: one read of
+// the keys, counting the digit of every place in LDS counters shared by the
 // workgroup, then one global atomic per nonzero bin.  The lanes of a wave
 // that hold the first lane's digit add their count once instead of as
 // conflicting LDS atomics on one address (all 64 for a constant high place
@@ -169,7 +168,7 @@ __device__ __forceinline__ void hist_tail(RunState *st, uint32_t n, int nplaces,
 template <int DT, bool CODE>
 __global__ __launch_bounds__(CODE ? 1024 : 256) void k_hist(const typename KT<DT>::U *__restrict__ keys, uint32_t n,
                                                             int nplaces, RunState *st, const float *model, int cb,
-                                                            int staged, uint32_t pfx_cap) {
+                                                            int staged) {
     extern __shared__ float4 s_leaves[];
     using U = typename KT<DT>::U;
     constexpr int B = CODE ? 1024 : 256, ITEMS = 8;
@@ -239,7 +238,6 @@ __global__ __launch_bounds__(CODE ? 1024 : 256) void k_hist(const typename KT<DT
     uint32_t(*gh)[RADIX] = st->hist[blockIdx.x % HIST_REP];
     for (int i = tid; i < nplaces * RADIX; i += B)
         if (s_h[i]) atomicAdd(&gh[i / RADIX][i % RADIX], s_h[i]);
-    hist_tail<B, HP>(st, n, nplaces, s_h, pfx_cap);
 }
 
 // Histogram of the keys of 16-, 32- and 64-bit key types.  Every lane of a
@@ -253,11 +251,16 @@ __global__ __launch_bounds__(CODE ? 1024 : 256) void k_hist(const typename KT<DT
 // can wrap, and added to the global copies once per workgroup.  One
 // workgroup of B threads per CU for 64-bit keys (128 KB), two for narrower
 // keys; ITEMS keys per lane per batch.
-template <int DT, int B, int ITEMS>
+// CODE: the digits of the model codes (at most 24 bits: three places, of
+// which the first `nplaces` are counted), with the model's leaf table staged
+// in dynamic LDS when `staged`.
+template <int DT, int B, int ITEMS, bool CODE = false>
 __global__ __launch_bounds__(B) void k_hist_lp(const typename KT<DT>::U *__restrict__ keys, uint32_t n,
-                                               RunState *st, uint32_t pfx_cap) {
+                                               RunState *st, int nplaces = 0, const float *model = nullptr,
+                                               int cb = 0, int staged = 0) {
+    extern __shared__ float4 s_leaves[];
     using U = typename KT<DT>::U;
-    constexpr int NP = (int)sizeof(U);   // digit places
+    constexpr int NP = CODE ? 3 : (int)sizeof(U);   // digit places
     constexpr int ROWS = NP * 128;       // counter words per copy
     constexpr int NR = (ROWS + B - 1) / B;
     // adds one 16-bit count takes per batch at most: two lanes of every wave
@@ -312,23 +315,52 @@ __global__ __launch_bounds__(B) void k_hist_lp(const typename KT<DT>::U *__restr
         count4((uint32_t)t, 0);
         if constexpr (NP > 4) count4((uint32_t)((uint64_t)t >> 32), 4);
     };
+    RmiHead h{};
+    float scale = 0.f;
+    if constexpr (CODE) {
+        h = rmi_head(model);
+        rmi_stage(model, staged ? s_leaves : nullptr);
+        scale = (float)(1u << cb);
+    }
+    // model codes of a batch: one uniform branch per batch, so the staged
+    // table is read with LDS instructions
+    auto codes = [&](const U (&v)[ITEMS], uint32_t (&c)[ITEMS]) {
+        if constexpr (CODE) {
+            auto run = [&](const RmiLeaf *lv) {
+#pragma unroll
+                for (int it = 0; it < ITEMS; ++it) c[it] = rmi_code(h, lv, KT<DT>::image(v[it]), cb, scale);
+            };
+            if (staged) run(reinterpret_cast<const RmiLeaf *>(s_leaves));
+            else run(rmi_leaves(model));
+        }
+    };
     __syncthreads();
     const uint32_t per = (uint32_t)B * ITEMS;
     const uint32_t stride = gridDim.x * per;
     int batches = 0;
     for (uint32_t base = blockIdx.x * per; base < n; base += stride) {
         U v[ITEMS];
-        if (base + per <= n) {
+        const bool full = base + per <= n;
+        if (full) {
 #pragma unroll
             for (int it = 0; it < ITEMS; ++it) v[it] = __builtin_nontemporal_load(keys + base + it * B + tid);
-#pragma unroll
-            for (int it = 0; it < ITEMS; ++it) count(v[it]);
         } else {
 #pragma unroll
             for (int it = 0; it < ITEMS; ++it) {
                 const uint32_t i = base + it * B + tid;
                 v[it] = i < n ? __builtin_nontemporal_load(keys + i) : U(0);
             }
+        }
+        if constexpr (CODE) {
+            uint32_t c[ITEMS];
+            codes(v, c);
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it)
+                if (full || base + it * B + tid < n) count4(c[it], 0);
+        } else if (full) {
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it) count(v[it]);
+        } else {
 #pragma unroll
             for (int it = 0; it < ITEMS; ++it)
                 if (base + it * B + tid < n) count(v[it]);
@@ -342,19 +374,18 @@ __global__ __launch_bounds__(B) void k_hist_lp(const typename KT<DT>::U *__restr
     }
     __syncthreads();
     fold(false);
-    uint32_t(*h)[MAX_PLACES][RADIX] = st->hist;
+    uint32_t(*gh)[MAX_PLACES][RADIX] = st->hist;
     const int rep = blockIdx.x % HIST_REP;
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         const int r = j * B + tid;
-        if (r < ROWS) {
+        // (code digits: only the places the run has; the others stay zero)
+        if (r < ROWS && (!CODE || (r >> 7) < nplaces)) {
             const int p = r >> 7, w = r & 127;
-            if (lo[j]) atomicAdd(&h[rep][p][w], lo[j]);
-            if (hi[j]) atomicAdd(&h[rep][p][w + 128], hi[j]);
+            if (lo[j]) atomicAdd(&gh[rep][p][w], lo[j]);
+            if (hi[j]) atomicAdd(&gh[rep][p][w + 128], hi[j]);
         }
     }
-    __syncthreads();   // s_h is reused by the digit scan
-    hist_tail<B, NP>(st, n, NP, s_h, pfx_cap);
 }
 
 // ----------------------------------------------------- one-sweep pass
@@ -1004,8 +1035,10 @@ static ak_status launch_run(hipStream_t s, Workspace *ws, RunState *st, void *ke
         // the lane-private histogram for 16- to 64-bit key digits (shape
         // $AK_HIST_VARIANT 0..2; 3: the shared-counter kernel)
         const int hv = hist_variant();
+        bool done = false;
         if constexpr (!CODE && key_bits(DT) <= 64) {
             if (hv < 3) {
+                done = true;
                 constexpr int NP = (int)sizeof(U);
                 auto launch = [&](auto bc, auto ic) {
                     constexpr int B = decltype(bc)::value, IT = decltype(ic)::value;
@@ -1013,8 +1046,7 @@ static ak_status launch_run(hipStream_t s, Workspace *ws, RunState *st, void *ke
                     const int per_cu = std::min(160 / (NP * 16), 2048 / B);
                     const uint32_t grid = (uint32_t)std::min<int64_t>(((int64_t)n + B * IT - 1) / (B * IT),
                                                                       (int64_t)num_cus() * per_cu);
-                    hipLaunchKernelGGL((k_hist_lp<DT, B, IT>), dim3(grid), dim3(B), 0, s, (const U *)keys, n, st,
-                                       pfx_cap);
+                    hipLaunchKernelGGL((k_hist_lp<DT, B, IT>), dim3(grid), dim3(B), 0, s, (const U *)keys, n, st);
                 };
                 if (hv == 0) launch(std::integral_constant<int, 1024>{}, std::integral_constant<int, 8>{});
                 else if (hv == 1) launch(std::integral_constant<int, 1024>{}, std::integral_constant<int, 16>{});
@@ -1022,15 +1054,31 @@ static ak_status launch_run(hipStream_t s, Workspace *ws, RunState *st, void *ke
                 AK_LAUNCH_CHECK("k_hist_lp");
             }
         }
-        if (CODE || key_bits(DT) > 64 || hv >= 3) {
+        // code digits: the lane-private kernel next to the staged table (one
+        // workgroup per CU: 48 KB of counters, up to 64 KB of table)
+        if constexpr (CODE) {
+            if (hv < 3 && nplaces <= 3) {
+                done = true;
+                constexpr int B = 1024, IT = 8;
+                const uint32_t grid =
+                    (uint32_t)std::min<int64_t>(((int64_t)n + B * IT - 1) / (B * IT), (int64_t)num_cus());
+                hipLaunchKernelGGL((k_hist_lp<DT, B, IT, true>), dim3(grid), dim3(B), stage, s, (const U *)keys, n,
+                                   st, nplaces, model, cb, (int)(stage > 0));
+                AK_LAUNCH_CHECK("k_hist_lp");
+            }
+        }
+        if (!done) {
             constexpr int HB = CODE ? 1024 : 256;
             const uint32_t hgrid = (uint32_t)std::min<int64_t>(((int64_t)n + HB * 8 - 1) / (HB * 8),
                                                                (int64_t)num_cus() * (CODE ? 2 : 8));
             hipLaunchKernelGGL((k_hist<DT, CODE>), dim3(hgrid), dim3(HB), stage, s, (const U *)keys, n, nplaces,
-                               st, model, cb, (int)(stage > 0), pfx_cap);
+                               st, model, cb, (int)(stage > 0));
             AK_LAUNCH_CHECK("k_hist");
         }
     }
+    constexpr int HP = CODE ? 4 : (int)sizeof(U);
+    hipLaunchKernelGGL((k_scan_places<HP>), dim3(1), dim3(256), 0, s, st, n, nplaces, pfx_cap);
+    AK_LAUNCH_CHECK("k_scan_places");
     OnesweepArgs a{};
     a.keys = keys;
     a.t0 = ws->keys0;

@@ -116,7 +116,8 @@ constexpr bool os_all_variants(int dt, int mode) { return dt >= AK_I32 && dt <= 
 bool os_rts();
 // Shape of the digit histogram of 16- to 64-bit keys: 0..2 the lane-private
 // kernel (1024 x 8, 1024 x 16, 512 x 16 keys per batch), 3 the shared-
-// counter one ($AK_HIST_VARIANT overrides the default).
+// counter one, also for code digits ($AK_HIST_VARIANT overrides the
+// default).
 int hist_variant();
 uint32_t rts_chunk_tiles(uint32_t tiles);
 
