@@ -279,9 +279,13 @@ size_t radix_temp_bytes(int dtype, int64_t n, bool perm);
 // the runs of equal prefix, then the segmented radix sort of the runs that
 // exceed a chunk.  Every launch exits at once when the run took plain
 // passes.
-size_t prefix_finish_bytes(int dtype, int64_t n);
+size_t prefix_finish_bytes(int dtype, int64_t n, bool small);
 ak_status prefix_reserve(Workspace *ws, int dtype, int64_t n);
-ak_status prefix_finish(Workspace *ws, int dtype, void *keys, int64_t n, const RunState *st);
+// Launches on s.  small: fixed launches only, so that the run can be
+// captured (fallback runs sorted by one workgroup each instead of by the
+// segmented sort); otherwise s must be the workspace's stream.
+ak_status prefix_finish(Workspace *ws, hipStream_t s, int dtype, void *keys, int64_t n, const RunState *st,
+                        bool small);
 // Chunk capacity of the prefix finish; a run of equal prefix up to this
 // length is sorted on chip.
 int prefix_chunk_keys();

@@ -375,34 +375,43 @@ struct PrefixCoder {
 };
 
 // Smallest i >= q with code(i) != c (or n); codes are nondecreasing in the
-// position.  Gallops, then bisects (single thread).
+// position.  Called by all 64 lanes of one wave (same arguments, same
+// result in every lane): a 64-ary search.  Each round probes 64 positions
+// at once; while none differs the stride grows 64-fold, then each round
+// narrows the bracket [first unknown, first known different] 64-fold.  A
+// run of up to 63 keys takes one round trip, a run of L keys about
+// 2 log64(L) (a one-thread gallop-and-bisect takes 2 log2(L) dependent
+// loads).
 template <int DT, typename CD>
 __device__ uint32_t next_code_change(const typename KT<DT>::U *keys, uint32_t n, uint32_t q, uint32_t c,
                                      const CD &cd) {
-    if (q >= n || cd(keys[q]) != c) return q;
-    uint32_t good = q;  // code(good) == c
-    uint64_t step = 1;
-    uint32_t bad = n;   // first known position with a different code (or n)
+    const uint64_t lane = threadIdx.x & 63;
+    uint64_t lo = q, hi = n;  // the answer lies in [lo, hi]; hi differs (or is n)
+    uint64_t stride = 1;
+    bool growing = true;
     while (true) {
-        const uint64_t probe = (uint64_t)good + step;
-        if (probe >= n) break;
-        if (cd(keys[probe]) != c) {
-            bad = (uint32_t)probe;
-            break;
+        const uint64_t i = lo + lane * stride;
+        const bool diff = i >= hi || cd(keys[i]) != c;
+        const uint64_t m = ballot64(diff);
+        if (m == 0) {
+            // lo + 63 * stride has code c
+            lo += 63 * stride + 1;
+            if (growing) stride *= 64;
+            continue;
         }
-        good = (uint32_t)probe;
-        step <<= 1;
+        const uint64_t j = (uint64_t)__builtin_ctzll(m);
+        const uint64_t cand = lo + j * stride < hi ? lo + j * stride : hi;
+        if (j == 0 || stride == 1) return (uint32_t)cand;
+        // lo + (j - 1) * stride has code c, cand differs
+        hi = cand;
+        lo += (j - 1) * stride + 1;
+        growing = false;
+        stride = stride / 64 > 0 ? stride / 64 : 1;
     }
-    while (bad - good > 1) {
-        const uint32_t mid = good + (bad - good) / 2;
-        if (cd(keys[mid]) != c) bad = mid;
-        else good = mid;
-    }
-    return bad;
 }
 
 // A piece boundary: p itself if p is 0, n, or the first key of a code run;
-// otherwise the start of the next code run.
+// otherwise the start of the next code run (one wave, as above).
 template <int DT, typename CD>
 __device__ uint32_t piece_boundary(const typename KT<DT>::U *keys, uint32_t n, uint32_t p, const CD &cd) {
     if (p == 0 || p >= n) return p >= n ? n : 0;
@@ -452,9 +461,10 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(WPE))) v
     }
     const uint64_t p0 = (uint64_t)blockIdx.x * piece;
     const uint64_t p1 = std::min<uint64_t>(p0 + piece, n);
-    if (tid == 0) {
-        sm.bound[0] = piece_boundary<DT>(keys, n, (uint32_t)p0, cd);
-        sm.bound[1] = piece_boundary<DT>(keys, n, (uint32_t)p1, cd);
+    // the two ends at once, one wave each
+    if (w < 2) {
+        const uint32_t b = piece_boundary<DT>(keys, n, (uint32_t)(w == 0 ? p0 : p1), cd);
+        if (lane == 0) sm.bound[w] = b;
     }
     __syncthreads();
     uint32_t pos = sm.bound[0];
@@ -508,11 +518,13 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(WPE))) v
             const uint32_t q = sm.clast != sm.code_next ? len : sm.cut;
             if (q == 0) {
                 // one code spans past the chunk: hand the whole run to the fallback
-                if (tid == 0) {
+                if (w == 0) {
                     const uint32_t run_end = next_code_change<DT>(keys, end, pos + len, sm.code0, cd);
-                    const uint32_t slot = atomicAdd(&ls->fb_count, 1u);
-                    fb[slot] = FbRun{pos, run_end - pos};
-                    sm.cut = run_end;
+                    if (lane == 0) {
+                        const uint32_t slot = atomicAdd(&ls->fb_count, 1u);
+                        fb[slot] = FbRun{pos, run_end - pos};
+                        sm.cut = run_end;
+                    }
                 }
                 __syncthreads();
                 pos = sm.cut;
@@ -837,19 +849,44 @@ static size_t prefix_aux_bytes(uint32_t cap) {
     return 256 + (((size_t)cap * sizeof(FbRun) + 255) & ~size_t(255)) + (size_t)cap * 16;
 }
 
-size_t prefix_finish_bytes(int dt, int64_t n) {
+size_t prefix_finish_bytes(int dt, int64_t n, bool small) {
     const uint32_t cap = prefix_fb_cap(n);
-    return ((prefix_aux_bytes(cap) + 255) & ~size_t(255)) + segmented_scratch_bytes(dt, n, cap, false);
+    return ((prefix_aux_bytes(cap) + 255) & ~size_t(255)) + (small ? 0 : segmented_scratch_bytes(dt, n, cap, false));
 }
 
 ak_status prefix_reserve(Workspace *ws, int, int64_t n) {
     return ws_reserve(ws, &ws->aux[5], &ws->aux_bytes[5], prefix_aux_bytes(prefix_fb_cap(n)));
 }
 
+// Fallback of the prefix finish of small runs (at most a few million keys):
+// every workgroup takes fallback runs from the list and sorts each with the
+// one-workgroup LSD sort through the scratch copy.  One fixed launch, so a
+// small sort's whole launch sequence can be captured and replayed; the runs
+// a chunk cannot hold are rare there (the route is chosen only when the
+// expected run is a quarter chunk).
+constexpr int PFX_FB_W = 16, PFX_FB_IPT = 4;
 template <int DT>
-static ak_status prefix_finish_t(Workspace *ws, void *keys, int64_t n64, const RunState *st) {
+__global__ __launch_bounds__(PFX_FB_W * 64) void k_pfx_fallback(typename KT<DT>::U *keys, typename KT<DT>::U *tmp,
+                                                                const FbRun *fb, LearnedState *ls) {
     using U = typename KT<DT>::U;
-    hipStream_t s = ws->stream;
+    __shared__ LongSmem<U, PFX_FB_W, PFX_FB_IPT> sm;
+    __shared__ uint32_t s_r;
+    while (true) {
+        if (threadIdx.x == 0) s_r = atomicAdd(&ls->fb_next, 1u);
+        __syncthreads();
+        const uint32_t r = s_r;
+        __syncthreads();
+        if (r >= ls->fb_count) break;
+        const FbRun run = fb[r];
+        if (threadIdx.x == 0) atomicAdd(&ls->fb_keys, (unsigned long long)run.len);
+        sort_long<DT, PFX_FB_W, PFX_FB_IPT>(keys + run.start, tmp + run.start, run.len, sm);
+    }
+}
+
+template <int DT>
+static ak_status prefix_finish_t(Workspace *ws, hipStream_t s, void *keys, int64_t n64, const RunState *st,
+                                 bool small) {
+    using U = typename KT<DT>::U;
     const uint32_t n = (uint32_t)n64;
     const uint32_t cap = prefix_fb_cap(n64);
     char *base = (char *)ws->aux[5];
@@ -859,8 +896,10 @@ static ak_status prefix_finish_t(Workspace *ws, void *keys, int64_t n64, const R
     int64_t *hi = lo + cap;
     hipLaunchKernelGGL(k_learned_reset, dim3(1), dim3(256), 0, s, ls, (uint32_t *)nullptr, 0u);
     AK_LAUNCH_CHECK("k_learned_reset");
+    // small runs: one chunk per workgroup, so every CU works at once
     const uint32_t pieces_target = (uint32_t)num_cus() * 16;
-    const uint32_t piece = std::max<uint32_t>(PFX_CAP * 4, (n + pieces_target - 1) / pieces_target);
+    const uint32_t piece =
+        small ? PFX_CAP : std::max<uint32_t>(PFX_CAP * 4, (n + pieces_target - 1) / pieces_target);
     const uint32_t npieces = (n + piece - 1) / piece;
     {
         ProfScope ps("prefix_chunk_sort", s);
@@ -876,6 +915,13 @@ static ak_status prefix_finish_t(Workspace *ws, void *keys, int64_t n64, const R
         }
     }
     AK_LAUNCH_CHECK("k_chunk_sort");
+    if (small) {
+        ProfScope ps("prefix_fallback", s);
+        hipLaunchKernelGGL((k_pfx_fallback<DT>), dim3((unsigned)num_cus()), dim3(PFX_FB_W * 64), 0, s, (U *)keys,
+                           (U *)ws->keys0, (const FbRun *)fb, ls);
+        AK_LAUNCH_CHECK("k_pfx_fallback");
+        return AK_OK;
+    }
     const uint32_t fgrid = std::min<uint32_t>((cap + 255) / 256, 4096);
     hipLaunchKernelGGL(k_fb_ranges, dim3(fgrid), dim3(256), 0, s, (const FbRun *)fb, ls, lo, hi, cap);
     AK_LAUNCH_CHECK("k_fb_ranges");
@@ -892,8 +938,8 @@ ak_status prefix_counts(Workspace *ws, int64_t out[3]) {
     return AK_OK;
 }
 
-ak_status prefix_finish(Workspace *ws, int dt, void *keys, int64_t n, const RunState *st) {
-    AK_DT_SWITCH(dt, prefix_finish_t, ws, keys, n, st)
+ak_status prefix_finish(Workspace *ws, hipStream_t s, int dt, void *keys, int64_t n, const RunState *st, bool small) {
+    AK_DT_SWITCH(dt, prefix_finish_t, ws, s, keys, n, st, small)
 }
 
 // aux[0] of one learned call: sample keys | model | learned state |

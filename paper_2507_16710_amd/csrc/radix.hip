@@ -77,7 +77,7 @@ size_t radix_temp_bytes_mode(int dt, int mode, int64_t n) {
     if (mode != M_LOWMEM) b += 2 * al256((size_t)n * kb);
     if (mode == M_PERM || mode == M_LOWMEM) b += al256((size_t)n * 4);
     if (mode == M_PAIRS4 || mode == M_PAIRS8) b += 2 * al256((size_t)n * (mode == M_PAIRS8 ? 8 : 4));
-    if (mode == M_KEYS && prefix_dtype(dt) && n > PREFIX_MIN) b += prefix_finish_bytes(dt, n);
+    if (mode == M_KEYS && prefix_dtype(dt) && n > PREFIX_MIN) b += prefix_finish_bytes(dt, n, n <= GRAPH_MAX);
     return b;
 }
 

@@ -1103,9 +1103,8 @@ static ak_status launch_run(hipStream_t s, Workspace *ws, RunState *st, void *ke
 
 // --------------------------------------------------------------- driver
 constexpr int SMALL_W = 4, SMALL_IPT = 16;
-// Key-only runs above this size may take the prefix-partitioned finish
-// (smaller ones replay a captured graph of plain passes).
-constexpr int64_t PREFIX_MIN = int64_t(1) << 22;
+// Key-only runs above this size may take the prefix-partitioned finish.
+constexpr int64_t PREFIX_MIN = int64_t(1) << 16;
 // Runs of up to GRAPH_MAX keys are latency-bound (about p+3 launches of a
 // few microseconds of work each), so their launch sequence is captured once
 // per (dtype, mode, n, pointers, workspace generation) and replayed.
@@ -1167,27 +1166,27 @@ static ak_status radix_sort_t(Workspace *ws, void *keys, void *vals, int64_t n64
     const size_t tiles = (n + TILE - 1) / TILE;
     if ((r = ws_reserve_lookback(ws, lookback_words(tiles) * 8)) != AK_OK) return r;
     if ((r = ws_reserve(ws, &ws->aux[4], &ws->aux_bytes[4], rts_bytes(tiles))) != AK_OK) return r;
-    // key-only runs too large for a captured graph may finish on chip once
-    // their top places are placed (decided on the device from the digit
-    // counts; plain passes otherwise)
-    const bool pfx = MODE == M_KEYS && prefix_dtype(DT) && n64 > PREFIX_MIN && !stream_capturing(s);
+    // key-only runs may finish on chip once their top places are placed
+    // (decided on the device from the digit counts; plain passes otherwise).
+    // Small runs finish with fixed launches only (captured with the rest);
+    // larger ones hand long runs to the segmented sort, which captures its
+    // own launch graph, so they cannot be recorded into a caller's graph.
+    const bool small = n64 <= GRAPH_MAX;
+    const bool pfx = MODE == M_KEYS && prefix_dtype(DT) && n64 > PREFIX_MIN && (small || !stream_capturing(s));
     if (pfx && (r = prefix_reserve(ws, DT, n64)) != AK_OK) return r;
     if (slot == 0) ws->last_route = pfx ? 2 : 1;
     uint32_t epoch;
     if ((r = ws_next_epoch(ws, &epoch)) != AK_OK) return r;
     RunState *st = ws->state + slot;
     const int nplaces = (int)sizeof(U);
-    if (pfx) {
-        if ((r = launch_run<DT, MODE, false>(s, ws, st, keys, vals, n, nplaces, nullptr, 0, 0,
-                                             (uint32_t)(prefix_chunk_keys() / 4))) != AK_OK)
-            return r;
-        return prefix_finish(ws, DT, keys, n64, st);
-    }
-    if (n64 > GRAPH_MAX || ws->no_graph || stream_capturing(s))
-        return launch_run<DT, MODE, false>(s, ws, st, keys, vals, n, nplaces, nullptr, 0);
-    return graph_run(ws, GraphKey{DT, MODE, slot, n, keys, vals, ws->gen}, [&](hipStream_t cs) {
-        return launch_run<DT, MODE, false>(cs, ws, st, keys, vals, n, nplaces, nullptr, 0);
-    });
+    const uint32_t pfx_cap = pfx ? (uint32_t)(prefix_chunk_keys() / 4) : 0u;
+    auto run = [&](hipStream_t cs) -> ak_status {
+        ak_status rr = launch_run<DT, MODE, false>(cs, ws, st, keys, vals, n, nplaces, nullptr, 0, 0, pfx_cap);
+        if (rr != AK_OK || !pfx) return rr;
+        return prefix_finish(ws, cs, DT, keys, n64, st, small);
+    };
+    if (!small || ws->no_graph || stream_capturing(s)) return run(s);
+    return graph_run(ws, GraphKey{DT, MODE, slot, n, keys, vals, ws->gen}, run);
 }
 
 }  // namespace ak

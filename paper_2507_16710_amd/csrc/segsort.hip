@@ -53,9 +53,30 @@ constexpr int BIG_SPLIT = BIG_W * 64 * 16;
 template <typename U>
 constexpr int big_ipt() { return 32; }
 inline uint32_t big_cap(int) { return (uint32_t)BIG_W * 64u * 32u; }
-constexpr int XL_W = 8, XL_IPT = 8;   // huge-class tile: 4096 keys
-constexpr int XL_TILE = XL_W * 64 * XL_IPT;
+// Huge-class tile shapes (W waves x IPT keys per lane); xl_variant() picks
+// one ($AK_XL_VARIANT overrides the default), and the tile size travels in
+// the argument block.  The default from the sweep on the 100,000-segment
+// batch (uint32 keys, 65% of them in huge segments): 8 x 12 keys 9.28 ms,
+// 8 x 8 10.51 ms, 16 x 8 and 8 x 16 11.15 ms (8 x 16 holds 162 registers,
+// three waves per SIMD).
+struct XlShape {
+    int w, ipt;
+};
+constexpr int XL_NVAR = 4;
+constexpr XlShape XL_SHAPES[XL_NVAR] = {{8, 12}, {8, 10}, {8, 14}, {8, 8}};
 constexpr int XL_HT = 16;             // tiles per histogram work item
+static int xl_variant() {
+    static const int v = [] {
+        const char *e = getenv("AK_XL_VARIANT");
+        const int x = (e && *e) ? atoi(e) : 0;
+        return x >= 0 && x < XL_NVAR ? x : 0;
+    }();
+    return v;
+}
+static uint32_t xl_tile() {
+    const XlShape sh = XL_SHAPES[xl_variant()];
+    return (uint32_t)(sh.w * 64 * sh.ipt);
+}
 
 // per huge segment: active digit places and the index of each active pass
 struct XlDesc {
@@ -74,6 +95,7 @@ struct SegArgs {
     int64_t base;       // off[0]
     int64_t end;        // off[nseg]
     uint32_t a_max, b_max, c_max, xl_min;
+    uint32_t xl_tile;   // keys per huge-class tile
     uint32_t xl_cap;    // room for huge segments in the arrays below
     uint32_t *xl_pre;   // xl_cap+1 tile prefix of the huge segments
     uint32_t *xl_tseg;  // huge segment of every tile
@@ -336,7 +358,7 @@ __global__ __launch_bounds__(1024) void k_xl_prefix(const SegArgs *ap, SegState 
         if (i < cnt) {
             const int64_t s = a.list[first + i];
             const int64_t len = a.hi[s] - a.off[s];
-            v = (uint32_t)((len + XL_TILE - 1) / XL_TILE);
+            v = (uint32_t)((len + a.xl_tile - 1) / a.xl_tile);
         }
         const uint32_t incl = wave_incl_scan(v);
         if (lane == 63) s_wsum[w] = incl;
@@ -434,59 +456,106 @@ __global__ __launch_bounds__(256) void k_xl_zero(const SegArgs *ap, const SegSta
 }
 
 // Digit counts of every place per huge segment: work items of XL_HT tiles,
-// LDS counters flushed whenever the items' tiles move to another segment.
+// counted in lane-private LDS counters (lane l adds to copy l mod 32 of a
+// counter word; 16-bit halves for bins d and d + 128), so a wave's LDS
+// atomics never meet in a bank whatever the digits; the copies are folded
+// and added to the segment's global counts whenever the item's tiles move
+// to another segment and at the item's end (an item adds at most
+// XL_HT * tile / 32 to one 16-bit count, below 2^15 for every tile shape).
+// A wave whose 64 keys are all equal (runs of one repeated key, as in the
+// learned sort's fallback) adds its count once per place to a separate
+// 32-bit array instead.
 template <int DT>
-__global__ __launch_bounds__(256) void k_xl_hist(const SegArgs *ap, SegState *st) {
+__global__ __launch_bounds__(1024) void k_xl_hist(const SegArgs *ap, SegState *st) {
     using U = typename KT<DT>::U;
+    constexpr int B = 1024;
     constexpr int P = (int)sizeof(U);
-    __shared__ uint32_t s_h[P * RADIX];
-    __shared__ uint32_t s_item, s_seg;
+    constexpr int ROWS = P * 128, NR = (ROWS + B - 1) / B;
+    __shared__ uint32_t s_h[ROWS * 32];
+    __shared__ uint32_t s_eq[P * RADIX];
+    __shared__ uint32_t s_item;
     const SegArgs a = *ap;
     const U *keys = (const U *)a.keys;
-    const uint32_t cnt = st->xl_count, ntiles = st->xl_tiles, first = st->start[B_XL];
+    const uint32_t ntiles = st->xl_tiles, first = st->start[B_XL];
     const uint32_t nitems = (ntiles + XL_HT - 1) / XL_HT;
     const int tid = threadIdx.x;
+    const uint32_t copy = (uint32_t)tid & 31u;
+    {
+        uint4 *z = reinterpret_cast<uint4 *>(s_h);
+        for (int i = tid; i < ROWS * 8; i += B) z[i] = make_uint4(0, 0, 0, 0);
+        for (int i = tid; i < P * RADIX; i += B) s_eq[i] = 0;
+    }
+    // folds the copies of every counter word (lane r starts at copy r mod
+    // 32: distinct banks), adds the totals to segment `seg`, clears
+    auto flush = [&](int seg) {
+        uint32_t *gh = a.xl_hist + (size_t)seg * P * RADIX;
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            const int r = j * B + tid;
+            if (r < ROWS) {
+                uint32_t lo = 0, hi = 0;
+#pragma unroll 8
+                for (int k = 0; k < 32; ++k) {
+                    const int idx = r * 32 + ((k + r) & 31);
+                    const uint32_t v = s_h[idx];
+                    lo += v & 0xFFFFu;
+                    hi += v >> 16;
+                    s_h[idx] = 0;
+                }
+                const int p = r >> 7, w = r & 127;
+                lo += s_eq[p * RADIX + w];
+                hi += s_eq[p * RADIX + w + 128];
+                s_eq[p * RADIX + w] = 0;
+                s_eq[p * RADIX + w + 128] = 0;
+                if (lo) atomicAdd(&gh[p * RADIX + w], lo);
+                if (hi) atomicAdd(&gh[p * RADIX + w + 128], hi);
+            }
+        }
+    };
+    auto count4 = [&](uint32_t x, int p0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (p0 + q >= P) break;
+            const uint32_t w = (x >> (8 * q)) & 127u;
+            const uint32_t half = (x >> (8 * q + 7)) & 1u;
+            atomicAdd(&s_h[((p0 + q) * 128 + w) * 32 + copy], half * 0xFFFFu + 1u);
+        }
+    };
+    __syncthreads();
     while (true) {
         if (tid == 0) s_item = atomicAdd(&st->xl_ctr[0], 1u);
-        for (int i = tid; i < P * RADIX; i += 256) s_h[i] = 0;
         __syncthreads();
         const uint32_t item = s_item;
+        __syncthreads();
         if (item >= nitems) break;
         const uint32_t g0 = item * XL_HT, g1 = min(g0 + XL_HT, ntiles);
         int cur = -1;
         for (uint32_t g = g0; g < g1; ++g) {
-            if (tid == 0) s_seg = a.xl_tseg[g];
-            __syncthreads();
-            const int i = (int)s_seg;
+            const int i = (int)a.xl_tseg[g];
             if (cur >= 0 && i != cur) {
-                for (int k = tid; k < P * RADIX; k += 256)
-                    if (s_h[k]) {
-                        atomicAdd(&a.xl_hist[(size_t)cur * P * RADIX + k], s_h[k]);
-                        s_h[k] = 0;
-                    }
+                __syncthreads();
+                flush(cur);
                 __syncthreads();
             }
             cur = i;
             const int64_t s = a.list[first + i];
             const int64_t lo = a.off[s], len = a.hi[s] - lo;
-            const uint32_t tb = (g - a.xl_pre[i]) * (uint32_t)XL_TILE;
-            const uint32_t tv = (uint32_t)min((int64_t)XL_TILE, len - (int64_t)tb);
+            const uint32_t tb = (g - a.xl_pre[i]) * a.xl_tile;
+            const uint32_t tv = (uint32_t)min((int64_t)a.xl_tile, len - (int64_t)tb);
             // XI keys per thread in flight before they are counted
             constexpr int XI = 4;
-            for (uint32_t e0 = 0; e0 < tv; e0 += 256 * XI) {
+            for (uint32_t e0 = 0; e0 < tv; e0 += B * XI) {
                 U v[XI];
 #pragma unroll
                 for (int it = 0; it < XI; ++it) {
-                    const uint32_t e = e0 + it * 256 + tid;
+                    const uint32_t e = e0 + it * B + tid;
                     v[it] = e < tv ? keys[lo + tb + e] : U(0);
                 }
 #pragma unroll
                 for (int it = 0; it < XI; ++it) {
-                    if (e0 + it * 256 + tid >= tv) break;
+                    if (e0 + it * B + tid >= tv) break;
                     const U t = KT<DT>::image(v[it]);
                     const uint64_t act = ballot64(true);
-                    // a wave whose keys are all equal (runs of one repeated
-                    // key) adds its count once per place
                     const uint64_t t64 = (uint64_t)t;
                     const uint32_t tl = __builtin_amdgcn_readfirstlane((uint32_t)t64);
                     const uint32_t th = __builtin_amdgcn_readfirstlane((uint32_t)(t64 >> 32));
@@ -494,31 +563,18 @@ __global__ __launch_bounds__(256) void k_xl_hist(const SegArgs *ap, SegState *st
                         if (count_below(act) == 0) {
                             const uint32_t c = (uint32_t)__popcll(act);
 #pragma unroll
-                            for (int p = 0; p < P; ++p) atomicAdd(&s_h[p * RADIX + ((uint32_t)(t64 >> (8 * p)) & (RADIX - 1))], c);
+                            for (int p = 0; p < P; ++p)
+                                atomicAdd(&s_eq[p * RADIX + ((uint32_t)(t64 >> (8 * p)) & (RADIX - 1))], c);
                         }
                         continue;
                     }
-#pragma unroll
-                    for (int p = 0; p < P; ++p) {
-                        const uint32_t d = (uint32_t)(t >> (8 * p)) & (RADIX - 1);
-                        // lanes sharing the first lane's digit add once when
-                        // there are many (constant or skewed places)
-                        const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-                        const uint64_t m0 = ballot64(d == d0);
-                        if (__popcll(m0) > 8) {
-                            if (count_below(act) == 0) atomicAdd(&s_h[p * RADIX + d0], (uint32_t)__popcll(m0));
-                            if (d != d0) atomicAdd(&s_h[p * RADIX + d], 1u);
-                        } else {
-                            atomicAdd(&s_h[p * RADIX + d], 1u);
-                        }
-                    }
+                    count4((uint32_t)t64, 0);
+                    if constexpr (P > 4) count4((uint32_t)(t64 >> 32), 4);
                 }
             }
-            __syncthreads();
         }
-        if (cur >= 0)
-            for (int k = tid; k < P * RADIX; k += 256)
-                if (s_h[k]) atomicAdd(&a.xl_hist[(size_t)cur * P * RADIX + k], s_h[k]);
+        __syncthreads();
+        if (cur >= 0) flush(cur);
         __syncthreads();
     }
 }
@@ -566,10 +622,10 @@ __global__ __launch_bounds__(256) void k_xl_scan(const SegArgs *ap, SegState *st
 // tiles taken in order).  Same tile work as the global one-sweep pass, with
 // the look-back stopping at the segment's first tile and offsets relative
 // to the segment; the segment ping-pongs with its scratch copy.
-template <int DT>
-__global__ __launch_bounds__(XL_W * 64) void k_xl_pass(const SegArgs *ap, SegState *st, int place) {
+template <int DT, int W, int IPT>
+__global__ __launch_bounds__(W * 64) void k_xl_pass(const SegArgs *ap, SegState *st, int place) {
     using U = typename KT<DT>::U;
-    constexpr int W = XL_W, IPT = XL_IPT, B = W * 64, TILE = XL_TILE;
+    constexpr int B = W * 64, TILE = W * 64 * IPT;
     constexpr int P = (int)sizeof(U);
     constexpr size_t RAW = (size_t)TILE * sizeof(U) > (size_t)W * RADIX * 2 ? (size_t)TILE * sizeof(U)
                                                                             : (size_t)W * RADIX * 2;
@@ -674,8 +730,8 @@ __global__ __launch_bounds__(256) void k_xl_final(const SegArgs *ap, SegState *s
         if (tile >= ntiles) break;
         const int64_t s = a.list[first + i];
         const int64_t lo = a.off[s], len = a.hi[s] - lo;
-        const uint32_t tbase = (tile - apre[i]) * (uint32_t)XL_TILE;
-        const uint32_t tv = (uint32_t)min((int64_t)XL_TILE, len - (int64_t)tbase);
+        const uint32_t tbase = (tile - apre[i]) * a.xl_tile;
+        const uint32_t tv = (uint32_t)min((int64_t)a.xl_tile, len - (int64_t)tbase);
         for (uint32_t e = threadIdx.x; e < tv; e += 256) keys[lo + tbase + e] = tmp[lo - a.base + tbase + e];
     }
 }
@@ -831,7 +887,9 @@ static ak_status launch_xl(int grid, hipStream_t s, SegArgs *a, SegState *st) {
     AK_LAUNCH_CHECK("k_xl_tilemap");
     hipLaunchKernelGGL((k_xl_zero<P>), dim3(grid), dim3(256), 0, s, a, st);
     AK_LAUNCH_CHECK("k_xl_zero");
-    hipLaunchKernelGGL((k_xl_hist<DT>), dim3(grid), dim3(256), 0, s, a, st);
+    // one 1024-thread workgroup per CU for 64-bit keys (128 KB of counters), two for 32-bit keys
+    hipLaunchKernelGGL((k_xl_hist<DT>), dim3((unsigned)num_cus() * (key_bits(DT) == 64 ? 1 : 2)), dim3(1024), 0, s,
+                       a, st);
     AK_LAUNCH_CHECK("k_xl_hist");
     hipLaunchKernelGGL((k_xl_scan<P>), dim3(grid), dim3(256), 0, s, a, st);
     AK_LAUNCH_CHECK("k_xl_scan");
@@ -840,7 +898,16 @@ static ak_status launch_xl(int grid, hipStream_t s, SegArgs *a, SegState *st) {
     hipLaunchKernelGGL((k_xl_amap<P>), dim3(grid), dim3(256), 0, s, a, st);
     AK_LAUNCH_CHECK("k_xl_amap");
     for (int p = 0; p < P; ++p) {
-        hipLaunchKernelGGL((k_xl_pass<DT>), dim3(grid), dim3(XL_W * 64), 0, s, a, st, p);
+        auto pass = [&](auto vc) {
+            constexpr XlShape sh = XL_SHAPES[decltype(vc)::value];
+            hipLaunchKernelGGL((k_xl_pass<DT, sh.w, sh.ipt>), dim3(grid), dim3(sh.w * 64), 0, s, a, st, p);
+        };
+        switch (xl_variant()) {
+        case 0: pass(std::integral_constant<int, 0>{}); break;
+        case 1: pass(std::integral_constant<int, 1>{}); break;
+        case 2: pass(std::integral_constant<int, 2>{}); break;
+        default: pass(std::integral_constant<int, 3>{}); break;
+        }
         AK_LAUNCH_CHECK("k_xl_pass");
     }
     hipLaunchKernelGGL((k_xl_final<DT>), dim3(grid), dim3(256), 0, s, a, st);
@@ -906,7 +973,7 @@ static ak_status seg_launch_all(int dt, const SegTune &t, int64_t nseg, int grid
 // digit counts, tile maps) plus the huge segments' look-back words.
 struct SegLayout {
     SegTune t;
-    uint32_t a_max, b_max, c_max, xl_min, xl_cap;
+    uint32_t a_max, b_max, c_max, xl_min, xl_cap, xl_tile;
     size_t off_pre, off_desc, off_hist, off_tseg, off_apre, off_amap, misc2_need;
     size_t max_tiles, lb_words;
 };
@@ -928,7 +995,8 @@ static SegLayout seg_layout(int dt, int64_t n, int64_t nseg) {
     L.xl_min = (uint32_t)std::max(t.xl_min, (int)L.b_max + 1);
     L.c_max = big_cap(dt);
     L.xl_cap = (uint32_t)std::min<int64_t>(nseg, n / L.xl_min + 1);
-    L.max_tiles = (size_t)n / XL_TILE + L.xl_cap + 1;
+    L.xl_tile = xl_tile();
+    L.max_tiles = (size_t)n / L.xl_tile + L.xl_cap + 1;
     L.off_pre = al((size_t)nseg * 4);
     L.off_desc = L.off_pre + al((size_t)(L.xl_cap + 1) * 4);
     L.off_hist = L.off_desc + al((size_t)L.xl_cap * sizeof(XlDesc));
@@ -998,6 +1066,7 @@ static ak_status seg_run(Workspace *ws, int dt, void *keys, const int64_t *lo, c
     v.xl_min = L.xl_min;
     v.c_max = L.c_max;
     v.xl_cap = L.xl_cap;
+    v.xl_tile = L.xl_tile;
     v.xl_pre = (uint32_t *)((char *)ws->misc2 + L.off_pre);
     v.xl_desc = (XlDesc *)((char *)ws->misc2 + L.off_desc);
     v.xl_hist = (uint32_t *)((char *)ws->misc2 + L.off_hist);

@@ -1,10 +1,11 @@
 """GPU parity of the prefix-partitioned radix sort (bit-exact vs the oracle).
 
-A key-only sort of more than 2**22 keys whose top digit places spread the
+A key-only sort of more than 2**16 keys whose top digit places spread the
 keys takes passes over those places only; each run of equal prefix is then
-sorted on chip, and runs longer than a chunk by the segmented sort.  The
-route is read back with ak_sort_route, so every case checks both the order
-and the route it expects.
+sorted on chip, and runs longer than a chunk by the segmented sort (above
+2**22 keys) or by one workgroup each (at the sizes replayed from a captured
+graph).  The route is read back with ak_sort_route, so every case checks
+both the order and the route it expects.
 """
 import zlib
 
@@ -19,7 +20,7 @@ from pools import bits, random_keys
 
 pytestmark = pytest.mark.gpu
 
-N0 = (1 << 22) + 777  # just above the size that replays a captured graph
+N0 = (1 << 22) + 777  # just above the sizes that replay a captured graph
 CHUNK = 2048          # keys one on-chip chunk sort holds
 
 
@@ -152,6 +153,59 @@ def test_prefix_route_with_nan_payloads_and_zeros(dt):
     assert route["prefix_places"] >= 2, route
     if dt == "f32":
         assert route["fallback_runs"] >= 1, route   # about n/256 NaNs in one run
+
+
+SMALL_SIZES = [(1 << 16) + 1, 300_001, 1_000_000, 1 << 22]
+
+
+@pytest.mark.parametrize("dt", ["u64", "i64", "f64", "u32", "i32", "f32"])
+def test_small_runs_take_prefix_route(dt):
+    """Sizes whose launch sequence is replayed from a captured graph
+    (2**16 < n <= 2**22) take the prefix route too, with fixed launches
+    only; a second input of the same size replays the same graph."""
+    rng = np.random.default_rng(zlib.crc32(f"pfxsmall{dt}".encode()))
+    for n in SMALL_SIZES:
+        for rep in range(2):
+            k = random_keys(dt, n, rng, "uniform")
+            route = _check(k, dt, f"small-uniform{rep}")
+            assert route["prefix_places"] == 2 and route["passes"] == 2, route
+            assert route["chunks"] > 0, route
+
+
+@pytest.mark.parametrize("n,frac", [(300_001, 0.01), (1 << 22, 0.001)])
+def test_small_heavy_prefix_sorted_by_fallback_kernel(n, frac):
+    """A fraction of the keys share one 16-bit prefix (small enough that the
+    per-place counts still choose two prefix places): that run exceeds a
+    chunk and one workgroup sorts it (LSD through the scratch copy); the rest
+    finish in chunks."""
+    rng = np.random.default_rng(n)
+    k = rng.integers(0, 1 << 64, size=n, dtype=np.uint64)
+    heavy = rng.random(n) < frac
+    k[heavy] = (np.uint64(0x5A5A) << np.uint64(48)) | (k[heavy] & np.uint64((1 << 48) - 1))
+    route = _check(k, "u64", "small-heavy")
+    assert route["prefix_places"] == 2, route
+    assert route["fallback_runs"] >= 1 and route["fallback_keys"] > CHUNK, route
+
+
+def test_small_runs_nan_payloads_repeated_and_constant_place():
+    """At graph-replayed sizes: float32 raw bits (a run of about n/256 NaNs
+    of every payload, which must keep input order), keys repeated 100 times,
+    and a constant byte inside the prefix."""
+    rng = np.random.default_rng(19)
+    n = 1_000_000
+    k = rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32).view(np.float32).copy()
+    k[rng.choice(n, size=2000, replace=False)] = -0.0
+    route = _check(k, "f32", "small-nan")
+    assert route["prefix_places"] >= 2 and route["fallback_runs"] >= 1, route
+    vals = rng.integers(0, 1 << 64, size=n // 100 + 1, dtype=np.uint64)
+    r = np.repeat(vals, 100)[:n]
+    rng.shuffle(r)
+    route = _check(r, "u64", "small-repeated")
+    assert route["prefix_places"] >= 2, route
+    c = rng.integers(0, 1 << 64, size=n, dtype=np.uint64)
+    c = (c & ~np.uint64(0xFF << 48)) | np.uint64(0x3C << 48)
+    route = _check(c, "u64", "small-inactive")
+    assert route["prefix_places"] >= 2 and route["passes"] == route["prefix_places"] - 1, route
 
 
 def test_prefix_route_full_size_2p31():
