@@ -46,9 +46,13 @@ static __global__ void k_run_init(RunState *st, uint32_t *epoch_dev) {
 // Exclusive digit offsets per place; a place where one digit holds every
 // key is inactive (its pass would be a copy).  Active passes are numbered
 // so that each pass kernel can pick its source and destination buffers
-// without a host round trip.  Run by one workgroup of B >= 256 threads
-// after the histogram kernel (whose workgroups added their counts into the
-// HIST_REP copies); it sums the copies and clears them for the next run.
+// without a host round trip.  One 1024-thread workgroup, in its own launch
+// after the histogram (the kernel boundary makes every workgroup's counts
+// visible: a "last workgroup finishes" handoff inside the histogram needs a
+// device-scope release fence in every workgroup, which on gfx950 writes
+// back the L2 of its XCD, about 50 us at one million keys); it sums the
+// HIST_REP copies, clears them for the next run, and scans four places at
+// a time.
 //
 // pfx_cap > 0 (key-only runs that can finish on chip): if the top k = 2..4
 // places spread the keys so that the expected largest run of equal prefix,
@@ -59,48 +63,57 @@ static __global__ void k_run_init(RunState *st, uint32_t *epoch_dev) {
 // and the chunk sort finishes each run of equal prefix.  The estimate
 // assumes independent places; a wrong guess costs time (longer runs go to
 // the segmented fallback), never order.
-template <int B, int MAXP>
-__device__ void scan_places(RunState *st, uint32_t n, int nplaces, uint32_t *s_buf, uint32_t *s_wsum,
-                            int *s_active, uint32_t *s_pmax, uint32_t pfx_cap) {
-    const int tid = threadIdx.x;
-    // every place's count in flight at once (one round trip, not one per place)
-    // every copy of every place in flight at once (one round trip; the
-    // places a run does not have hold zeros)
-    uint32_t cnt[MAXP];
+template <int MAXP>
+__global__ __launch_bounds__(1024) void k_scan_places(RunState *st, uint32_t n, int nplaces, uint32_t pfx_cap) {
+    // four groups of 256 threads, one place each at a time
+    constexpr int G = 4, PG = (MAXP + G - 1) / G;
+    __shared__ uint32_t s_buf[G][RADIX];
+    __shared__ uint32_t s_wsum[G][4];
+    __shared__ int s_active[MAX_PLACES], s_triv[MAX_PLACES];
+    __shared__ uint32_t s_pmax[MAX_PLACES];
+    const int tid = threadIdx.x, g = tid >> 8, t = tid & (RADIX - 1);
+    if (tid < MAX_PLACES) {
+        s_pmax[tid] = 0;
+        s_triv[tid] = 0;
+    }
+    // every copy of every place of this group in flight at once (one round
+    // trip; the places a run does not have hold zeros), then cleared
+    uint32_t cnt[PG];
+    {
+        uint32_t v[PG][HIST_REP];
 #pragma unroll
-    for (int p = 0; p < MAXP; ++p) cnt[p] = 0;
-    if (tid < RADIX) {
-        uint32_t v[MAXP][HIST_REP];
+        for (int k = 0; k < PG; ++k)
 #pragma unroll
-        for (int p = 0; p < MAXP; ++p)
+            for (int r = 0; r < HIST_REP; ++r) v[k][r] = g + G * k < MAXP ? st->hist[r][g + G * k][t] : 0u;
 #pragma unroll
-            for (int r = 0; r < HIST_REP; ++r) v[p][r] = st->hist[r][p][tid];
-#pragma unroll
-        for (int p = 0; p < MAXP; ++p)
+        for (int k = 0; k < PG; ++k) {
+            cnt[k] = 0;
 #pragma unroll
             for (int r = 0; r < HIST_REP; ++r) {
-                cnt[p] += v[p][r];
-                st->hist[r][p][tid] = 0;
+                cnt[k] += v[k][r];
+                if (g + G * k < MAXP) st->hist[r][g + G * k][t] = 0;
             }
+        }
     }
-    if (tid < MAX_PLACES) s_pmax[tid] = 0;
     __syncthreads();
 #pragma unroll
-    for (int p = 0; p < MAXP; ++p) {
-        if (p >= nplaces) break;
-        const uint32_t c = cnt[p];
-        const int trivial = __syncthreads_or(tid < RADIX && c == n);
-        uint32_t m = tid < RADIX ? c : 0u;   // the wave's largest count, then one LDS atomic
+    for (int k = 0; k < PG; ++k) {
+        const int p = g + G * k;
+        const bool live = p < nplaces;
+        const uint32_t c = live ? cnt[k] : 0u;
+        if (live && c == n) s_triv[p] = 1;
+        uint32_t m = c;   // the wave's largest count, then one LDS atomic
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
-        if (tid < RADIX) s_buf[tid] = c;
-        if ((tid & 63) == 0 && m) atomicMax(&s_pmax[p], m);
+        if (live && (t & 63) == 0 && m) atomicMax(&s_pmax[p], m);
+        s_buf[g][t] = c;
         __syncthreads();
-        block_exscan<B, RADIX>(s_buf, s_buf, s_wsum, tid);
-        if (tid < RADIX) st->base[p][tid] = s_buf[tid];
-        if (tid == 0) s_active[p] = !trivial;
+        block_exscan<RADIX, RADIX>(s_buf[g], s_buf[g], s_wsum[g], t);
+        if (live) st->base[p][t] = s_buf[g][t];
         __syncthreads();
     }
+    if (tid < MAX_PLACES) s_active[tid] = tid < nplaces ? !s_triv[tid] : 0;
+    __syncthreads();
     if (tid == 0) {
         int q = 0, top = -1;
         for (int p = 0; p < nplaces; ++p) {
@@ -143,20 +156,6 @@ __device__ void scan_places(RunState *st, uint32_t n, int nplaces, uint32_t *s_b
 }
 
 // ---------------------------------------------------------- histogram
-// The digit scan as its own one-workgroup kernel after the histogram: the
-// kernel boundary makes every workgroup's counts visible.  (A "last
-// workgroup finishes" handoff inside the histogram needs a device-scope
-// release fence in every workgroup, which on gfx950 writes back the L2 of
-// its XCD: about 50 us at one million keys.)
-template <int MAXP>
-__global__ __launch_bounds__(256) void k_scan_places(RunState *st, uint32_t n, int nplaces, uint32_t pfx_cap) {
-    __shared__ uint32_t s_buf[RADIX];
-    __shared__ uint32_t s_wsum[4];
-    __shared__ int s_active[MAX_PLACES];
-    __shared__ uint32_t s_pmax[MAX_PLACES];
-    scan_places<256, MAXP>(st, n, nplaces, s_buf, s_wsum, s_active, s_pmax, pfx_cap);
-}
-
 // Histogram of code digits (learned sort) and of 128-bit keys: one read of
 // the keys, counting the digit of every place in LDS counters shared by the
 // workgroup, then one global atomic per nonzero bin.  The lanes of a wave
@@ -1077,7 +1076,7 @@ static ak_status launch_run(hipStream_t s, Workspace *ws, RunState *st, void *ke
         }
     }
     constexpr int HP = CODE ? 4 : (int)sizeof(U);
-    hipLaunchKernelGGL((k_scan_places<HP>), dim3(1), dim3(256), 0, s, st, n, nplaces, pfx_cap);
+    hipLaunchKernelGGL((k_scan_places<HP>), dim3(1), dim3(1024), 0, s, st, n, nplaces, pfx_cap);
     AK_LAUNCH_CHECK("k_scan_places");
     OnesweepArgs a{};
     a.keys = keys;
