@@ -54,27 +54,30 @@ template <typename U>
 constexpr int big_ipt() { return 32; }
 inline uint32_t big_cap(int) { return (uint32_t)BIG_W * 64u * 32u; }
 // Huge-class tile shapes (W waves x IPT keys per lane); xl_variant() picks
-// one ($AK_XL_VARIANT overrides the default), and the tile size travels in
-// the argument block.  The default from the sweep on the 100,000-segment
-// batch (uint32 keys, 65% of them in huge segments): 8 x 12 keys 9.28 ms,
-// 8 x 8 10.51 ms, 16 x 8 and 8 x 16 11.15 ms (8 x 16 holds 162 registers,
-// three waves per SIMD).
+// one per key width ($AK_XL_VARIANT overrides the default), and the tile
+// size travels in the argument block.  Defaults from the sweeps: 32-bit
+// keys on the 100,000-segment batch (65% of the keys in huge segments):
+// 8 x 12 keys 9.28 ms, 8 x 10 9.89 ms, 8 x 8 10.51 ms, 8 x 14 11.55 ms,
+// 16 x 8 and 8 x 16 11.15 ms (8 x 16 holds 162 registers, three waves per
+// SIMD); 64-bit keys (the learned sort's fallback runs of 2^31 mixture
+// keys, whole learned sort): 8 x 8 68.2 ms, 8 x 12 68.9 ms.
 struct XlShape {
     int w, ipt;
 };
 constexpr int XL_NVAR = 4;
 constexpr XlShape XL_SHAPES[XL_NVAR] = {{8, 12}, {8, 10}, {8, 14}, {8, 8}};
 constexpr int XL_HT = 16;             // tiles per histogram work item
-static int xl_variant() {
-    static const int v = [] {
+static int xl_variant(int dt) {
+    static const int forced = [] {
         const char *e = getenv("AK_XL_VARIANT");
-        const int x = (e && *e) ? atoi(e) : 0;
-        return x >= 0 && x < XL_NVAR ? x : 0;
+        const int x = (e && *e) ? atoi(e) : -1;
+        return x >= 0 && x < XL_NVAR ? x : -1;
     }();
-    return v;
+    if (forced >= 0) return forced;
+    return key_bits(dt) == 64 ? 3 : 0;
 }
-static uint32_t xl_tile() {
-    const XlShape sh = XL_SHAPES[xl_variant()];
+static uint32_t xl_tile(int dt) {
+    const XlShape sh = XL_SHAPES[xl_variant(dt)];
     return (uint32_t)(sh.w * 64 * sh.ipt);
 }
 
@@ -902,7 +905,7 @@ static ak_status launch_xl(int grid, hipStream_t s, SegArgs *a, SegState *st) {
             constexpr XlShape sh = XL_SHAPES[decltype(vc)::value];
             hipLaunchKernelGGL((k_xl_pass<DT, sh.w, sh.ipt>), dim3(grid), dim3(sh.w * 64), 0, s, a, st, p);
         };
-        switch (xl_variant()) {
+        switch (xl_variant(DT)) {
         case 0: pass(std::integral_constant<int, 0>{}); break;
         case 1: pass(std::integral_constant<int, 1>{}); break;
         case 2: pass(std::integral_constant<int, 2>{}); break;
@@ -995,7 +998,7 @@ static SegLayout seg_layout(int dt, int64_t n, int64_t nseg) {
     L.xl_min = (uint32_t)std::max(t.xl_min, (int)L.b_max + 1);
     L.c_max = big_cap(dt);
     L.xl_cap = (uint32_t)std::min<int64_t>(nseg, n / L.xl_min + 1);
-    L.xl_tile = xl_tile();
+    L.xl_tile = xl_tile(dt);
     L.max_tiles = (size_t)n / L.xl_tile + L.xl_cap + 1;
     L.off_pre = al((size_t)nseg * 4);
     L.off_desc = L.off_pre + al((size_t)(L.xl_cap + 1) * 4);
