@@ -74,11 +74,12 @@ typedef enum {
  * Sec. II-B (merge_sort): sorts keys[0..n) ascending, in place.  Output keys
  * keep their original bit patterns (NaN payloads and signs included); NaNs
  * end up last, in input order.  LSD radix passes over the active digit
- * places; above 2^22 keys, when the digit counts show that the top places
+ * places; above 2^16 keys, when the digit counts show that the top places
  * spread the keys, only those places take passes and each run of equal
  * prefix is finished on chip (same result; ak_sort_route tells which).
- * Scratch: two key buffers, per-tile look-back words, and above 2^22 keys
- * the prefix finish's run lists (ak_temp_bytes gives the total).
+ * Scratch: two key buffers, per-tile look-back words, and above 2^16 keys
+ * the prefix finish's run lists, plus above 2^22 keys the segmented sort's
+ * scratch for long runs (ak_temp_bytes gives the total).
  * Errors: AK_ERR_INVALID_ARG for n < 0, n > AK_MAX_KEYS or keys == NULL
  * with n > 0; AK_ERR_UNSUPPORTED_DTYPE for an unknown dtype. */
 ak_status ak_sort(void *keys, int64_t n, ak_dtype dtype, ak_stream_t stream);
@@ -409,12 +410,12 @@ ak_status ak_searchsortedlast(const void *sorted, int64_t n, const void *keys, i
  * otherwise).  Waits for the stream.  info is a HOST array of 5:
  *   info[0] prefix places k: 0 if every active digit place took a pass;
  *           2..4 if the passes covered only the top k places (a key-only
- *           sort of more than 2^22 keys whose top places spread the keys)
+ *           sort of more than 2^16 keys whose top places spread the keys)
  *           and each run of equal prefix was then sorted on chip;
  *   info[1] digit passes run;
  *   info[2] on-chip chunk sorts of the prefix finish;
- *   info[3] runs of equal prefix longer than a chunk, sorted by the
- *           segmented sort instead;
+ *   info[3] runs of equal prefix longer than a chunk, sorted instead by
+ *           the segmented sort (above 2^22 keys) or by one workgroup each;
  *   info[4] keys in those runs.
  * Errors: info NULL -> AK_ERR_INVALID_ARG. */
 ak_status ak_sort_route(int64_t *info, ak_stream_t stream);

@@ -15,7 +15,8 @@ namespace ak {
 // tiles an admitted run can have (2^21 64-bit keys in 4096-key tiles, or
 // 2^22 32-bit keys in 8192- or 16384-key tiles: at most 512 tiles, 1.06
 // MiB of words); the arena holds two key buffers of AK_NOALLOC_MAX_KEY_BYTES
-// each plus the counts (512 KiB).
+// each plus the per-tile counts (512 KiB) and the prefix finish's state and
+// run list (about 25 KiB at the largest admitted run).
 constexpr size_t NA_STATE = (RUN_STATE_BYTES + 4095) & ~size_t(4095);
 constexpr size_t NA_LOOKBACK = size_t(2) << 20;
 constexpr size_t NA_ARENA = 2 * (size_t)AK_NOALLOC_MAX_KEY_BYTES + (size_t(2) << 20);

@@ -1019,9 +1019,9 @@ static ak_status launch_passes(hipStream_t stream, Workspace *ws, OnesweepArgs a
     return AK_OK;
 }
 
-// The whole multi-workgroup run: init (epochs, counters), histogram with
-// the digit scan fused into its last workgroup, one pass per place (inactive
-// ones exit at once), and the device-decided copy-back / identity.  `vals`
+// The whole multi-workgroup run: init (epochs, counters), histogram, digit
+// scan, one pass per place (inactive ones exit at once), and the device-
+// decided copy-back / identity.  `vals`
 // is the permutation output (sortperm), the payload (sort by key) or null.
 template <int DT, int MODE, bool CODE>
 static ak_status launch_run(hipStream_t s, Workspace *ws, RunState *st, void *keys, void *vals, uint32_t n,

@@ -142,8 +142,8 @@ def test_temp_bytes_predictable():
         s = lib.ak_temp_bytes(0, n, dt)
         p = lib.ak_temp_bytes(1, n, dt)
         # two ping-pong buffers + look-back, and above 2**22 keys the prefix
-        # finish's fallback scratch (its huge-segment tables scale with
-        # n / the tuned huge-segment threshold)
+        # finish's segmented fallback scratch (its huge-segment tables scale
+        # with n / the tuned huge-segment threshold)
         assert 2 * n * kb <= s <= n * kb * 2.3
         assert p >= 2 * n * kb + n * 4
         assert lib.ak_temp_bytes(2, n, dt) >= n * kb

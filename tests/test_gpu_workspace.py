@@ -106,9 +106,10 @@ def test_segment_offsets_beyond_keys_are_refused():
 
 
 def test_arena_prefix_route_exact_size():
-    """Key-only sorts above 2**22 keys take the prefix route, whose run lists
-    and fallback scratch come from the arena too: an arena of exactly
-    ak_temp_bytes("sort", n) suffices, with and without fallback runs."""
+    """Key-only sorts above 2**22 keys take the prefix route with the
+    segmented fallback, whose run lists and scratch come from the arena too:
+    an arena of exactly ak_temp_bytes("sort", n) suffices, with and without
+    fallback runs."""
     rng = np.random.default_rng(41)
     n = (1 << 22) + 777
     need = ak.temp_bytes("sort", n, "u64")
