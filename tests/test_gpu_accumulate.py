@@ -80,3 +80,17 @@ def test_accumulate_large_int64():
     print(f"accumulate large n={n}", flush=True)
     got = to_host(ak.accumulate(to_gpu(x, "i64"), True, dtype="i64"), "i64")
     assert np.array_equal(got, oracle.accumulate(x, True))
+
+
+def test_accumulate_repeats_bit_for_bit():
+    """The association does not depend on which chunks finish first, so
+    repeated calls agree bit for bit (float sums included)."""
+    rng = np.random.default_rng(33)
+    for dt in ("u64", "f32", "f64"):
+        x = _inputs(dt, 300 * CHUNK + 11, rng)
+        t = to_gpu(x, dt)
+        first = to_host(ak.accumulate(t, True, dtype=dt), dt).view(np.uint8).copy()
+        for _ in range(3):
+            again = to_host(ak.accumulate(t, True, dtype=dt), dt).view(np.uint8)
+            assert np.array_equal(again, first), dt
+        _check(dt, x, first.view(NP[dt]), True)
