@@ -347,8 +347,10 @@ size_t ak_temp_bytes_segmented(int64_t n, int64_t nseg, ak_dtype dtype);
  * runs first, in stream order), and allocates no scratch.  A call that needs
  * more than the arena holds returns AK_ERR_NO_MEMORY, launches nothing and
  * says how many bytes it needed; ak_temp_bytes gives the size.  The
- * per-stream run state (a few KB), segmented-sort argument blocks and cached
- * graphs stay library-owned.
+ * per-stream run states (about 600 KB), segmented-sort argument blocks and
+ * cached graphs stay library-owned.  The look-back words of the radix passes
+ * are zero-filled when their piece of the arena last held other data (the
+ * first call, or a call of another kind that carved its buffers there).
  *   dev_ptr: 256-byte aligned device memory of >= 4096 bytes, or NULL (with
  *            bytes == 0) to unbind and return to library-owned scratch.
  * The caller keeps the arena alive, and leaves it untouched, while it is

@@ -102,6 +102,8 @@ ak_status ws_reserve(Workspace *ws, void **p, size_t *have, size_t need) {
         *p = np;
         *have = need;
         ws->arena_used = off + need;
+        // other data over the known look-back words
+        if (off < ws->arena_lb_off + ws->arena_lb_ok && ws->arena_lb_off < off + need) ws->arena_lb_ok = 0;
         return AK_OK;
     }
     size_t sz = need + need / 8 + 4096;
@@ -127,6 +129,25 @@ ak_status ws_reserve_lookback(Workspace *ws, size_t need) {
     if (ws->fixed_lookback) {
         set_error("look-back region too small for this run");
         return AK_ERR_INTERNAL;
+    }
+    if (ws->arena) {
+        // carved like every arena buffer; zeroed only if these bytes held
+        // other data since they last held look-back words
+        const size_t off = (ws->arena_used + 255) & ~size_t(255);
+        if (off > ws->arena_bytes || need > ws->arena_bytes - off) {
+            set_error("workspace arena too small: this call needs at least " + std::to_string(off + need) +
+                      " bytes, the arena has " + std::to_string(ws->arena_bytes));
+            return AK_ERR_NO_MEMORY;
+        }
+        uint64_t *np = (uint64_t *)(ws->arena + off);
+        if (np != ws->lookback) ++ws->gen;
+        ws->lookback = np;
+        ws->lookback_bytes = need;
+        ws->arena_used = off + need;
+        if (off == ws->arena_lb_off && need <= ws->arena_lb_ok) return AK_OK;
+        ws->arena_lb_off = off;
+        ws->arena_lb_ok = need;
+        return zero_fill(ws->stream, ws->lookback, need);
     }
     void *p = ws->lookback;
     size_t have = ws->lookback_bytes;
@@ -670,6 +691,7 @@ ak_status ak_set_workspace(void *dev_ptr, size_t bytes, ak_stream_t stream) {
     ws->arena = (char *)dev_ptr;
     ws->arena_bytes = dev_ptr ? bytes : 0;
     ws->arena_used = 0;
+    ws->arena_lb_off = ws->arena_lb_ok = 0;
     return AK_OK;
 }
 

@@ -220,6 +220,11 @@ struct Workspace {
     uint32_t epoch = 0;             // last epoch base handed out
     char *arena = nullptr;          // caller-owned scratch (ak_set_workspace), else null
     size_t arena_bytes = 0, arena_used = 0;
+    // arena bytes [arena_lb_off, arena_lb_off + arena_lb_ok) hold nothing
+    // but look-back words (zeroed once, then only words of earlier runs,
+    // whose epochs never match a later run's), so a call that carves its
+    // look-back region there again needs no zero fill
+    size_t arena_lb_off = 0, arena_lb_ok = 0;
     // route of this call's radix run on state slot 0: 0 none or on chip,
     // 1 digit passes only, 2 passes with the prefix-partitioned finish
     int last_route = 0;

@@ -157,3 +157,32 @@ def test_arena_accumulate_exact_size():
             ak.accumulate(to_gpu(x, "i64"), True, dtype="i64")
     finally:
         ak.set_workspace(None)
+
+
+def test_arena_lookback_words_reused_then_refilled():
+    """In a bound arena the radix passes' look-back words are zero-filled
+    only when their bytes last held other data: back-to-back sorts reuse
+    them (earlier runs' words carry older epochs), and after a segmented
+    sort has carved its own buffers over them the next sort fills them
+    again.  Every result is bit-exact."""
+    rng = np.random.default_rng(47)
+    n = 1_000_003
+    need = max(ak.temp_bytes("sort", n, "u64"), ak.temp_bytes_segmented(n, 3, "u64"))
+    arena = torch.empty(need, dtype=torch.uint8, device="cuda")
+    ak.set_workspace(arena)
+    try:
+        for it in range(6):
+            k = rng.integers(0, 1 << 64, size=n, dtype=np.uint64)
+            if it % 2:
+                k >>= np.uint64(rng.integers(8, 40))      # fewer active places
+            t = to_gpu(k, "u64")
+            print(f"arena look-back reuse it={it}", flush=True)
+            ak.sort_(t, dtype="u64")
+            assert np.array_equal(to_host(t, "u64"), oracle.sort(k)), it
+            if it == 2:
+                off = _offsets([n // 3, n // 3, n - 2 * (n // 3)])
+                s = to_gpu(k, "u64")
+                ak.segmented_sort_(s, torch.from_numpy(off).cuda(), dtype="u64")
+                assert np.array_equal(to_host(s, "u64"), oracle.segsort(k, off))
+    finally:
+        ak.set_workspace(None)
