@@ -340,6 +340,14 @@ def main():
     # learned-path algorithmic bytes: histogram read + 2 per code pass + chunk sort
     passes = (stats["code_bits"] + 7) // 8
     alg_bytes = n * 8 * (1 + 2 * passes + 2)
+    # by the route the keys took: the chunk sorts read and write only the
+    # keys outside fallback runs; the fallback reads its keys once (digit
+    # counts) and moves its non-constant ones through at most 8 LSD passes;
+    # the sample (gather, its own radix sort) and the model fit
+    fb, const = stats["fallback_keys"], stats["constant_keys"]
+    m = stats["sample_size"]
+    route_bytes_learned = (n * 8 * (1 + 2 * passes) + (n - fb) * 16 + fb * 8 + (fb - const) * 8 * 16
+                           + m * 8 * (2 + 1 + 2 * 8))
     plain_alg = n * 8 * (1 + 2 * 8)
     work.copy_(keys)
     ak.sort_(work, dtype="u64")
@@ -360,6 +368,8 @@ def main():
         "learned_other_models": others,
         "learned_vs_plain": round(plain_step / ms_step, 3),
         "learned_hbm_frac_alg": round(alg_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "learned_route_bytes": int(route_bytes_learned),
+        "learned_hbm_frac_route": round(route_bytes_learned / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "learned_stats": stats,
         "roofline": rl,
         "kernels_ms": {k: [c, round(ms, 3)] for k, (c, ms) in prof.items()},
