@@ -8,6 +8,51 @@
 namespace ak {
 
 // ------------------------------------------------ single-workgroup sort
+// Stable LSD passes over the image bits [lo, hi] (8-bit digits from lo
+// up) of a tile held in registers (wave-striped); afterwards the keys are in
+// sm.keys[0..len) in their new order and k[j] holds element
+// striped_elem(w, j, lane) of it.
+template <int DT, bool VAL, int W, int IPT>
+__device__ __forceinline__ void lsd_range(typename KT<DT>::U (&k)[IPT], uint32_t (&v)[IPT], uint32_t len,
+                                          SmallSmem<typename KT<DT>::U, VAL, W, IPT> &sm, int tid, int lo, int hi) {
+    constexpr int B = W * 64;
+    uint32_t rd[IPT];  // digit, then rank | digit << 16
+    for (int shift = lo; shift <= hi; shift += RADIX_BITS) {
+        // per-thread indices re-derived every pass from an opaque copy of
+        // the thread id: hoisted out of the loop they would hold one
+        // register per key
+        int tq = tid;
+        asm volatile("" : "+v"(tq));
+        const int lane = tq & 63, w = tq >> 6;
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const uint32_t e = striped_elem<IPT>(w, j, lane);
+            rd[j] = e < len ? (uint32_t)(KT<DT>::image(k[j]) >> shift) & (RADIX - 1) : 0u;
+        }
+        rank_match_packed<RADIX_BITS, W, IPT>(rd, len, sm.cnt, sm.tot, tid);
+        block_exscan<B, RADIX>(sm.tot, sm.start, sm.wsum, tid);
+        rank_finish_packed<RADIX_BITS, W, IPT>(rd, sm.cnt, sm.start, tid);
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const uint32_t e = striped_elem<IPT>(w, j, lane);
+            if (e < len) {
+                sm.keys[rd[j] & 0xFFFFu] = k[j];
+                if (VAL) sm.vals[rd[j] & 0xFFFFu] = v[j];
+            }
+        }
+        grp_sync<W>();
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const uint32_t e = striped_elem<IPT>(w, j, lane);
+            if (e < len) {
+                k[j] = sm.keys[e];
+                if (VAL) v[j] = sm.vals[e];
+            }
+        }
+        grp_sync<W>();
+    }
+}
+
 // Sorts up to W*64*IPT keys on chip with a group of W waves (tid = thread
 // index within the group): load once, skip the bits that do not vary
 // (OR/AND reduction of the images), one stable ranking per 8-bit digit
@@ -21,10 +66,7 @@ namespace ak {
 template <int DT, bool VAL, int W, int IPT>
 __device__ __forceinline__ void lds_sort_core(typename KT<DT>::U (&k)[IPT], uint32_t (&v)[IPT], uint32_t len,
                                               SmallSmem<typename KT<DT>::U, VAL, W, IPT> &sm, int tid) {
-    using U = typename KT<DT>::U;
-    constexpr int B = W * 64;
     const int lane = tid & 63, w = tid >> 6;
-    uint32_t rd[IPT];  // digit, then rank | digit << 16
     // the bits that vary over the tile: OR and AND of the images, in two
     // 64-bit halves (the high half is zero below 128-bit keys)
     uint64_t olo = 0, alo = ~0ull, ohi = 0, ahi = ~0ull;
@@ -51,40 +93,7 @@ __device__ __forceinline__ void lds_sort_core(typename KT<DT>::U (&k)[IPT], uint
     if (dlo != 0 || dhi != 0) {
         const int lo = dlo ? __builtin_ctzll(dlo) : 64 + __builtin_ctzll(dhi);
         const int hi = dhi ? 127 - __builtin_clzll(dhi) : 63 - __builtin_clzll(dlo);
-        for (int shift = lo; shift <= hi; shift += RADIX_BITS) {
-            // per-thread indices re-derived every pass from an opaque copy
-            // of the thread id: hoisted out of the loop they would hold one
-            // register per key
-            int tq = tid;
-            asm volatile("" : "+v"(tq));
-            const int lane = tq & 63, w = tq >> 6;
-#pragma unroll
-            for (int j = 0; j < IPT; ++j) {
-                const uint32_t e = striped_elem<IPT>(w, j, lane);
-                rd[j] = e < len ? (uint32_t)(KT<DT>::image(k[j]) >> shift) & (RADIX - 1) : 0u;
-            }
-            rank_match_packed<RADIX_BITS, W, IPT>(rd, len, sm.cnt, sm.tot, tid);
-            block_exscan<B, RADIX>(sm.tot, sm.start, sm.wsum, tid);
-            rank_finish_packed<RADIX_BITS, W, IPT>(rd, sm.cnt, sm.start, tid);
-#pragma unroll
-            for (int j = 0; j < IPT; ++j) {
-                const uint32_t e = striped_elem<IPT>(w, j, lane);
-                if (e < len) {
-                    sm.keys[rd[j] & 0xFFFFu] = k[j];
-                    if (VAL) sm.vals[rd[j] & 0xFFFFu] = v[j];
-                }
-            }
-            grp_sync<W>();
-#pragma unroll
-            for (int j = 0; j < IPT; ++j) {
-                const uint32_t e = striped_elem<IPT>(w, j, lane);
-                if (e < len) {
-                    k[j] = sm.keys[e];
-                    if (VAL) v[j] = sm.vals[e];
-                }
-            }
-            grp_sync<W>();
-        }
+        lsd_range<DT, VAL, W, IPT>(k, v, len, sm, tid, lo, hi);
     }
 }
 
@@ -103,6 +112,126 @@ __device__ __forceinline__ void lds_sort_regs(typename KT<DT>::U (&k)[IPT], type
             else vout[e] = v[j];
         }
     }
+}
+
+// True in every thread of the group if `pred` holds in any of its threads
+// (a group of one wave: a ballot; otherwise a block barrier).
+template <int W>
+__device__ __forceinline__ bool grp_any(bool pred) {
+    if constexpr (W == 1) return ballot64(pred) != 0;
+    else return __syncthreads_or(pred) != 0;
+}
+
+// Keys-only stable on-chip sort of a tile held in registers, same result as
+// lds_sort_regs, with fewer ranking passes when the keys spread over many
+// more bits than the tile needs to tell them apart.  If more than T + 8
+// bits vary (T = 8 for tiles of at most 256 keys, else 16), stable LSD
+// passes order the tile by its top T varying bits only; the keys sharing
+// such a prefix then form small contiguous groups (about len / 2^T keys),
+// in input order.  A key's final place is its place e in that order, less
+// the keys before it in its group with a larger image, plus the keys after
+// it with a smaller one (equal images keep their order, so the result is
+// stable); each key walks its group in LDS and is stored there in `out`
+// (every key is read before any is written, so `out` may be the input).
+// A group longer than GMAX keys (many repeated keys) sends the tile to the
+// LSD passes over all its varying bits instead.
+template <int DT, int W, int IPT, int GMAX = 16>
+__device__ __forceinline__ void lds_sort_top(typename KT<DT>::U (&k)[IPT], typename KT<DT>::U *out, uint32_t len,
+                                             SmallSmem<typename KT<DT>::U, false, W, IPT> &sm, int tid) {
+    using U = typename KT<DT>::U;
+    if constexpr (key_bits(DT) > 64) {
+        lds_sort_regs<DT, false, W, IPT>(k, out, nullptr, len, sm, tid);
+    } else {
+        using I = decltype(KT<DT>::image(k[0]));
+        const int lane = tid & 63, w = tid >> 6;
+        uint32_t v[IPT];  // no payload
+        uint64_t vor = 0, vand = ~0ull;
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const uint32_t e = striped_elem<IPT>(w, j, lane);
+            if (e < len) {
+                const uint64_t t = (uint64_t)KT<DT>::image(k[j]);
+                vor |= t;
+                vand &= t;
+            }
+        }
+        uint64_t ror, rand_;
+        block_or_and<W>(vor, vand, sm.red, ror, rand_, tid);
+        const uint64_t diff = ror ^ rand_;
+        if (diff != 0) {
+            const int lo = __builtin_ctzll(diff), hi = 63 - __builtin_clzll(diff);
+            const int T = len <= 256u ? RADIX_BITS : 2 * RADIX_BITS;
+            const bool top = hi - lo + 1 > T + RADIX_BITS;
+            const int s0 = hi - T + 1;
+            // one call site of the passes (a second copy would raise the
+            // register count): the top bits first, and all varying bits if
+            // a group is too long
+            int first = top ? s0 : lo;
+#pragma nounroll
+            for (int round = 0; round < 2; ++round) {
+                lsd_range<DT, false, W, IPT>(k, v, len, sm, tid, first, hi);
+                if (first == lo) break;
+                // (loops over a lane's items not unrolled: unrolled, their
+                // loads would all be held in registers at once)
+                bool big = false;
+#pragma nounroll
+                for (int j = 0; j < IPT; ++j) {
+                    const uint32_t e = striped_elem<IPT>(w, j, lane);
+                    if (e + GMAX < len)
+                        big |= (KT<DT>::image(sm.keys[e]) >> s0) == (KT<DT>::image(sm.keys[e + GMAX]) >> s0);
+                }
+                if (!grp_any<W>(big)) {
+#pragma nounroll
+                    for (int j = 0; j < IPT; ++j) {
+                        const uint32_t e = striped_elem<IPT>(w, j, lane);
+                        if (e < len) {
+                            // the key again from LDS (k[] stays dead here)
+                            const U key = sm.keys[e];
+                            const I ti = KT<DT>::image(key);
+                            const I px = ti >> s0;
+                            uint32_t gl = 0, sr = 0;
+                            for (uint32_t q = e; q-- > 0;) {
+                                const I tq = KT<DT>::image(sm.keys[q]);
+                                if ((tq >> s0) != px) break;
+                                gl += tq > ti ? 1u : 0u;
+                            }
+                            for (uint32_t q = e + 1; q < len; ++q) {
+                                const I tq = KT<DT>::image(sm.keys[q]);
+                                if ((tq >> s0) != px) break;
+                                sr += tq < ti ? 1u : 0u;
+                            }
+                            out[e - gl + sr] = key;
+                        }
+                    }
+                    return;
+                }
+                // long groups: LSD passes over every varying bit, from the
+                // present order (equal keys are still in input order)
+                first = lo;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const uint32_t e = striped_elem<IPT>(w, j, lane);
+            if (e < len) out[e] = k[j];
+        }
+    }
+}
+
+// Loads up to W*64*IPT keys from `in` and sorts them on chip with
+// lds_sort_top (`in` may equal `out`).
+template <int DT, int W, int IPT>
+__device__ __forceinline__ void lds_sort_tile_top(const typename KT<DT>::U *in, typename KT<DT>::U *out, uint32_t len,
+                                                  SmallSmem<typename KT<DT>::U, false, W, IPT> &sm, int tid) {
+    using U = typename KT<DT>::U;
+    const int lane = tid & 63, w = tid >> 6;
+    U k[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const uint32_t e = striped_elem<IPT>(w, j, lane);
+        k[j] = e < len ? in[e] : U(0);
+    }
+    lds_sort_top<DT, W, IPT>(k, out, len, sm, tid);
 }
 
 // Sort by key of up to W*64*IPT keys on chip, in place: the keys sorted,

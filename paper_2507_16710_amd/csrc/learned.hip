@@ -444,7 +444,7 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(WPE))) v
     using U = typename KT<DT>::U;
     using CD = typename std::conditional<PREFIX, PrefixCoder<DT>, RmiCoder<DT>>::type;
     constexpr int B = W * 64, CAP = B * IPT;
-    __shared__ ChunkSmem<U, W, IPT, PREFIX ? (1 << MB) : 1> sm;
+    __shared__ ChunkSmem<U, W, IPT, (PREFIX && MB > 0) ? (1 << MB) : 1> sm;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     CD cd;
     if constexpr (PREFIX) {
@@ -534,11 +534,13 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(WPE))) v
             cut = pos + q;
             __syncthreads();
         }
-        // prefix runs (keys spread over many bits): one top-digit pass and
-        // comparisons; model-code chunks (measured: no gain, many repeated
-        // keys): LSD passes
-        if constexpr (PREFIX) lds_sort_chunk<DT, W, IPT, MB>(k, keys + pos, cut - pos, sm.sort, sm.mtot, sm.mstart, tid);
-        else lds_sort_regs<DT, false, W, IPT>(k, keys + pos, nullptr, cut - pos, sm.sort, tid);
+        // the group finish (passes over the top 16 varying bits, then
+        // comparisons inside the short groups of equal top bits they leave;
+        // LSD passes over every varying bit for chunks of few varying bits
+        // or long groups), or for prefix chunks optionally one pass on the
+        // top MB varying bits and comparisons inside its buckets
+        if constexpr (PREFIX && MB > 0) lds_sort_chunk<DT, W, IPT, MB>(k, keys + pos, cut - pos, sm.sort, sm.mtot, sm.mstart, tid);
+        else lds_sort_top<DT, W, IPT>(k, keys + pos, cut - pos, sm.sort, tid);
         ++nchunks;
         pos = cut;
         __syncthreads();
@@ -820,21 +822,26 @@ static void launch_chunk_sort(hipStream_t s, uint32_t npieces, typename KT<DT>::
 // stops after the passes over those places; these launches finish it (they
 // exit at once when the run took all its passes).
 // Chunk shapes of the prefix finish (2048 keys each: waves, keys per lane,
-// register budget, bits of the top digit; $AK_PFX_CHUNK_VARIANT picks one).
+// register budget, and how a chunk is finished: 0 = the group finish of
+// lds_sort_top, else the bits of the one top-digit pass of lds_sort_chunk;
+// $AK_PFX_CHUNK_VARIANT picks one).  2^30 uniform int64 keys: 27.6 ms with
+// the first, 30.1 ms with the second, 30.5-30.7 ms with the one-pass
+// finishes.
 struct PfxShape {
     int w, ipt, wpe, mb;
 };
-constexpr PfxShape PFX_SHAPES[3] = {{8, 4, 8, 9}, {4, 8, 6, 9}, {4, 8, 6, 8}};
+constexpr PfxShape PFX_SHAPES[5] = {{4, 8, 6, 0}, {8, 4, 8, 0}, {8, 4, 8, 9}, {4, 8, 6, 9}, {4, 8, 6, 8}};
 constexpr int PFX_CAP = 2048;
 static_assert(PFX_SHAPES[0].w * 64 * PFX_SHAPES[0].ipt == PFX_CAP && PFX_SHAPES[1].w * 64 * PFX_SHAPES[1].ipt == PFX_CAP &&
-                  PFX_SHAPES[2].w * 64 * PFX_SHAPES[2].ipt == PFX_CAP,
+                  PFX_SHAPES[2].w * 64 * PFX_SHAPES[2].ipt == PFX_CAP && PFX_SHAPES[3].w * 64 * PFX_SHAPES[3].ipt == PFX_CAP &&
+                  PFX_SHAPES[4].w * 64 * PFX_SHAPES[4].ipt == PFX_CAP,
               "prefix chunk shapes hold PFX_CAP keys");
 
 static int pfx_variant() {
     static const int v = [] {
         const char *e = getenv("AK_PFX_CHUNK_VARIANT");
         const int x = (e && *e) ? atoi(e) : 0;
-        return x >= 0 && x < 3 ? x : 0;
+        return x >= 0 && x < 5 ? x : 0;
     }();
     return v;
 }
@@ -911,7 +918,9 @@ static ak_status prefix_finish_t(Workspace *ws, hipStream_t s, void *keys, int64
         switch (pfx_variant()) {
         case 0: launch(std::integral_constant<int, 0>{}); break;
         case 1: launch(std::integral_constant<int, 1>{}); break;
-        default: launch(std::integral_constant<int, 2>{}); break;
+        case 2: launch(std::integral_constant<int, 2>{}); break;
+        case 3: launch(std::integral_constant<int, 3>{}); break;
+        default: launch(std::integral_constant<int, 4>{}); break;
         }
     }
     AK_LAUNCH_CHECK("k_chunk_sort");

@@ -298,8 +298,8 @@ __global__ __launch_bounds__(BIG_W * 64) void k_seg_big(const SegArgs *ap, SegSt
         const int64_t s = a.list[item];
         const int64_t lo = a.off[s];
         const uint32_t len = (uint32_t)(a.hi[s] - lo);
-        if (len <= (uint32_t)BIG_SPLIT) lds_sort_tile<DT, false, BIG_W, 16>(keys + lo, keys + lo, nullptr, len, sm.lo, threadIdx.x);
-        else lds_sort_tile<DT, false, BIG_W, big_ipt<U>()>(keys + lo, keys + lo, nullptr, len, sm.hi, threadIdx.x);
+        if (len <= (uint32_t)BIG_SPLIT) lds_sort_tile_top<DT, BIG_W, 16>(keys + lo, keys + lo, len, sm.lo, threadIdx.x);
+        else lds_sort_tile_top<DT, BIG_W, big_ipt<U>()>(keys + lo, keys + lo, len, sm.hi, threadIdx.x);
         __syncthreads();
     }
 }
@@ -310,8 +310,11 @@ union SegSmem {
     SmallSmem<U, false, 1, IPT_A> shrt[SEG_W];
 };
 
+// Register budget: three workgroups per CU for the medium tiles up to 16
+// keys per lane (the group finish would otherwise take the kernel just past
+// the 168 registers that allow it).
 template <int DT, int IPT_A, int IPT_B>
-__global__ __launch_bounds__(SEG_W * 64) void k_seg_sort(const SegArgs *ap, SegState *st) {
+__global__ __launch_bounds__(SEG_W * 64) __attribute__((amdgpu_waves_per_eu(IPT_B <= 16 ? 3 : 1))) void k_seg_sort(const SegArgs *ap, SegState *st) {
     using U = typename KT<DT>::U;
     __shared__ SegSmem<U, IPT_A, IPT_B> sm;
     __shared__ uint32_t s_item;
@@ -329,13 +332,13 @@ __global__ __launch_bounds__(SEG_W * 64) void k_seg_sort(const SegArgs *ap, SegS
         if (item < short0) {
             const int64_t s = a.list[item];
             const int64_t lo = a.off[s], len = a.hi[s] - lo;
-            lds_sort_tile<DT, false, SEG_W, IPT_B>(keys + lo, keys + lo, nullptr, (uint32_t)len, sm.med, tid);
+            lds_sort_tile_top<DT, SEG_W, IPT_B>(keys + lo, keys + lo, (uint32_t)len, sm.med, tid);
         } else {
             const uint32_t g = (item - short0) * SEG_W + w;
             if (g < nshort) {
                 const int64_t s = a.list[short0 + g];
                 const int64_t lo = a.off[s], len = a.hi[s] - lo;
-                lds_sort_tile<DT, false, 1, IPT_A>(keys + lo, keys + lo, nullptr, (uint32_t)len, sm.shrt[w], lane);
+                lds_sort_tile_top<DT, 1, IPT_A>(keys + lo, keys + lo, (uint32_t)len, sm.shrt[w], lane);
             }
         }
         __syncthreads();

@@ -111,3 +111,55 @@ def wide_keys(dt: str, n: int, rng: np.random.Generator, kind: str = "mixed") ->
 def wide_arg(dt: str):
     """The oracle's explicit dtype argument (128-bit keys only)."""
     return dt if dt in ("i128", "u128") else None
+
+
+def from_image(img: np.ndarray, dt: str) -> np.ndarray:
+    """Keys whose order-preserving image (the unsigned integer whose order is
+    the keys' total order) is `img`: the inverse of that map, written out
+    for tests that shape inputs in image bits (signed integers: the sign
+    bit flipped; floats: images with the top bit set are the non-negative
+    values with that bit cleared, the others are bit-complemented negative
+    values)."""
+    w = np.dtype(NP[dt]).itemsize * 8
+    ub = np.uint32 if w == 32 else np.uint64
+    img = np.asarray(img).astype(ub)
+    top = ub(1) << ub(w - 1)
+    if dt.startswith("u"):
+        b = img
+    elif dt.startswith("i"):
+        b = img ^ top
+    else:
+        b = np.where((img & top) != 0, img ^ top, ~img).astype(ub)
+    return b.view(NP[dt])
+
+
+def prefix_groups(n: int, w: int, t: int, gmax: int, rng: np.random.Generator,
+                  long_group: int = 0) -> np.ndarray:
+    """n w-bit images whose top t bits form groups of equal prefix of at
+    most `gmax` images each (plus one group of `long_group` images when it
+    is nonzero); prefixes 0 and 2^t - 1 both occur, so the top bit varies,
+    and every group holds some equal images.  Shuffled."""
+    ub = np.uint32 if w == 32 else np.uint64
+    sizes = []
+    left = n
+    if long_group:
+        sizes.append(min(long_group, n))
+        left -= sizes[-1]
+    while left > 0:
+        sizes.append(min(gmax, left))
+        left -= sizes[-1]
+    g = len(sizes)
+    assert g <= (1 << t)
+    inner = rng.choice(np.arange(1, (1 << t) - 1, dtype=np.uint64), size=max(g - 2, 0), replace=False)
+    pref = np.concatenate([np.array([0, (1 << t) - 1], dtype=np.uint64)[:g], inner])
+    lowbits = w - t
+    out = []
+    for p, s in zip(pref, sizes):
+        low = rng.integers(0, 1 << lowbits, size=s, dtype=np.uint64)
+        if s >= 3:
+            low[1] = low[0]            # equal images inside the group
+        low[0] |= np.uint64(1)        # the lowest bit varies
+        out.append((np.uint64(p) << np.uint64(lowbits)) | low)
+    a = np.concatenate(out).astype(ub)
+    rng.shuffle(a)
+    return a

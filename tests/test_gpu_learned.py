@@ -132,6 +132,23 @@ def test_learned_sort_all_dtypes_and_edges(dt):
             assert np.array_equal(bits(to_host(t, dt)), bits(oracle.sort(k))), (dt, n, kind)
 
 
+def test_learned_chunks_with_repeated_spread_keys():
+    """Chunks whose keys spread over all 64 bits and repeat: values drawn
+    once to 99 times each.  A chunk whose groups of equal top bits stay
+    short is finished by comparisons inside the groups; one holding a long
+    run of equal keys takes the passes over every varying bit."""
+    rng = np.random.default_rng(21)
+    for dt, hi in (("u64", 1 << 64), ("i64", 1 << 63)):
+        vals = rng.integers(0, hi, size=20_000, dtype=np.uint64)
+        k = np.repeat(vals, rng.integers(1, 100, size=vals.size))
+        rng.shuffle(k)
+        k = k.view(np.int64) if dt == "i64" else k
+        t = to_gpu(k, dt)
+        ak.sort_learned_(t, dtype=dt)
+        torch.cuda.synchronize()
+        assert np.array_equal(bits(to_host(t, dt)), bits(oracle.sort(k))), dt
+
+
 def test_learned_degenerate_and_configs():
     rng = np.random.default_rng(5)
     n = 300_000

@@ -9,7 +9,7 @@ import oracle
 import paper_2507_16710_amd as ak
 import synth
 from gpucheck import fingerprint, segment_fingerprints, signed_order_key, to_gpu, to_host
-from pools import DTYPES, bits, random_keys
+from pools import DTYPES, bits, from_image, prefix_groups, random_keys
 
 pytestmark = pytest.mark.gpu
 
@@ -157,3 +157,60 @@ def test_huge_segments_under_tunings(dt):
             assert np.array_equal(bits(_seg(k, off, dt)), bits(oracle.segsort(k, off))), xl
     finally:
         ak.seg_set_tuning(kb, 4, 16, 4, 0, 32768)
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+def test_on_chip_prefix_groups(dt):
+    """On-chip classes (short, medium, big): segments whose keys spread
+    over every bit, shaped in image bits so that after ordering by the top
+    8 (segments of up to 256 keys) or 16 varying bits the groups of equal
+    prefix hold at most 16 keys (each key placed by comparisons inside its
+    group), or one group holds 17 (the segment then takes the passes over
+    every varying bit), with equal keys inside groups."""
+    rng = np.random.default_rng(zlib.crc32(b"groups" + dt.encode()))
+    w = 32 if dt in ("i32", "u32", "f32") else 64
+    lens, parts = [], []
+    for L in [40, 200, 256, 257, 1000, 2048, 2049, 4096, 4097, 8192, 12_000, 16_384]:
+        t = 8 if L <= 256 else 16
+        for long_group in (0, 17, 16 * 3):
+            lens.append(L)
+            parts.append(from_image(prefix_groups(L, w, t, 16, rng, long_group), dt))
+        lens.append(L)
+        parts.append(random_keys(dt, L, rng, "uniform"))
+    k = np.concatenate(parts)
+    off = _offsets(lens)
+    assert np.array_equal(bits(_seg(k, off, dt)), bits(oracle.segsort(k, off)))
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+def test_huge_segments_shaped_keys(dt):
+    """Huge segments (above 16384 keys) shaped in image bits: uniform keys,
+    one top-byte bucket of exactly 8192 keys and one of 8193, keys below
+    2^20 (the top byte constant: its place is skipped), a segment one key
+    above the class limit, and keys repeated 60 times."""
+    rng = np.random.default_rng(zlib.crc32(b"hugeshaped" + dt.encode()))
+    w = 32 if dt in ("i32", "u32", "f32") else 64
+    ub = np.uint32 if w == 32 else np.uint64
+    top = np.uint64(w - 8)
+
+    def img_uniform(n, bits_=w):
+        v = rng.integers(0, 1 << min(bits_, 63), size=n, dtype=np.uint64)
+        if bits_ == 64:
+            v ^= rng.integers(0, 2, size=n, dtype=np.uint64) << np.uint64(63)
+        return v.astype(ub)
+
+    def img_bucket(n, big):
+        v = img_uniform(n)
+        v[:big] = (v[:big] & ub((1 << (w - 8)) - 1)) | (ub(0x80) << ub(top))
+        rest = v[big:]
+        hit = (rest >> ub(top)) == ub(0x80)
+        rest[hit] ^= ub(1) << ub(top)       # no other key in that bucket
+        rng.shuffle(v)
+        return v
+
+    segs = [img_uniform(40_000), img_uniform(300_000), img_bucket(40_000, 8192), img_bucket(40_000, 8193),
+            img_uniform(70_000, 20), img_uniform(16_385), np.repeat(img_uniform(500), 60)]
+    lens = [int(x.size) for x in segs]
+    k = np.concatenate([from_image(x, dt) for x in segs])
+    off = _offsets(lens)
+    assert np.array_equal(bits(_seg(k, off, dt)), bits(oracle.segsort(k, off)))
