@@ -933,7 +933,7 @@ __global__ __launch_bounds__(W * 64) void k_small_sort(typename KT<DT>::U *keys,
     using U = typename KT<DT>::U;
     constexpr bool VAL = ModeT<MODE>::VAL;
     __shared__ SmallSmem<U, VAL, W, IPT> sm;
-    if constexpr (MODE == M_KEYS) lds_sort_tile<DT, false, W, IPT>(keys, keys, nullptr, n, sm, threadIdx.x);
+    if constexpr (MODE == M_KEYS) lds_sort_tile_top<DT, W, IPT>(keys, keys, n, sm, threadIdx.x);
     else if constexpr (ModeT<MODE>::PAIRS)
         lds_sort_pairs<DT, typename ModeT<MODE>::V, W, IPT>(keys, (typename ModeT<MODE>::V *)vals, n, sm, threadIdx.x);
     else lds_sort_tile<DT, true, W, IPT>(keys, nullptr, (uint32_t *)vals, n, sm, threadIdx.x);
