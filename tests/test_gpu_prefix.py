@@ -134,6 +134,20 @@ def test_repeated_keys_take_in_chunk_fallback():
     _check(f.astype(np.float64), "f64", "repeated-float")
 
 
+@pytest.mark.parametrize("reps", [16, 17])
+def test_repeats_at_the_group_limit(reps):
+    """Every value repeated 16 or 17 times: a chunk's groups of equal top
+    16 bits are the repeats (one group per value).  At 16 each key is
+    placed by comparisons inside its group; at 17 every chunk exceeds the
+    limit and takes the passes over all its varying bits."""
+    rng = np.random.default_rng(100 + reps)
+    vals = rng.integers(0, 1 << 64, size=N0 // reps + 1, dtype=np.uint64)
+    k = np.repeat(vals, reps)[:N0]
+    rng.shuffle(k)
+    route = _check(k, "u64", f"repeats{reps}")
+    assert route["prefix_places"] >= 2 and route["chunks"] > 0, route
+
+
 @pytest.mark.parametrize("dt", ["f32", "f64"])
 def test_prefix_route_with_nan_payloads_and_zeros(dt):
     """Raw random bits: NaNs with every payload and sign (all tie, so they
