@@ -612,6 +612,22 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(
         if (next < ntiles) load_tile(next, w, lane, kn, vn);
     }
 
+    // The keys are staged in LDS by their tile positions before the
+    // look-back (the positions do not depend on it): that work then lies
+    // between publishing this tile's counts and reading its predecessors'
+    // (2^31-key learned sort: code passes 46.2 -> 44.2 ms; 2^30 lognormal
+    // int64 keys 37.4 -> 36.1 ms).
+    __syncthreads();  // counters are dead from here on: their bytes hold keys
+#pragma unroll
+    for (int jj = 0; jj < IPT; ++jj) {
+        const uint32_t e = striped_elem<IPT>(w, jj, lane);
+        if (e < tvalid) {
+            const uint32_t r = rd[jj] & 0xFFFFu;
+            s_keys[r] = k[jj];
+            if (CODE) s_dig[r] = (uint8_t)(rd[jj] >> 16);
+            if (VAL) s_vals[r] = v[jj];
+        }
+    }
     // two-level decoupled look-back (K*LB_M words per round trip): inside
     // the tile's group, then over the words of the groups before it
     {
@@ -633,18 +649,6 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(
                 lb_store(lbg + (size_t)g * RADIX + d, lb_pack(epoch, LB_INC, gexcl + lexcl + s_tot[d]));
         }
         if (kk == 0) s_glob[d] = a.st->base[a.place][d] + gexcl + lexcl - s_start[d];
-    }
-    __syncthreads();  // counters are dead from here on: their bytes hold keys
-
-#pragma unroll
-    for (int jj = 0; jj < IPT; ++jj) {
-        const uint32_t e = striped_elem<IPT>(w, jj, lane);
-        if (e < tvalid) {
-            const uint32_t r = rd[jj] & 0xFFFFu;
-            s_keys[r] = k[jj];
-            if (CODE) s_dig[r] = (uint8_t)(rd[jj] >> 16);
-            if (VAL) s_vals[r] = v[jj];
-        }
     }
     __syncthreads();
 

@@ -683,6 +683,14 @@ __global__ __launch_bounds__(W * 64) void k_xl_pass(const SegArgs *ap, SegState 
             lb_store(lb + d, lb_pack(epoch, lt == 0 ? LB_INC : LB_AGG, s_tot[d]));
         block_exscan<B, RADIX>(s_tot, s_start, s_wsum, tid);
         rank_finish_packed<RADIX_BITS, W, IPT, uint16_t>(rd, s_cnt, s_start, tid);
+        // staged by tile position before the look-back, as in the one-sweep
+        // pass (the counters are dead after the barrier)
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const uint32_t e = striped_elem<IPT>(w, j, lane);
+            if (e < tvalid) s_keys[rd[j] & 0xFFFFu] = k[j];
+        }
         {
             constexpr int K = B / RADIX;
             const int d = tid / K, kk = tid % K;
@@ -692,12 +700,6 @@ __global__ __launch_bounds__(W * 64) void k_xl_pass(const SegArgs *ap, SegState 
                 if (kk == 0) lb_store(lb + d, lb_pack(epoch, LB_INC, excl + s_tot[d]));
             }
             if (kk == 0) s_glob[d] = a.xl_hist[((size_t)i * P + place) * RADIX + d] + excl - s_start[d];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-            const uint32_t e = striped_elem<IPT>(w, j, lane);
-            if (e < tvalid) s_keys[rd[j] & 0xFFFFu] = k[j];
         }
         __syncthreads();
 #pragma unroll
