@@ -49,7 +49,14 @@ struct OnesweepArgs {
 // One-sweep tile shapes (W waves x IPT keys per lane).  A few shapes are
 // compiled per (key width, with values); os_variant() picks one at run time
 // (default from the tuning sweep; $AK_OS_VARIANT overrides it).
-constexpr int LB_M = 4;  // look-back words read per thread per round trip
+// Look-back words read per thread per round trip after the first.  One:
+// most look-backs end within a round trip or two, and fewer words per round
+// trip cost less than the rounds they save (2^31-key learned sort: 63.0 ms
+// with 1, 63.8 with 2, 63.9-64.2 with 4, 66.6 with 8).
+#ifndef AK_LB_M
+#define AK_LB_M 1
+#endif
+constexpr int LB_M = AK_LB_M;
 // Tiles per look-back group.  A tile looks back only inside its group (the
 // group's first tile is inclusive by definition); every group's last tile
 // publishes the group's digit totals, and the prefix of the groups before a
