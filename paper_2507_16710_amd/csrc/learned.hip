@@ -779,6 +779,20 @@ static ak_status leaf_grad_t(Workspace *ws, const void *sorted, uint32_t m, cons
     return leaf_sums<DT>(s, srt, m, L, model_in, f, out);
 }
 
+// Pieces of the code-ordered array per CU for the chunk sorts (one
+// workgroup per piece, at least four chunks each; $AK_PIECES_PER_CU
+// overrides the default).  Smaller pieces even out the tail of the launch:
+// on 2^31 mixture keys the learned sort took 63.6-63.8 ms at 16 per CU,
+// 61.3-62.4 at 64, 61.1-61.5 at 128 and 61.4-61.7 at 256.
+static uint32_t pieces_per_cu() {
+    static const uint32_t v = [] {
+        const char *e = getenv("AK_PIECES_PER_CU");
+        const int x = (e && *e) ? atoi(e) : 128;
+        return (uint32_t)(x >= 1 && x <= 4096 ? x : 128);
+    }();
+    return v;
+}
+
 // On-chip chunk shapes (waves, keys per lane, register budget in waves per
 // SIMD); $AK_CHUNK_VARIANT picks one (default 2).  The smallest capacity
 // sizes the fallback bookkeeping: a fallback run is longer than a chunk.
@@ -904,7 +918,7 @@ static ak_status prefix_finish_t(Workspace *ws, hipStream_t s, void *keys, int64
     hipLaunchKernelGGL(k_learned_reset, dim3(1), dim3(256), 0, s, ls, (uint32_t *)nullptr, 0u);
     AK_LAUNCH_CHECK("k_learned_reset");
     // small runs: one chunk per workgroup, so every CU works at once
-    const uint32_t pieces_target = (uint32_t)num_cus() * 16;
+    const uint32_t pieces_target = (uint32_t)num_cus() * pieces_per_cu();
     const uint32_t piece =
         small ? PFX_CAP : std::max<uint32_t>(PFX_CAP * 4, (n + pieces_target - 1) / pieces_target);
     const uint32_t npieces = (n + piece - 1) / piece;
@@ -1016,7 +1030,7 @@ static ak_status learned_t(Workspace *ws, void *keys, int64_t n64, const ak_lear
     // 3. order by code
     if ((r = code_partition(ws, DT, keys, n, model, L, cb, 2)) != AK_OK) return r;
     // 4. chunks on chip
-    const uint32_t pieces_target = (uint32_t)num_cus() * 16;
+    const uint32_t pieces_target = (uint32_t)num_cus() * pieces_per_cu();
     uint32_t piece = std::max<uint32_t>((uint32_t)CAP * 4, (n + pieces_target - 1) / pieces_target);
     const uint32_t npieces = (n + piece - 1) / piece;
     // The keys of a chunk lie in a narrow code range, so its model reads hit
